@@ -1,0 +1,208 @@
+"""Seeded synthetic input tensors shaped like the paper's test problems.
+
+This module only draws random numbers and assembles tensors of a known
+structure; it holds none of the decomposition's arithmetic.  The oracle and the
+GPU path both consume its arrays, and neither is imported here.
+
+Constructions (all in float64 with ``numpy.random.default_rng(seed)``, rounded
+once to the storage dtype at the very end):
+
+* ``orth(X)``: the Q factor of a Householder QR of a Gaussian matrix, with the
+  signs fixed so that diag(R) > 0 -- "an orthonormal basis for the column space
+  of a standard Gaussian matrix" as in the Eq. (9) test tensor (Section 4.3).
+* Tucker-form signal plus noise, Eq. (9): A = B + gamma*||B||_F/sqrt(prod I_n)*E,
+  B = C x_1 U_1 ... x_N U_N, E iid N(0,1).  The paper's divisor sqrt(400^3) for
+  a 600^3 tensor is read as sqrt(prod I_n), so that ||noise||_F ~ gamma*||B||_F.
+* Superdiagonal core tendiag(v) (Section 6.3): every mode-n unfolding of the
+  signal then has the singular values v exactly.
+* Sum of separable Gaussian bumps (a smooth, image-like field).
+
+Draw order is fixed: core (or bump amplitudes), then factors 1..N (or bump
+centres and widths per mode), then noise.
+
+Arrays are returned in column-major (Fortran) order: the first index is the
+fastest, i.e. mode-1 fibers are contiguous, which is the layout the library and
+the paper's unfolding (Section 2) use.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional, Sequence
+
+import numpy as np
+
+__all__ = [
+    "orth", "tucker_signal", "tendiag", "add_noise", "Workload",
+    "low_rank_plus_noise", "gaussian_bumps", "config", "CONFIGS",
+    "serving_request",
+]
+
+
+def orth(X: np.ndarray) -> np.ndarray:
+    """Orthonormal basis of range(X) (Householder QR, diag(R) > 0)."""
+    Q, R = np.linalg.qr(X)
+    d = np.sign(np.diag(R))
+    d[d == 0] = 1.0
+    return Q * d
+
+
+def tucker_signal(core: np.ndarray, factors: Sequence[np.ndarray]) -> np.ndarray:
+    """B = core x_1 U_1 x_2 U_2 ... x_N U_N, returned Fortran-ordered float64."""
+    B = np.asarray(core, dtype=np.float64)
+    for n, U in enumerate(factors):
+        B = np.moveaxis(np.tensordot(U, B, axes=(1, n)), 0, n)
+    return np.asfortranarray(B)
+
+
+def tendiag(v: Sequence[float], order: int) -> np.ndarray:
+    """Superdiagonal tensor with v on its diagonal (entries (k,k,...,k))."""
+    r = len(v)
+    C = np.zeros((r,) * order)
+    for k in range(r):
+        C[(k,) * order] = v[k]
+    return C
+
+
+def add_noise(B: np.ndarray, gamma: float, rng: np.random.Generator) -> np.ndarray:
+    """A = B + gamma*||B||_F/sqrt(prod(I_n))*E with E iid N(0,1)."""
+    if gamma == 0.0:
+        return B
+    scale = gamma * float(np.linalg.norm(B.ravel(order="K"))) / math.sqrt(B.size)
+    E = rng.standard_normal(B.shape[::-1]).T  # Fortran-ordered draw, same stream
+    B = B + scale * E
+    return np.asfortranarray(B)
+
+
+@dataclasses.dataclass
+class Workload:
+    """A generated tensor plus the decomposition parameters it is run with."""
+    name: str
+    A: np.ndarray                 # Fortran-ordered, storage dtype
+    ranks: tuple
+    oversample: int
+    power: int
+    algo: str                     # "thosvd" | "sthosvd"
+    prob: str                     # "none" | "nearly_optimal" | "uniform"
+    samples: Optional[tuple]      # T_n per mode (None if prob == "none")
+    seed: int
+    precision: str = "native"
+    note: str = ""
+
+    @property
+    def dims(self) -> tuple:
+        return tuple(self.A.shape)
+
+
+def low_rank_plus_noise(dims, core_dims, gamma, seed, dtype=np.float64,
+                        core="gauss", decay=None) -> np.ndarray:
+    """Tucker-form signal plus relative Gaussian noise (Eq. (9) style).
+
+    core="gauss": iid N(0,1) core; core="uniform": iid U(0,1) core (Eq. (9));
+    core="tendiag": superdiagonal core with diagonal ``decay`` (Section 6.3).
+    """
+    rng = np.random.default_rng(seed)
+    N = len(dims)
+    if core == "gauss":
+        C = rng.standard_normal(tuple(core_dims)[::-1]).T
+    elif core == "uniform":
+        C = rng.random(tuple(core_dims)[::-1]).T
+    elif core == "tendiag":
+        assert decay is not None and all(c == len(decay) for c in core_dims)
+        C = tendiag(decay, N)
+    else:
+        raise ValueError(core)
+    U = [orth(rng.standard_normal((dims[n], core_dims[n]))) for n in range(N)]
+    if core == "tendiag":
+        # Sum of r rank-one terms; built mode by mode to keep memory modest.
+        B = _cp_sum(np.asarray(decay, dtype=np.float64), U)
+    else:
+        B = tucker_signal(C, U)
+    A = add_noise(B, gamma, rng)
+    return np.asfortranarray(A.astype(dtype))
+
+
+def _cp_sum(weights: np.ndarray, factors: Sequence[np.ndarray]) -> np.ndarray:
+    """sum_b w_b * f1_b o f2_b o ... o fN_b, Fortran-ordered float64."""
+    N = len(factors)
+    # Build the Fortran-ordered result as a C-ordered array of reversed shape.
+    rev = factors[::-1]
+    letters = "abcdefgh"[:N]
+    spec = ",".join(f"{letters[i]}z" for i in range(N)) + ",z->" + letters
+    out = np.ascontiguousarray(np.einsum(spec, *rev, weights, optimize=True))
+    return out.T  # shape (I_1..I_N), Fortran-contiguous view
+
+
+def gaussian_bumps(dims, n_bumps, seed, dtype=np.float32, width=(4.0, 32.0),
+                   nonneg=False) -> np.ndarray:
+    """Sum of separable Gaussian bumps: A(i) = sum_b a_b prod_n exp(-(i_n-c)^2/(2w^2)).
+
+    a_b ~ N(0,1) (|a_b| if nonneg), centres c_{b,n} ~ U[0, I_n), widths
+    w_{b,n} ~ U[width]. One width per bump per mode.
+    """
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal(n_bumps)
+    if nonneg:
+        a = np.abs(a)
+    F = []
+    for I in dims:
+        c = rng.random(n_bumps) * I
+        w = width[0] + (width[1] - width[0]) * rng.random(n_bumps)
+        i = np.arange(I, dtype=np.float64)[:, None]
+        F.append(np.exp(-((i - c[None, :]) ** 2) / (2.0 * w[None, :] ** 2)))
+    return np.asfortranarray(_cp_sum(a, F).astype(dtype))
+
+
+def config(k: int, seed: int = 0) -> Workload:
+    """The five benchmark configurations (1-based ``k``), synthesised.
+
+    1: 64^3 float64, Gaussian core 5^3, noise 1e-3, Alg. 1 (T-HOSVD), exact.
+    2: 400^3 float32, tendiag core 0.5^k (k<10), noise 1e-4, Alg. 5
+       (ST-HOSVD + AMM), nearly-optimal probabilities, T_n = 4000.
+    3: 100^4 float32, tendiag core (k+1)^-2 (k<20), noise 1e-3, q = 2.
+    4: 512x512x256 float32, 50 Gaussian bumps, Alg. 4, uniform, T_n = 8000.
+    """
+    if k == 1:
+        A = low_rank_plus_noise((64, 64, 64), (5, 5, 5), 1e-3, seed, np.float64)
+        return Workload("c1_64cube_f64_thosvd", A, (5, 5, 5), 5, 1, "thosvd",
+                        "none", None, seed)
+    if k == 2:
+        v = [0.5 ** i for i in range(10)]
+        A = low_rank_plus_noise((400, 400, 400), (10, 10, 10), 1e-4, seed,
+                                np.float32, core="tendiag", decay=v)
+        return Workload("c2_400cube_f32_sthosvd_amm", A, (10, 10, 10), 10, 1,
+                        "sthosvd", "nearly_optimal", (4000, 4000, 4000), seed)
+    if k == 3:
+        v = [(i + 1.0) ** -2 for i in range(20)]
+        A = low_rank_plus_noise((100, 100, 100, 100), (20,) * 4, 1e-3, seed,
+                                np.float32, core="tendiag", decay=v)
+        return Workload("c3_100pow4_f32", A, (20,) * 4, 10, 2, "thosvd", "none",
+                        None, seed)
+    if k == 4:
+        A = gaussian_bumps((512, 512, 256), 50, seed, np.float32)
+        return Workload("c4_512x512x256_bumps_f32", A, (30, 30, 15), 10, 1,
+                        "thosvd", "uniform", (8000, 8000, 8000), seed)
+    raise ValueError(f"no config {k}")
+
+
+CONFIGS = (1, 2, 3, 4)
+
+
+def serving_request(req_id: int, base_seed: int = 1000, dtype=np.float32):
+    """One request of the serving stream: modes U{32..384}, ranks U{4..24}.
+
+    Ranks are redrawn until mu_n <= I_n and mu_n <= prod_{m != n} mu_m (a
+    feasible multilinear rank).  Gaussian core, orthonormal factors, noise 1e-3.
+    Returns (A, ranks, samples) with samples T_n = 4*mu_n.
+    """
+    rng = np.random.default_rng(base_seed + req_id)
+    dims = tuple(int(x) for x in rng.integers(32, 385, size=3))
+    while True:
+        ranks = tuple(int(x) for x in rng.integers(4, 25, size=3))
+        ok = all(ranks[n] <= dims[n] and
+                 ranks[n] <= int(np.prod([ranks[m] for m in range(3) if m != n]))
+                 for n in range(3))
+        if ok:
+            break
+    A = low_rank_plus_noise(dims, ranks, 1e-3, base_seed + req_id, dtype)
+    return A, ranks, tuple(4 * r for r in ranks)
