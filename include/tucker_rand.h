@@ -1,0 +1,266 @@
+/*
+ * tucker_rand.h -- C ABI of the MI355X (gfx950) randomized Tucker library.
+ *
+ * The library computes low multilinear rank approximations in Tucker format
+ * (Problem 1 of Che, Wei, Yan, "Efficient algorithms for Tucker decomposition
+ * via approximate matrix multiplication"): N orthonormal factors Q_n (I_n x mu_n)
+ * and a core G (mu_1 x ... x mu_N) with A ~ G x_1 Q_1 ... x_N Q_N.
+ *
+ *   tucker_rand_thosvd   randomized T-HOSVD: Alg. 1 (exact power products) or
+ *                        Alg. 4 (column-sampled approximate products).
+ *   tucker_rand_sthosvd  randomized ST-HOSVD: Alg. 2 (exact) or Alg. 5 (sampled).
+ *
+ * Each step of the per-mode range finder is also exported on its own so that
+ * it can be checked in isolation (Gaussian test matrix, column norms, sampler,
+ * gather, power products, factor extraction, mode-n product).
+ *
+ * Conventions for every entry point:
+ *  - Tensors are dense and column-major: index i_1 is fastest, so mode-1 fibers
+ *    are contiguous (the unfolding order of Section 2).  A tensor's mode n is
+ *    addressed through its 3-D view L x I x R with L = I_1...I_{n-1},
+ *    I = I_n, R = I_{n+1}...I_N; element (l, i, r) sits at l + L*(i + I*r) and
+ *    column j of the mode-n unfolding A_(n) is j = l + L*r (0-based).
+ *  - Matrices are column-major with leading dimension equal to their row count.
+ *  - "device" pointers are HIP device memory owned by the caller; the library
+ *    never allocates or frees device memory and keeps no global state.  "host"
+ *    pointers are read during the call only.
+ *  - Calls are asynchronous on `stream` (a hipStream_t; NULL = default stream).
+ *    Argument errors are detected on the host before anything is launched and
+ *    returned synchronously; nothing is written in that case.  Numeric trouble
+ *    found on the device (non-finite data, an all-zero sampling distribution)
+ *    is reported through the optional device status word (TR_DEV_* bits).
+ *  - Calls that share a workspace must not overlap in time.
+ */
+#ifndef TUCKER_RAND_H
+#define TUCKER_RAND_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TR_MAX_ORDER 8
+
+/* Return codes. */
+typedef enum {
+  TR_OK = 0,
+  TR_EINVAL = 1,   /* invalid argument (shape, rank, null pointer, ...)      */
+  TR_ENOMEM = 2,   /* workspace smaller than tucker_rand_workspace_size()    */
+  TR_EDEVICE = 3,  /* a HIP launch or runtime call failed                    */
+  TR_ENOTSUP = 4,  /* valid request outside what this build implements      */
+  TR_ENUMERIC = 5  /* reserved for numeric failures detected on the host    */
+} tr_status;
+
+/* Storage type of the input tensor, the factors and the core. */
+typedef enum { TR_F64 = 0, TR_F32 = 1 } tr_dtype;
+
+/* Probabilities of the sampled product (Remark after Alg. 3). */
+typedef enum {
+  TR_PROB_NONE = 0,            /* exact products: Alg. 1 / Alg. 2             */
+  TR_PROB_NEARLY_OPTIMAL = 1,  /* p_j ~ ||A_(n)(:,j)||^2: Alg. 4 / Alg. 5      */
+  TR_PROB_UNIFORM = 2          /* p_j = 1/J_n:             Alg. 4 / Alg. 5      */
+} tr_prob;
+
+/* Arithmetic of the large contractions.  TR_PREC_NATIVE accumulates every
+ * product, norm and factor in float64 (float32 inputs are widened exactly). */
+typedef enum { TR_PREC_NATIVE = 0, TR_PREC_BF16 = 1, TR_PREC_FP8E4M3 = 2 } tr_prec;
+
+/* Device status bits (OR-ed into tr_diag.status). */
+#define TR_DEV_NONFINITE 0x1u  /* a column norm or sketch entry was NaN/Inf   */
+#define TR_DEV_ZERO_DIST 0x2u  /* every column norm was zero: nothing to draw */
+
+typedef struct tr_params {
+  int32_t order;            /* N, 1 <= N <= TR_MAX_ORDER                          */
+  const int64_t *dims;      /* host [N]: I_1..I_N, each >= 1                       */
+  const int64_t *ranks;     /* host [N]: mu_n, 1 <= mu_n <= min(I_n, J_n) where J_n
+                               is the column count of the unfolding that mode n is
+                               computed from (original tensor for T-HOSVD, shrunk
+                               tensor mu_1..mu_{n-1} I_{n+1}..I_N for ST-HOSVD)    */
+  int32_t oversample;       /* K >= 0; sketch width s_n = min(mu_n + K, I_n)       */
+  int32_t power;            /* q >= 1 power steps                                  */
+  int32_t prob;             /* tr_prob                                             */
+  const int64_t *samples;   /* host [N]: T_n >= 1 sampled columns (prob != NONE);
+                               T_n > J_n computes that mode exactly.  May be NULL
+                               when prob == TR_PROB_NONE.                          */
+  uint64_t seed;            /* Philox4x64-10 key word 0                            */
+  int32_t precision;        /* tr_prec                                             */
+  uint32_t flags;           /* reserved, must be 0                                 */
+} tr_params;
+
+typedef struct tr_timer tr_timer;
+
+/* Optional per-mode diagnostics, all device memory (except timer); any pointer
+ * may be NULL. */
+typedef struct tr_diag {
+  int64_t *const *indices;  /* [N] -> T_n sampled column indices xi_t (0-based)   */
+  double *const *scales;    /* [N] -> T_n rescale factors 1/sqrt(T_n p_xi)        */
+  double *const *sketch;    /* [N] -> C_n, I_n x s_n float64                      */
+  double *const *sigma;     /* [N] -> s_n singular values of C_n, descending      */
+  uint32_t *status;         /* one word; TR_DEV_* bits are OR-ed in (caller zeroes) */
+  tr_timer *timer;          /* host handle from tucker_rand_timer_create, or NULL */
+} tr_diag;
+
+/* Text for a tr_status value (static storage). */
+const char *tucker_rand_status_string(int status);
+
+/*
+ * Bytes of device workspace needed by tucker_rand_thosvd (sthosvd == 0) or
+ * tucker_rand_sthosvd (sthosvd != 0) for these parameters and input dtype.
+ * Validates the parameters exactly as the driver does.
+ */
+int tucker_rand_workspace_size(const tr_params *p, int dtype, int sthosvd,
+                               size_t *bytes);
+
+/*
+ * Randomized T-HOSVD (Section 3): for every mode n independently of the others
+ * draw G_n (I_n x s_n Gaussian), form C_n = (A_(n) A_(n)^T)^q G_n (Alg. 1) or
+ * C'_n = A_(n) S_n, S_n ~ RANDSAMPLE(T_n, p_n), C_n = (C'_n C'_n^T)^q G_n (Alg. 4),
+ * take Q_n = the mu_n leading left singular vectors of C_n (Remark after Alg. 5),
+ * then core = A x_1 Q_1^T ... x_N Q_N^T.
+ *   A        device, column-major I_1 x ... x I_N, dtype; read only.
+ *   Q        host array [N] of device pointers; Q[n] receives I_n x mu_n (dtype).
+ *            Each column's largest-magnitude entry is positive.
+ *   core     device, mu_1 x ... x mu_N (dtype).
+ *   workspace, workspace_bytes: device scratch of at least the size reported by
+ *            tucker_rand_workspace_size(p, dtype, 0, ...).
+ *   diag     optional (may be NULL).
+ */
+int tucker_rand_thosvd(const tr_params *p, int dtype, const void *A,
+                       void *const *Q, void *core, void *workspace,
+                       size_t workspace_bytes, const tr_diag *diag, void *stream);
+
+/*
+ * Randomized ST-HOSVD (Section 4): modes in the order 1..N; after Q_n is found
+ * the current tensor is replaced by its shrink A x_n Q_n^T (Alg. 2 / Alg. 5),
+ * and the last shrink is the core.  Sampling probabilities of mode n refer to
+ * the shrunk tensor.  Arguments as tucker_rand_thosvd (sthosvd workspace size).
+ */
+int tucker_rand_sthosvd(const tr_params *p, int dtype, const void *A,
+                        void *const *Q, void *core, void *workspace,
+                        size_t workspace_bytes, const tr_diag *diag, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Individual steps of the per-mode range finder.
+ * ------------------------------------------------------------------------- */
+
+/*
+ * Standard Gaussian matrix G_n (Alg. 1 step 2; Alg. 4 step 5): G device float64
+ * I x s column-major.  Element e = i + I*c takes the Philox4x64-10 block with
+ * counter (e/4, mode, 0, 0) and key (seed, 0); output words (0,1) and (2,3) are
+ * Box-Muller pairs.
+ */
+int tucker_rand_gaussian(int64_t I, int64_t s, int32_t mode, uint64_t seed,
+                         double *G, void *stream);
+
+/*
+ * Squared column norms n_j = ||A_(n)(:,j)||^2 of the mode-n unfolding of the
+ * L x I x R view of X (device, dtype), summed in float64 over rows in
+ * increasing order (Remark after Alg. 3, nearly-optimal probabilities).
+ * norms: device float64 [L*R].  max_bits (device uint64, may be NULL): receives
+ * the atomic maximum of the IEEE bit patterns of the norms; the caller sets it
+ * to 0 beforehand.
+ */
+int tucker_rand_colnorms(int dtype, const void *X, int64_t L, int64_t I,
+                         int64_t R, double *norms, uint64_t *max_bits,
+                         void *stream);
+
+/* Device workspace bytes needed by tucker_rand_sample for J columns. */
+size_t tucker_rand_sample_workspace_size(int64_t J);
+
+/*
+ * RANDSAMPLE(T, p) of Section 3.2 as index/scale pairs: S[idx[t], t] = scale[t].
+ * prob = TR_PROB_NEARLY_OPTIMAL: norms (device float64 [J], finite, not all 0)
+ *   are quantised to integer weights w_j = floor((n_j / max n) * 2^(60 -
+ *   ceil(log2 J))), raised to 1 for every non-zero column;
+ * prob = TR_PROB_UNIFORM: w_j = 1 and norms may be NULL.
+ * Draw t uses the Philox4x64-10 block with counter (t/2, mode, 1, 0), key
+ * (seed, 0), words (2(t%2), 2(t%2)+1) = (h, l): x = floor((h 2^64 + l) W / 2^128),
+ * idx[t] = min{ j : w_0 + ... + w_j > x }, scale[t] = sqrt((W / w_idx) / T)
+ * with W = sum w.  idx: device int64 [T]; scale: device float64 [T].
+ * workspace: device, >= tucker_rand_sample_workspace_size(J) bytes.
+ * status (device, may be NULL) receives TR_DEV_* bits.
+ */
+int tucker_rand_sample(const double *norms, int64_t J, int64_t T, int prob,
+                       uint64_t seed, int32_t mode, int64_t *idx, double *scale,
+                       void *workspace, size_t workspace_bytes,
+                       uint32_t *status, void *stream);
+
+/*
+ * Gather of the sampled product C'_n = A_(n) S_n without its rescale
+ * (Alg. 4 step 4): Cp[:, t] = A_(n)(:, idx[t]) for the L x I x R view of X.
+ * Cp: device I x T, same dtype as X.  idx: device int64 [T], each < L*R.
+ */
+int tucker_rand_gather(int dtype, const void *X, int64_t L, int64_t I,
+                       int64_t R, const int64_t *idx, int64_t T, void *Cp,
+                       void *stream);
+
+/* Device workspace bytes needed by tucker_rand_power for these sizes. */
+size_t tucker_rand_power_workspace_size(int64_t L, int64_t I, int64_t R,
+                                        int64_t s);
+
+/*
+ * Power-scheme products (Alg. 1 step 4 by Strategy A of the Remark after
+ * Alg. 1; Alg. 4 step 6): C = (M D M^T)^q G where M is the mode-n unfolding of
+ * the L x I x R view of X (device, dtype) and D = diag(colweight) (device
+ * float64 [L*R], or NULL for the identity).  With X a gathered I x T matrix
+ * (L = 1, R = T) and colweight = scale^2 this is (C'_n C'_n^T)^q G_n.
+ * G, C: device float64 I x s (may alias).  Float64 accumulation.
+ */
+int tucker_rand_power(int dtype, const void *X, int64_t L, int64_t I,
+                      int64_t R, const double *colweight, int32_t q,
+                      const double *G, int64_t s, double *C, void *workspace,
+                      size_t workspace_bytes, void *stream);
+
+/*
+ * Factor of a sketch (Remark after Alg. 5): Q = the mu leading left singular
+ * vectors of C (device float64 I x s, 1 <= mu <= s <= I), each column's
+ * largest-magnitude entry made positive (lowest row on ties).  Computed with
+ * a Householder QR C = P R, a one-sided Jacobi SVD of R and Q = P U_R(:, 1:mu),
+ * all in float64 on one workgroup.  Q: device float64 I x mu; sigma: device
+ * float64 [s] singular values in descending order (may be NULL).
+ * Supported sizes: s <= 64 and I*s <= 32768 (TR_ENOTSUP otherwise).
+ */
+int tucker_rand_factor(const double *C, int64_t I, int64_t s, int64_t mu,
+                       double *Q, double *sigma, void *stream);
+
+/*
+ * Mode-n product Y = X x_n Q^T (Section 2): for the L x I x R view of X
+ * (device, in_dtype) and Q (device float64 I x mu), Y is L x mu x R (device,
+ * out_dtype) with Y(l, k, r) = sum_i Q(i, k) X(l, i, r), float64 accumulation.
+ * This is the ST-HOSVD shrink (Alg. 2 step 6) and each link of the T-HOSVD
+ * core chain.  Q is transposed into Qt (device float64 mu*I, row i holds Q(i,:))
+ * first; Qt must be provided by the caller as scratch.
+ */
+int tucker_rand_ttm(int in_dtype, const void *X, int64_t L, int64_t I,
+                    int64_t R, const double *Q, int64_t mu, double *Qt,
+                    int out_dtype, void *Y, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Kernel timing (benchmarking aid).  A timer owns a pool of HIP events; when it
+ * is passed in tr_diag.timer, the drivers record an event pair on the launch
+ * stream around every kernel of the selected classes.  Read it after
+ * synchronising the stream.
+ * ------------------------------------------------------------------------- */
+typedef enum {
+  TR_KC_COLNORMS = 0, TR_KC_SAMPLE = 1, TR_KC_GATHER = 2, TR_KC_POWER = 3,
+  TR_KC_FACTOR = 4, TR_KC_TTM = 5, TR_KC_GAUSSIAN = 6, TR_KC_COUNT = 7
+} tr_kernel_class;
+
+/* capacity: maximum number of timed launches; class_mask: bit c times class c. */
+int tucker_rand_timer_create(int capacity, uint32_t class_mask, tr_timer **out);
+int tucker_rand_timer_destroy(tr_timer *t);
+/* Clears recorded launches. */
+int tucker_rand_timer_reset(tr_timer *t);
+/* Sum of elapsed milliseconds and number of launches recorded for a class, and
+ * for the first-mode launch of that class only (mode-1 sweeps of the full
+ * tensor); synchronises on the recorded events. */
+int tucker_rand_timer_read(tr_timer *t, int kernel_class, double *total_ms,
+                           int64_t *launches, double *mode0_ms,
+                           int64_t *mode0_launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TUCKER_RAND_H */

@@ -1,0 +1,337 @@
+"""Randomized T-HOSVD / ST-HOSVD with the power scheme and approximate matrix
+multiplication (Che, Wei, Yan) on AMD MI355X (gfx950).
+
+This module is a thin binding over the C ABI of ``include/tucker_rand.h``: it
+checks tensor layouts, allocates outputs and workspaces through torch (device
+memory and streams only) and passes raw pointers.  Every arithmetic step runs
+in the library's HIP kernels; if the library is missing, every call raises.
+
+Tensors are column-major: a tensor of shape (I_1, ..., I_N) must have strides
+(1, I_1, I_1 I_2, ...).  ``colmajor_empty`` and ``to_device`` make such tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+from ctypes import byref, c_double, c_int64, c_size_t, c_void_p
+from typing import Optional, Sequence
+
+import torch
+
+from . import _abi
+from ._abi import KC, PREC, PROB, TR_F32, TR_F64, check, lib
+
+__all__ = [
+    "colmajor_empty", "to_device", "is_colmajor", "Timer",
+    "tucker_rand_workspace_size", "tucker_rand_thosvd", "tucker_rand_sthosvd",
+    "tucker_rand_gaussian", "tucker_rand_colnorms", "tucker_rand_sample",
+    "tucker_rand_gather", "tucker_rand_power", "tucker_rand_factor",
+    "tucker_rand_ttm", "tucker_rand_status_string",
+]
+
+_DT = {torch.float64: TR_F64, torch.float32: TR_F32}
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype not in _DT:
+        raise TypeError(f"unsupported dtype {t.dtype}; use float32 or float64")
+    return _DT[t.dtype]
+
+
+def colmajor_empty(shape: Sequence[int], dtype=torch.float64, device="cuda") -> torch.Tensor:
+    """Uninitialised tensor of ``shape`` with column-major strides."""
+    shape = tuple(int(s) for s in shape)
+    n = len(shape)
+    return torch.empty(shape[::-1], dtype=dtype, device=device).permute(*range(n - 1, -1, -1))
+
+
+def is_colmajor(t: torch.Tensor) -> bool:
+    stride = 1
+    for size, st in zip(t.shape, t.stride()):
+        if size != 1 and st != stride:
+            return False
+        stride *= size
+    return True
+
+
+def to_device(a, dtype=None, device="cuda") -> torch.Tensor:
+    """Copy a numpy array (any order) into a column-major device tensor."""
+    src = torch.as_tensor(a)
+    out = colmajor_empty(src.shape, dtype or src.dtype, device)
+    out.copy_(src)
+    return out
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return c_void_p(stream.cuda_stream)
+
+
+def _i64arr(vals):
+    arr = (c_int64 * len(vals))(*[int(v) for v in vals])
+    return arr
+
+
+def _params(dims, ranks, oversample, power, prob, samples, seed, precision):
+    N = len(dims)
+    if len(ranks) != N:
+        raise ValueError("ranks needs one entry per mode")
+    p = _abi.TrParams()
+    keep = [_i64arr(dims), _i64arr(ranks)]
+    p.order = N
+    p.dims = ctypes.cast(keep[0], ctypes.POINTER(c_int64))
+    p.ranks = ctypes.cast(keep[1], ctypes.POINTER(c_int64))
+    p.oversample = int(oversample)
+    p.power = int(power)
+    p.prob = PROB[prob] if isinstance(prob, str) else int(prob)
+    if samples is not None:
+        if len(samples) != N:
+            raise ValueError("samples needs one entry per mode")
+        keep.append(_i64arr(samples))
+        p.samples = ctypes.cast(keep[2], ctypes.POINTER(c_int64))
+    p.seed = int(seed) & ((1 << 64) - 1)
+    p.precision = PREC[precision] if isinstance(precision, str) else int(precision)
+    p.flags = 0
+    return p, keep
+
+
+def tucker_rand_status_string(code: int) -> str:
+    return _abi.status_string(code)
+
+
+def tucker_rand_workspace_size(dims, ranks, oversample=10, power=1, prob="none",
+                               samples=None, seed=0, dtype=torch.float32,
+                               sthosvd=True, precision="native") -> int:
+    """Bytes of workspace tucker_rand_(s)thosvd needs (validates the arguments)."""
+    p, _keep = _params(dims, ranks, oversample, power, prob, samples, seed, precision)
+    out = c_size_t(0)
+    check("tucker_rand_workspace_size",
+          lib().tucker_rand_workspace_size(byref(p), _DT[dtype], int(bool(sthosvd)), byref(out)))
+    return out.value
+
+
+class Timer:
+    """Event-based kernel timer (tucker_rand_timer_*)."""
+
+    def __init__(self, capacity=4096, classes=("colnorms", "ttm", "power", "factor",
+                                               "sample", "gather", "gaussian")):
+        mask = 0
+        for c in classes:
+            mask |= 1 << KC[c]
+        h = c_void_p()
+        check("tucker_rand_timer_create",
+              lib().tucker_rand_timer_create(int(capacity), mask, byref(h)))
+        self.handle = h
+
+    def reset(self):
+        check("tucker_rand_timer_reset", lib().tucker_rand_timer_reset(self.handle))
+
+    def read(self, cls: str):
+        """(total_ms, launches, mode0_ms, mode0_launches) for a kernel class."""
+        t, n, t0, n0 = c_double(), c_int64(), c_double(), c_int64()
+        check("tucker_rand_timer_read",
+              lib().tucker_rand_timer_read(self.handle, KC[cls], byref(t), byref(n),
+                                           byref(t0), byref(n0)))
+        return t.value, n.value, t0.value, n0.value
+
+    def close(self):
+        if self.handle:
+            lib().tucker_rand_timer_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _decompose(fn_name, A, ranks, oversample, power, prob, samples, seed, precision,
+               diag, timer, workspace, stream, out=None):
+    if not A.is_cuda:
+        raise ValueError("A must be a device tensor")
+    if not is_colmajor(A):
+        raise ValueError("A must be column-major (use to_device / colmajor_empty)")
+    dims = tuple(A.shape)
+    N = len(dims)
+    dt = _dtype_code(A)
+    sthosvd = fn_name == "tucker_rand_sthosvd"
+    p, keep = _params(dims, ranks, oversample, power, prob, samples, seed, precision)
+    need = c_size_t(0)
+    check("tucker_rand_workspace_size",
+          lib().tucker_rand_workspace_size(byref(p), dt, int(sthosvd), byref(need)))
+    if workspace is None or workspace.numel() < need.value:
+        workspace = torch.empty(max(need.value, 1), dtype=torch.uint8, device=A.device)
+    if out is None:
+        Qs = [colmajor_empty((dims[n], ranks[n]), A.dtype, A.device) for n in range(N)]
+        core = colmajor_empty(tuple(ranks), A.dtype, A.device)
+    else:
+        Qs, core = out
+    qptrs = (c_void_p * N)(*[q.data_ptr() for q in Qs])
+    info = {}
+    dstruct = None
+    if diag or timer is not None:
+        dstruct = _abi.TrDiag()
+        if diag:
+            status = torch.zeros(1, dtype=torch.int32, device=A.device)
+            info["status"] = status
+            dstruct.status = status.data_ptr()
+            # sketches and singular values for every mode
+            s = [min(ranks[n] + oversample, dims[n]) for n in range(N)]
+            cur = list(dims)
+            I_n = []
+            for n in range(N):
+                I_n.append(cur[n])
+                if sthosvd:
+                    cur[n] = ranks[n]
+            info["sketch"] = [torch.zeros((s[n], I_n[n]), dtype=torch.float64,
+                                          device=A.device).t() for n in range(N)]
+            info["sigma"] = [torch.zeros(s[n], dtype=torch.float64, device=A.device)
+                             for n in range(N)]
+            skp = (c_void_p * N)(*[t.data_ptr() for t in info["sketch"]])
+            sgp = (c_void_p * N)(*[t.data_ptr() for t in info["sigma"]])
+            keep += [skp, sgp]
+            dstruct.sketch = ctypes.cast(skp, ctypes.POINTER(c_void_p))
+            dstruct.sigma = ctypes.cast(sgp, ctypes.POINTER(c_void_p))
+            if samples is not None and PROB.get(prob, prob) != 0:
+                info["indices"] = [torch.full((int(samples[n]),), -1, dtype=torch.int64,
+                                              device=A.device) for n in range(N)]
+                info["scales"] = [torch.zeros(int(samples[n]), dtype=torch.float64,
+                                              device=A.device) for n in range(N)]
+                ip = (c_void_p * N)(*[t.data_ptr() for t in info["indices"]])
+                sp = (c_void_p * N)(*[t.data_ptr() for t in info["scales"]])
+                keep += [ip, sp]
+                dstruct.indices = ctypes.cast(ip, ctypes.POINTER(c_void_p))
+                dstruct.scales = ctypes.cast(sp, ctypes.POINTER(c_void_p))
+        if timer is not None:
+            dstruct.timer = timer.handle
+    fn = getattr(lib(), fn_name)
+    rc = fn(byref(p), dt, c_void_p(A.data_ptr()), qptrs, c_void_p(core.data_ptr()),
+            c_void_p(workspace.data_ptr()), c_size_t(workspace.numel()),
+            byref(dstruct) if dstruct is not None else None, _stream(stream))
+    check(fn_name, rc)
+    return Qs, core, info
+
+
+def tucker_rand_thosvd(A: torch.Tensor, ranks, oversample=10, power=1, prob="none",
+                       samples=None, seed=0, precision="native", diag=False, timer=None,
+                       workspace=None, stream=None, out=None):
+    """Randomized T-HOSVD (Alg. 1 / Alg. 4).  Returns (Q list, core, diag dict)."""
+    return _decompose("tucker_rand_thosvd", A, ranks, oversample, power, prob, samples,
+                      seed, precision, diag, timer, workspace, stream, out)
+
+
+def tucker_rand_sthosvd(A: torch.Tensor, ranks, oversample=10, power=1, prob="none",
+                        samples=None, seed=0, precision="native", diag=False, timer=None,
+                        workspace=None, stream=None, out=None):
+    """Randomized ST-HOSVD (Alg. 2 / Alg. 5).  Returns (Q list, core, diag dict)."""
+    return _decompose("tucker_rand_sthosvd", A, ranks, oversample, power, prob, samples,
+                      seed, precision, diag, timer, workspace, stream, out)
+
+
+def _view3(X: torch.Tensor, L, I, R):
+    if not X.is_cuda or not X.is_contiguous() and not is_colmajor(X):
+        raise ValueError("X must be a dense device tensor")
+    if X.numel() != L * I * R:
+        raise ValueError("L*I*R does not match the tensor size")
+
+
+def tucker_rand_gaussian(I: int, s: int, mode: int, seed: int, device="cuda", stream=None):
+    """G_n (I x s, float64, column-major) from the library's Philox stream."""
+    G = colmajor_empty((I, s), torch.float64, device)
+    check("tucker_rand_gaussian",
+          lib().tucker_rand_gaussian(I, s, mode, int(seed) & ((1 << 64) - 1),
+                                     c_void_p(G.data_ptr()), _stream(stream)))
+    return G
+
+
+def tucker_rand_colnorms(X: torch.Tensor, L: int, I: int, R: int, stream=None):
+    """(norms float64 [L*R], max bit pattern as int64 tensor [1])."""
+    _view3(X, L, I, R)
+    norms = torch.empty(L * R, dtype=torch.float64, device=X.device)
+    mb = torch.zeros(1, dtype=torch.int64, device=X.device)
+    check("tucker_rand_colnorms",
+          lib().tucker_rand_colnorms(_dtype_code(X), c_void_p(X.data_ptr()), L, I, R,
+                                     c_void_p(norms.data_ptr()), c_void_p(mb.data_ptr()),
+                                     _stream(stream)))
+    return norms, mb
+
+
+def tucker_rand_sample(norms: Optional[torch.Tensor], J: int, T: int, prob: str, seed: int,
+                       mode: int, device="cuda", stream=None):
+    """(idx int64 [T], scale float64 [T], status int32 [1])."""
+    ws = torch.empty(max(1, lib().tucker_rand_sample_workspace_size(J)), dtype=torch.uint8,
+                     device=device)
+    idx = torch.empty(T, dtype=torch.int64, device=device)
+    scale = torch.empty(T, dtype=torch.float64, device=device)
+    status = torch.zeros(1, dtype=torch.int32, device=device)
+    check("tucker_rand_sample",
+          lib().tucker_rand_sample(_ptr(norms), J, T, PROB[prob], int(seed) & ((1 << 64) - 1),
+                                   mode, c_void_p(idx.data_ptr()), c_void_p(scale.data_ptr()),
+                                   c_void_p(ws.data_ptr()), c_size_t(ws.numel()),
+                                   c_void_p(status.data_ptr()), _stream(stream)))
+    return idx, scale, status
+
+
+def tucker_rand_gather(X: torch.Tensor, L: int, I: int, R: int, idx: torch.Tensor,
+                       stream=None):
+    """C' = A_(n)(:, idx) without rescale, I x T column-major (X's dtype)."""
+    _view3(X, L, I, R)
+    T = idx.numel()
+    Cp = colmajor_empty((I, T), X.dtype, X.device)
+    check("tucker_rand_gather",
+          lib().tucker_rand_gather(_dtype_code(X), c_void_p(X.data_ptr()), L, I, R,
+                                   c_void_p(idx.data_ptr()), T, c_void_p(Cp.data_ptr()),
+                                   _stream(stream)))
+    return Cp
+
+
+def tucker_rand_power(X: torch.Tensor, L: int, I: int, R: int, G: torch.Tensor, q: int,
+                      colweight: Optional[torch.Tensor] = None, stream=None):
+    """C = (M D M^T)^q G for the mode-n unfolding M of the L x I x R view of X."""
+    _view3(X, L, I, R)
+    if not is_colmajor(G) or G.dtype != torch.float64:
+        raise ValueError("G must be column-major float64")
+    s = G.shape[1]
+    C = colmajor_empty((I, s), torch.float64, X.device)
+    wsn = lib().tucker_rand_power_workspace_size(L, I, R, s)
+    ws = torch.empty(max(1, wsn), dtype=torch.uint8, device=X.device)
+    check("tucker_rand_power",
+          lib().tucker_rand_power(_dtype_code(X), c_void_p(X.data_ptr()), L, I, R,
+                                  _ptr(colweight), q, c_void_p(G.data_ptr()), s,
+                                  c_void_p(C.data_ptr()), c_void_p(ws.data_ptr()),
+                                  c_size_t(ws.numel()), _stream(stream)))
+    return C
+
+
+def tucker_rand_factor(C: torch.Tensor, mu: int, stream=None):
+    """(Q I x mu float64 column-major, sigma [s]) from a sketch C (I x s float64)."""
+    if not is_colmajor(C) or C.dtype != torch.float64:
+        raise ValueError("C must be column-major float64")
+    I, s = C.shape
+    Q = colmajor_empty((I, mu), torch.float64, C.device)
+    sig = torch.empty(s, dtype=torch.float64, device=C.device)
+    check("tucker_rand_factor",
+          lib().tucker_rand_factor(c_void_p(C.data_ptr()), I, s, mu, c_void_p(Q.data_ptr()),
+                                   c_void_p(sig.data_ptr()), _stream(stream)))
+    return Q, sig
+
+
+def tucker_rand_ttm(X: torch.Tensor, L: int, I: int, R: int, Q: torch.Tensor,
+                    out_dtype=torch.float64, stream=None):
+    """Y = X x_n Q^T as a flat column-major L x mu x R buffer (out_dtype)."""
+    _view3(X, L, I, R)
+    if not is_colmajor(Q) or Q.dtype != torch.float64:
+        raise ValueError("Q must be column-major float64")
+    mu = Q.shape[1]
+    Qt = torch.empty(I * mu, dtype=torch.float64, device=X.device)
+    Y = torch.empty(L * mu * R, dtype=out_dtype, device=X.device)
+    check("tucker_rand_ttm",
+          lib().tucker_rand_ttm(_dtype_code(X), c_void_p(X.data_ptr()), L, I, R,
+                                c_void_p(Q.data_ptr()), mu, c_void_p(Qt.data_ptr()),
+                                _DT[out_dtype], c_void_p(Y.data_ptr()), _stream(stream)))
+    return Y

@@ -1,0 +1,117 @@
+// Device helpers shared by the gfx950 kernels: the Philox4x64-10 generator and
+// wave64 / workgroup reductions with a fixed (deterministic) combination order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace trk {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): 256-bit counter, 128-bit
+// key, ten rounds.  Each round forms the 128-bit products of counter words 0
+// and 2 with two odd multipliers and recombines them with words 1, 3 and the
+// key; the key advances by two Weyl increments between rounds.
+// ---------------------------------------------------------------------------
+struct U64x4 {
+  uint64_t w[4];
+};
+
+__device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1,
+                                               uint64_t c2, uint64_t c3,
+                                               uint64_t k0, uint64_t k1) {
+  constexpr uint64_t kM0 = 0xD2E7470EE14C6C93ull;
+  constexpr uint64_t kM1 = 0xCA5A826395121157ull;
+  constexpr uint64_t kW0 = 0x9E3779B97F4A7C15ull;
+  constexpr uint64_t kW1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += kW0;
+      k1 += kW1;
+    }
+    const uint64_t hi0 = __umul64hi(kM0, c0), lo0 = kM0 * c0;
+    const uint64_t hi1 = __umul64hi(kM1, c2), lo1 = kM1 * c2;
+    const uint64_t n0 = hi1 ^ c1 ^ k0;
+    const uint64_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  return U64x4{{c0, c1, c2, c3}};
+}
+
+// Counter word 2 ("tag") separates the two random streams of the method.
+constexpr uint64_t kTagGauss = 0;
+constexpr uint64_t kTagSample = 1;
+
+// ---------------------------------------------------------------------------
+// Reductions.  All combine in a fixed pattern, so results are bitwise
+// reproducible run to run.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 1; m < kWave; m <<= 1) v += __shfl_xor(v, m, kWave);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int m = 1; m < kWave; m <<= 1) v = fmax(v, __shfl_xor(v, m, kWave));
+  return v;
+}
+
+// Sum over the workgroup of one double per thread; every thread gets the
+// result.  `scratch` holds at least blockDim.x/64 + 1 doubles.  Contains two
+// barriers; the caller must not reuse `scratch` before all threads returned.
+__device__ __forceinline__ double block_sum(double v, double* scratch) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  v = wave_sum(v);
+  if (lane == 0) scratch[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < nw; ++w) t += scratch[w];
+  __syncthreads();
+  return t;
+}
+
+// Transpose-reduce of M values (M a power of two <= 64) across one wave: on
+// return lane l holds the wave-wide sum of value index wave_vec_index<M>(l).
+// Uses M-1 + (6 - log2 M) shuffles instead of 6*M.
+template <int M>
+__device__ __forceinline__ int wave_vec_index(int lane) {
+  int idx = 0;
+  int half = M / 2;
+#pragma unroll
+  for (int b = 0; (1 << b) < M; ++b, half /= 2)
+    if ((lane >> b) & 1) idx += half;
+  return idx;
+}
+
+template <int M>
+__device__ __forceinline__ double wave_vec_sum(double (&v)[M], int lane) {
+  static_assert(M >= 1 && M <= kWave && (M & (M - 1)) == 0, "M power of 2");
+  int b = 0;
+#pragma unroll
+  for (int half = M / 2; half >= 1; half /= 2, ++b) {
+    const int mask = 1 << b;
+    const bool up = (lane & mask) != 0;
+#pragma unroll
+    for (int q = 0; q < half; ++q) {
+      const double send = up ? v[q] : v[q + half];
+      const double keep = up ? v[q + half] : v[q];
+      v[q] = keep + __shfl_xor(send, mask, kWave);
+    }
+  }
+  double r = v[0];
+#pragma unroll
+  for (int mask = M; mask < kWave; mask <<= 1) r += __shfl_xor(r, mask, kWave);
+  return r;
+}
+
+}  // namespace trk

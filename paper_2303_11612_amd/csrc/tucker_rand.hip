@@ -1,0 +1,745 @@
+// Host side of the library: argument validation, workspace planning, the
+// per-mode launch sequences of randomized T-HOSVD (Alg. 1 / Alg. 4) and
+// ST-HOSVD (Alg. 2 / Alg. 5), and the exported C ABI of tucker_rand.h.
+//
+// Nothing here allocates device memory; every buffer comes from the caller's
+// workspace.  All launches go to the caller's stream and no call waits on the
+// device, so a whole decomposition can be enqueued (or captured) at once.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "tr_kernels.hpp"
+#include "tucker_rand.h"
+
+namespace {
+
+using trk::kNT;
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------------------
+// Kernel timer: a pool of event pairs recorded around selected launches.
+// ---------------------------------------------------------------------------
+struct TimedLaunch {
+  int cls;
+  int mode;
+  hipEvent_t start, stop;
+};
+
+}  // namespace
+
+struct tr_timer {
+  uint32_t mask = 0;
+  std::vector<hipEvent_t> pool;  // 2 * capacity events
+  std::vector<TimedLaunch> used;
+};
+
+namespace {
+
+struct TimeScope {
+  tr_timer* t = nullptr;
+  hipStream_t st = nullptr;
+  int idx = -1;
+  TimeScope(tr_timer* timer, int cls, int mode, hipStream_t stream) : st(stream) {
+    if (!timer || !(timer->mask & (1u << cls))) return;
+    const size_t k = timer->used.size();
+    if (2 * k + 1 >= timer->pool.size()) return;
+    t = timer;
+    idx = (int)k;
+    TimedLaunch tl{cls, mode, timer->pool[2 * k], timer->pool[2 * k + 1]};
+    timer->used.push_back(tl);
+    (void)hipEventRecord(tl.start, st);
+  }
+  ~TimeScope() {
+    if (t) (void)hipEventRecord(t->used[idx].stop, st);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Plan: per-mode shapes and the workspace layout.
+// ---------------------------------------------------------------------------
+struct ModePlan {
+  int64_t L, I, R, J;   // 3-D view of the tensor the mode is computed from
+  int64_t s, mu, T;     // sketch width, rank, samples (T = 0: exact)
+  bool sampled;
+  bool src_f64;         // the tensor of this mode is float64
+};
+
+struct Plan {
+  int N = 0;
+  bool sthosvd = false;
+  int dtype = TR_F64;
+  int prob = TR_PROB_NONE;
+  int q = 1;
+  uint64_t seed = 0;
+  int64_t dims[TR_MAX_ORDER];
+  ModePlan m[TR_MAX_ORDER];
+  // workspace offsets (bytes)
+  size_t oG, oY, oYt, oZ, oPart, oNorms, oW, oCdf, oBsum, oIdx, oScale, oScale2, oCp,
+      oMax, oSig, oX0, oX1, total;
+  size_t oQ[TR_MAX_ORDER], oQt[TR_MAX_ORDER];
+};
+
+inline int64_t gram_parts(int64_t jsrc) {
+  return std::min<int64_t>(256, std::max<int64_t>(1, cdiv(jsrc, 64)));
+}
+
+inline int factor_sm(int64_t s) { return s <= 16 ? 16 : (s <= 32 ? 32 : 64); }
+
+inline bool factor_supported(int64_t I, int64_t s) {
+  if (s < 1 || s > 64) return false;
+  const int64_t rpt = cdiv(I, trk::kFactorNT);
+  const int sm = factor_sm(s);
+  return rpt * sm <= 64 && rpt <= 4;
+}
+
+// Validates and fills the plan; returns TR_OK or an error code.
+int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
+  if (!p || !P) return TR_EINVAL;
+  if (dtype != TR_F64 && dtype != TR_F32) return TR_EINVAL;
+  if (p->order < 1 || p->order > TR_MAX_ORDER || !p->dims || !p->ranks) return TR_EINVAL;
+  if (p->oversample < 0 || p->power < 1) return TR_EINVAL;
+  if (p->prob != TR_PROB_NONE && p->prob != TR_PROB_NEARLY_OPTIMAL &&
+      p->prob != TR_PROB_UNIFORM)
+    return TR_EINVAL;
+  if (p->prob != TR_PROB_NONE && !p->samples) return TR_EINVAL;
+  if (p->flags != 0) return TR_EINVAL;
+  if (p->precision != TR_PREC_NATIVE) {
+    if (p->precision == TR_PREC_BF16 || p->precision == TR_PREC_FP8E4M3) return TR_ENOTSUP;
+    return TR_EINVAL;
+  }
+  const int N = p->order;
+  P->N = N;
+  P->sthosvd = sthosvd;
+  P->dtype = dtype;
+  P->prob = p->prob;
+  P->q = p->power;
+  P->seed = p->seed;
+  int64_t cur[TR_MAX_ORDER];
+  for (int n = 0; n < N; ++n) {
+    if (p->dims[n] < 1 || p->dims[n] > (int64_t)1 << 31) return TR_EINVAL;
+    P->dims[n] = cur[n] = p->dims[n];
+  }
+  double total_el = 1.0;
+  for (int n = 0; n < N; ++n) total_el *= (double)cur[n];
+  if (total_el > 9.0e15) return TR_EINVAL;
+
+  size_t maxIs = 0, maxZ = 0, maxPart = 0, maxJs = 0, maxT = 0, maxCp = 0, maxInter = 0;
+  int64_t maxS = 0;
+  for (int n = 0; n < N; ++n) {
+    ModePlan& M = P->m[n];
+    M.L = 1;
+    M.R = 1;
+    for (int k = 0; k < n; ++k) M.L *= cur[k];
+    for (int k = n + 1; k < N; ++k) M.R *= cur[k];
+    M.I = cur[n];
+    M.J = M.L * M.R;
+    M.mu = p->ranks[n];
+    if (M.mu < 1 || M.mu > M.I || M.mu > M.J) return TR_EINVAL;
+    M.s = std::min<int64_t>(M.mu + p->oversample, M.I);
+    M.src_f64 = (dtype == TR_F64) || (sthosvd && n > 0);
+    M.T = 0;
+    M.sampled = false;
+    if (p->prob != TR_PROB_NONE) {
+      if (p->samples[n] < 1) return TR_EINVAL;
+      if (p->samples[n] <= M.J) {
+        M.sampled = true;
+        M.T = p->samples[n];
+      }
+    }
+    if (!factor_supported(M.I, M.s)) return TR_ENOTSUP;
+    const int64_t jsrc = M.sampled ? M.T : M.J;
+    maxIs = std::max(maxIs, (size_t)(M.I * M.s));
+    maxZ = std::max(maxZ, (size_t)(jsrc * M.s));
+    maxPart = std::max(maxPart, (size_t)(gram_parts(jsrc) * M.I * M.s));
+    maxS = std::max(maxS, M.s);
+    if (M.sampled) {
+      maxJs = std::max(maxJs, (size_t)M.J);
+      maxT = std::max(maxT, (size_t)M.T);
+      maxCp = std::max(maxCp, (size_t)(M.I * M.T));
+    }
+    if (sthosvd) cur[n] = M.mu;  // the next mode sees the shrunk tensor
+  }
+  // intermediate tensors: after the n-th shrink of the chain (n < N-1)
+  {
+    int64_t shp[TR_MAX_ORDER];
+    for (int n = 0; n < N; ++n) shp[n] = P->dims[n];
+    for (int n = 0; n + 1 < N; ++n) {
+      shp[n] = P->m[n].mu;
+      size_t e = 1;
+      for (int k = 0; k < N; ++k) e *= (size_t)shp[k];
+      maxInter = std::max(maxInter, e);
+    }
+  }
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(std::max<size_t>(bytes, 8));
+    return o;
+  };
+  P->oG = take(8 * maxIs);
+  P->oY = take(8 * maxIs);
+  P->oYt = take(8 * maxIs);
+  P->oZ = take(8 * maxZ);
+  P->oPart = take(8 * maxPart);
+  P->oNorms = take(8 * maxJs);
+  P->oW = take(8 * maxJs);
+  P->oCdf = take(8 * maxJs);
+  P->oBsum = take(8 * (size_t)(cdiv((int64_t)maxJs, trk::kScanChunk) + 1));
+  P->oIdx = take(8 * maxT);
+  P->oScale = take(8 * maxT);
+  P->oScale2 = take(8 * maxT);
+  P->oCp = take(8 * maxCp);
+  P->oMax = take(8);
+  P->oSig = take(8 * (size_t)maxS);
+  for (int n = 0; n < N; ++n) {
+    P->oQ[n] = take(8 * (size_t)(P->m[n].I * P->m[n].mu));
+    P->oQt[n] = take(8 * (size_t)(P->m[n].I * P->m[n].mu));
+  }
+  P->oX0 = take(8 * maxInter);
+  P->oX1 = take(8 * maxInter);
+  P->total = off;
+  return TR_OK;
+}
+
+inline int check_launch() { return hipGetLastError() == hipSuccess ? TR_OK : TR_EDEVICE; }
+
+#define TR_TRY(expr)              \
+  do {                            \
+    const int _rc = (expr);       \
+    if (_rc != TR_OK) return _rc; \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Launchers (all asynchronous on `st`).
+// ---------------------------------------------------------------------------
+int launch_gaussian(double* G, double* Gt, int64_t I, int64_t s, int mode, uint64_t seed,
+                    hipStream_t st) {
+  const int64_t blocks4 = cdiv(I * s, 4);
+  hipLaunchKernelGGL(trk::k_gaussian, dim3((unsigned)cdiv(blocks4, kNT)), dim3(kNT), 0, st,
+                     G, Gt, I, s, (uint64_t)mode, seed);
+  return check_launch();
+}
+
+template <typename T>
+int launch_colnorms_t(const T* X, int64_t L, int64_t I, int64_t R, double* norms,
+                      unsigned long long* maxb, hipStream_t st) {
+  const int64_t J = L * R;
+  const dim3 grid((unsigned)cdiv(J, kNT));
+  if (L == 1)
+    hipLaunchKernelGGL(trk::k_colnorms_l1<T>, grid, dim3(kNT), 0, st, X, I, J, norms, maxb);
+  else
+    hipLaunchKernelGGL(trk::k_colnorms_ln<T>, grid, dim3(kNT), 0, st, X, L, I, R, norms, maxb);
+  return check_launch();
+}
+
+int launch_colnorms(bool f64, const void* X, int64_t L, int64_t I, int64_t R, double* norms,
+                    unsigned long long* maxb, hipStream_t st) {
+  return f64 ? launch_colnorms_t((const double*)X, L, I, R, norms, maxb, st)
+             : launch_colnorms_t((const float*)X, L, I, R, norms, maxb, st);
+}
+
+int launch_fill(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t st) {
+  hipLaunchKernelGGL(trk::k_fill_u64, dim3((unsigned)cdiv(n, kNT)), dim3(kNT), 0, st, p, n, v);
+  return check_launch();
+}
+
+size_t sample_ws_bytes(int64_t J) {
+  return align_up(8 * (size_t)J) * 2 + align_up(8 * (size_t)(cdiv(J, trk::kScanChunk) + 1)) +
+         align_up(8);
+}
+
+// w, cdf: [J] u64; bsum: [ceil(J/1024)+1] u64.  norms/max_bits only for
+// nearly-optimal probabilities.
+int launch_sample(const double* norms, const unsigned long long* maxb, int64_t J, int64_t T,
+                  int prob, uint64_t seed, int mode, unsigned long long* w,
+                  unsigned long long* cdf, unsigned long long* bsum, int64_t* idx,
+                  double* scale, double* scale2, uint32_t* status, hipStream_t st) {
+  const int uniform = prob == TR_PROB_UNIFORM;
+  if (!uniform) {
+    int cl2 = 0;
+    while (((int64_t)1 << cl2) < J) ++cl2;
+    const int kexp = 60 - cl2;
+    const int64_t nb = cdiv(J, trk::kScanChunk);
+    hipLaunchKernelGGL(trk::k_weights, dim3((unsigned)nb), dim3(kNT), 0, st, norms, J, maxb,
+                       kexp, 0, w, bsum, status);
+    TR_TRY(check_launch());
+    hipLaunchKernelGGL(trk::k_scan_bsum, dim3(1), dim3(1024), 0, st, bsum, nb);
+    TR_TRY(check_launch());
+    hipLaunchKernelGGL(trk::k_cdf, dim3((unsigned)nb), dim3(kNT), 0, st, w, bsum, J, cdf);
+    TR_TRY(check_launch());
+  }
+  hipLaunchKernelGGL(trk::k_draw, dim3((unsigned)cdiv(T, kNT)), dim3(kNT), 0, st, cdf, J, T,
+                     seed, (uint64_t)mode, uniform, idx, scale, scale2);
+  return check_launch();
+}
+
+int launch_gather(bool f64, const void* X, int64_t L, int64_t I, const int64_t* idx, int64_t T,
+                  void* Cp, hipStream_t st) {
+  const dim3 grid((unsigned)T, (unsigned)cdiv(I, kNT));
+  if (f64)
+    hipLaunchKernelGGL(trk::k_gather<double>, grid, dim3(kNT), 0, st, (const double*)X, L, I,
+                       idx, (double*)Cp);
+  else
+    hipLaunchKernelGGL(trk::k_gather<float>, grid, dim3(kNT), 0, st, (const float*)X, L, I,
+                       idx, (float*)Cp);
+  return check_launch();
+}
+
+template <typename Tin, typename Tout, int MU>
+void ttm_mu(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Qt, int mu,
+            const double* colscale, Tout* Y, hipStream_t st) {
+  const dim3 grid((unsigned)cdiv(L * R, kNT));
+  if (L == 1)
+    hipLaunchKernelGGL((trk::k_ttm_l1<Tin, Tout, MU>), grid, dim3(kNT), 0, st, X, I, R, Qt, mu,
+                       colscale, Y);
+  else
+    hipLaunchKernelGGL((trk::k_ttm_ln<Tin, Tout, MU>), grid, dim3(kNT), 0, st, X, L, I, R, Qt,
+                       mu, colscale, Y);
+}
+
+template <typename Tin, typename Tout>
+int ttm_t(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Qt, int64_t mu,
+          const double* colscale, Tout* Y, hipStream_t st) {
+  if (mu <= 8) ttm_mu<Tin, Tout, 8>(X, L, I, R, Qt, (int)mu, colscale, Y, st);
+  else if (mu <= 16) ttm_mu<Tin, Tout, 16>(X, L, I, R, Qt, (int)mu, colscale, Y, st);
+  else if (mu <= 32) ttm_mu<Tin, Tout, 32>(X, L, I, R, Qt, (int)mu, colscale, Y, st);
+  else if (mu <= 64) ttm_mu<Tin, Tout, 64>(X, L, I, R, Qt, (int)mu, colscale, Y, st);
+  else return TR_ENOTSUP;
+  return check_launch();
+}
+
+int launch_ttm(bool in_f64, const void* X, int64_t L, int64_t I, int64_t R, const double* Qt,
+               int64_t mu, const double* colscale, bool out_f64, void* Y, hipStream_t st) {
+  if (in_f64) {
+    if (out_f64) return ttm_t((const double*)X, L, I, R, Qt, mu, colscale, (double*)Y, st);
+    return ttm_t((const double*)X, L, I, R, Qt, mu, colscale, (float*)Y, st);
+  }
+  if (out_f64) return ttm_t((const float*)X, L, I, R, Qt, mu, colscale, (double*)Y, st);
+  return ttm_t((const float*)X, L, I, R, Qt, mu, colscale, (float*)Y, st);
+}
+
+template <typename Tin, int SM>
+void gramb_sm(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Z, int s,
+              int64_t nparts, int64_t chunk, double* part, hipStream_t st) {
+  if (L == 1)
+    hipLaunchKernelGGL((trk::k_gramb_l1<Tin, SM>), dim3((unsigned)nparts), dim3(kNT), 0, st, X,
+                       I, R, Z, s, chunk, part);
+  else
+    hipLaunchKernelGGL((trk::k_gramb_ln<Tin, SM>), dim3((unsigned)nparts), dim3(kNT), 0, st, X,
+                       L, I, R, Z, s, chunk, part);
+}
+
+template <typename Tin>
+int gramb_t(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Z, int64_t s,
+            int64_t nparts, int64_t chunk, double* part, hipStream_t st) {
+  if (s <= 8) gramb_sm<Tin, 8>(X, L, I, R, Z, (int)s, nparts, chunk, part, st);
+  else if (s <= 16) gramb_sm<Tin, 16>(X, L, I, R, Z, (int)s, nparts, chunk, part, st);
+  else if (s <= 32) gramb_sm<Tin, 32>(X, L, I, R, Z, (int)s, nparts, chunk, part, st);
+  else if (s <= 64) gramb_sm<Tin, 64>(X, L, I, R, Z, (int)s, nparts, chunk, part, st);
+  else return TR_ENOTSUP;
+  return check_launch();
+}
+
+size_t power_ws_bytes(int64_t L, int64_t I, int64_t R, int64_t s) {
+  const int64_t J = L * R;
+  return align_up(8 * (size_t)(J * s)) + align_up(8 * (size_t)(gram_parts(J) * I * s)) +
+         align_up(8 * (size_t)(I * s));
+}
+
+// C = (X_(n) D X_(n)^T)^q G by alternating the two halves of Strategy A.
+// Yt: row-major copy of the current sketch (initially of G); Z, part: scratch.
+int run_power(bool f64, const void* X, int64_t L, int64_t I, int64_t R, const double* colw,
+              int q, int64_t s, double* Y, double* Yt, double* Z, double* part,
+              uint32_t* status, hipStream_t st) {
+  const int64_t J = L * R;
+  const int64_t nparts = gram_parts(J);
+  const int64_t chunk = cdiv(J, nparts);
+  const int64_t nused = cdiv(J, chunk);
+  for (int step = 0; step < q; ++step) {
+    TR_TRY(launch_ttm(f64, X, L, I, R, Yt, s, colw, true, Z, st));
+    if (f64) TR_TRY(gramb_t((const double*)X, L, I, R, Z, s, nused, chunk, part, st));
+    else TR_TRY(gramb_t((const float*)X, L, I, R, Z, s, nused, chunk, part, st));
+    hipLaunchKernelGGL(trk::k_reduce_parts, dim3((unsigned)cdiv(I * s, kNT)), dim3(kNT), 0, st,
+                       part, nused, I, (int)s, Y, Yt, status);
+    TR_TRY(check_launch());
+  }
+  return TR_OK;
+}
+
+template <int RPT, int SM>
+void factor_k(const double* C, int I, int s, int mu, double* Q, double* Qt, double* sig,
+              void* Qcast, int cast_f32, uint32_t* status, hipStream_t st) {
+  hipLaunchKernelGGL((trk::k_factor<RPT, SM>), dim3(1), dim3(trk::kFactorNT), 0, st, C, I, s,
+                     mu, Q, Qt, sig, Qcast, cast_f32, status);
+}
+
+int launch_factor(const double* C, int64_t I, int64_t s, int64_t mu, double* Q, double* Qt,
+                  double* sig, void* Qcast, int cast_f32, uint32_t* status, hipStream_t st) {
+  if (!factor_supported(I, s) || mu < 1 || mu > s) return TR_ENOTSUP;
+  const int64_t rpt = cdiv(I, trk::kFactorNT);
+  const int sm = factor_sm(s);
+  const int Ii = (int)I, si = (int)s, mi = (int)mu;
+  if (rpt == 1 && sm == 16) factor_k<1, 16>(C, Ii, si, mi, Q, Qt, sig, Qcast, cast_f32, status, st);
+  else if (rpt == 1 && sm == 32) factor_k<1, 32>(C, Ii, si, mi, Q, Qt, sig, Qcast, cast_f32, status, st);
+  else if (rpt == 1 && sm == 64) factor_k<1, 64>(C, Ii, si, mi, Q, Qt, sig, Qcast, cast_f32, status, st);
+  else if (rpt == 2 && sm == 16) factor_k<2, 16>(C, Ii, si, mi, Q, Qt, sig, Qcast, cast_f32, status, st);
+  else if (rpt == 2 && sm == 32) factor_k<2, 32>(C, Ii, si, mi, Q, Qt, sig, Qcast, cast_f32, status, st);
+  else if (rpt <= 4 && sm == 16) factor_k<4, 16>(C, Ii, si, mi, Q, Qt, sig, Qcast, cast_f32, status, st);
+  else return TR_ENOTSUP;
+  return check_launch();
+}
+
+// ---------------------------------------------------------------------------
+// Drivers
+// ---------------------------------------------------------------------------
+template <typename T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+int copy_d2d(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  if (!dst || bytes == 0) return TR_OK;
+  return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st) == hipSuccess
+             ? TR_OK
+             : TR_EDEVICE;
+}
+
+// Range finder of mode n on tensor X (3-D view from the plan): fills Q64 / Qt
+// of the mode in the workspace and the caller's Q (cast to dtype).
+int range_finder(const Plan& P, int n, const void* X, void* ws, void* Qout,
+                 const tr_diag* diag, hipStream_t st) {
+  const ModePlan& M = P.m[n];
+  tr_timer* tm = diag ? diag->timer : nullptr;
+  uint32_t* status = diag ? diag->status : nullptr;
+  double* G = at<double>(ws, P.oG);
+  double* Y = at<double>(ws, P.oY);
+  double* Yt = at<double>(ws, P.oYt);
+  double* Z = at<double>(ws, P.oZ);
+  double* part = at<double>(ws, P.oPart);
+  {
+    TimeScope ts(tm, TR_KC_GAUSSIAN, n, st);
+    TR_TRY(launch_gaussian(G, Yt, M.I, M.s, n, P.seed, st));
+  }
+  const void* src = X;
+  bool src_f64 = M.src_f64;
+  int64_t L = M.L, R = M.R;
+  const double* colw = nullptr;
+  if (M.sampled) {
+    double* norms = at<double>(ws, P.oNorms);
+    auto* maxb = at<unsigned long long>(ws, P.oMax);
+    int64_t* idx = at<int64_t>(ws, P.oIdx);
+    double* scale = at<double>(ws, P.oScale);
+    double* scale2 = at<double>(ws, P.oScale2);
+    if (P.prob == TR_PROB_NEARLY_OPTIMAL) {
+      TR_TRY(launch_fill(maxb, 1, 0ull, st));
+      TimeScope ts(tm, TR_KC_COLNORMS, n, st);
+      TR_TRY(launch_colnorms(M.src_f64, X, M.L, M.I, M.R, norms, maxb, st));
+    }
+    {
+      TimeScope ts(tm, TR_KC_SAMPLE, n, st);
+      TR_TRY(launch_sample(norms, maxb, M.J, M.T, P.prob, P.seed, n,
+                           at<unsigned long long>(ws, P.oW), at<unsigned long long>(ws, P.oCdf),
+                           at<unsigned long long>(ws, P.oBsum), idx, scale, scale2, status, st));
+    }
+    {
+      TimeScope ts(tm, TR_KC_GATHER, n, st);
+      TR_TRY(launch_gather(M.src_f64, X, M.L, M.I, idx, M.T, at<void>(ws, P.oCp), st));
+    }
+    if (diag && diag->indices && diag->indices[n])
+      TR_TRY(copy_d2d(diag->indices[n], idx, 8 * (size_t)M.T, st));
+    if (diag && diag->scales && diag->scales[n])
+      TR_TRY(copy_d2d(diag->scales[n], scale, 8 * (size_t)M.T, st));
+    src = at<void>(ws, P.oCp);
+    L = 1;
+    R = M.T;
+    colw = scale2;
+  }
+  // C_n = (M M^T)^q G_n, starting from Y = G_n (Yt already holds G_n^T).
+  {
+    TimeScope ts(tm, TR_KC_POWER, n, st);
+    TR_TRY(run_power(src_f64, src, L, M.I, R, colw, P.q, M.s, Y, Yt, Z, part, status, st));
+  }
+  if (diag && diag->sketch && diag->sketch[n])
+    TR_TRY(copy_d2d(diag->sketch[n], Y, 8 * (size_t)(M.I * M.s), st));
+  double* sig = (diag && diag->sigma && diag->sigma[n]) ? diag->sigma[n] : at<double>(ws, P.oSig);
+  {
+    TimeScope ts(tm, TR_KC_FACTOR, n, st);
+    TR_TRY(launch_factor(Y, M.I, M.s, M.mu, at<double>(ws, P.oQ[n]), at<double>(ws, P.oQt[n]),
+                         sig, Qout, P.dtype == TR_F32, status, st));
+  }
+  return TR_OK;
+}
+
+int check_buffers(const Plan& P, const void* A, void* const* Q, const void* core, void* ws,
+                  size_t ws_bytes) {
+  if (!A || !Q || !core) return TR_EINVAL;
+  for (int n = 0; n < P.N; ++n)
+    if (!Q[n]) return TR_EINVAL;
+  if (P.total > 0 && !ws) return TR_EINVAL;
+  if (ws_bytes < P.total) return TR_ENOMEM;
+  return TR_OK;
+}
+
+// Shrink chain X x_n Q_n^T over modes [n0, N): intermediates in float64
+// workspace buffers, the last one written to `core` in the caller's dtype.
+int core_chain(const Plan& P, const void* X, bool x_f64, int n0, const int64_t* shape_in,
+               void* ws, void* core, const tr_diag* diag, hipStream_t st) {
+  int64_t shp[TR_MAX_ORDER];
+  for (int k = 0; k < P.N; ++k) shp[k] = shape_in[k];
+  const void* cur = X;
+  bool cur_f64 = x_f64;
+  tr_timer* tm = diag ? diag->timer : nullptr;
+  for (int n = n0; n < P.N; ++n) {
+    int64_t L = 1, R = 1;
+    for (int k = 0; k < n; ++k) L *= shp[k];
+    for (int k = n + 1; k < P.N; ++k) R *= shp[k];
+    const bool last = n == P.N - 1;
+    void* out = last ? core : at<void>(ws, ((n - n0) % 2 == 0) ? P.oX0 : P.oX1);
+    const bool out_f64 = last ? (P.dtype == TR_F64) : true;
+    {
+      TimeScope ts(tm, TR_KC_TTM, n, st);
+      TR_TRY(launch_ttm(cur_f64, cur, L, shp[n], R, at<double>(ws, P.oQt[n]), P.m[n].mu,
+                        nullptr, out_f64, out, st));
+    }
+    shp[n] = P.m[n].mu;
+    cur = out;
+    cur_f64 = true;
+  }
+  return TR_OK;
+}
+
+int run_thosvd(const tr_params* p, int dtype, const void* A, void* const* Q, void* core,
+               void* ws, size_t ws_bytes, const tr_diag* diag, hipStream_t st) {
+  Plan P;
+  TR_TRY(make_plan(p, dtype, false, &P));
+  TR_TRY(check_buffers(P, A, Q, core, ws, ws_bytes));
+  for (int n = 0; n < P.N; ++n) TR_TRY(range_finder(P, n, A, ws, Q[n], diag, st));
+  return core_chain(P, A, dtype == TR_F64, 0, P.dims, ws, core, diag, st);
+}
+
+int run_sthosvd(const tr_params* p, int dtype, const void* A, void* const* Q, void* core,
+                void* ws, size_t ws_bytes, const tr_diag* diag, hipStream_t st) {
+  Plan P;
+  TR_TRY(make_plan(p, dtype, true, &P));
+  TR_TRY(check_buffers(P, A, Q, core, ws, ws_bytes));
+  int64_t shp[TR_MAX_ORDER];
+  for (int k = 0; k < P.N; ++k) shp[k] = P.dims[k];
+  const void* cur = A;
+  bool cur_f64 = dtype == TR_F64;
+  tr_timer* tm = diag ? diag->timer : nullptr;
+  for (int n = 0; n < P.N; ++n) {
+    TR_TRY(range_finder(P, n, cur, ws, Q[n], diag, st));
+    const ModePlan& M = P.m[n];
+    const bool last = n == P.N - 1;
+    void* out = last ? core : at<void>(ws, (n % 2 == 0) ? P.oX0 : P.oX1);
+    const bool out_f64 = last ? (dtype == TR_F64) : true;
+    {
+      TimeScope ts(tm, TR_KC_TTM, n, st);
+      TR_TRY(launch_ttm(cur_f64, cur, M.L, M.I, M.R, at<double>(ws, P.oQt[n]), M.mu, nullptr,
+                        out_f64, out, st));
+    }
+    shp[n] = M.mu;
+    cur = out;
+    cur_f64 = true;
+  }
+  return TR_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* tucker_rand_status_string(int status) {
+  switch (status) {
+    case TR_OK: return "ok";
+    case TR_EINVAL: return "invalid argument";
+    case TR_ENOMEM: return "workspace too small";
+    case TR_EDEVICE: return "HIP device error";
+    case TR_ENOTSUP: return "not supported by this build";
+    case TR_ENUMERIC: return "numeric failure";
+    default: return "unknown status";
+  }
+}
+
+int tucker_rand_workspace_size(const tr_params* p, int dtype, int sthosvd, size_t* bytes) {
+  if (!bytes) return TR_EINVAL;
+  Plan P;
+  const int rc = make_plan(p, dtype, sthosvd != 0, &P);
+  if (rc != TR_OK) return rc;
+  *bytes = P.total;
+  return TR_OK;
+}
+
+int tucker_rand_thosvd(const tr_params* p, int dtype, const void* A, void* const* Q, void* core,
+                       void* workspace, size_t workspace_bytes, const tr_diag* diag,
+                       void* stream) {
+  return run_thosvd(p, dtype, A, Q, core, workspace, workspace_bytes, diag, (hipStream_t)stream);
+}
+
+int tucker_rand_sthosvd(const tr_params* p, int dtype, const void* A, void* const* Q, void* core,
+                        void* workspace, size_t workspace_bytes, const tr_diag* diag,
+                        void* stream) {
+  return run_sthosvd(p, dtype, A, Q, core, workspace, workspace_bytes, diag,
+                     (hipStream_t)stream);
+}
+
+int tucker_rand_gaussian(int64_t I, int64_t s, int32_t mode, uint64_t seed, double* G,
+                         void* stream) {
+  if (I < 1 || s < 1 || !G || mode < 0) return TR_EINVAL;
+  return launch_gaussian(G, nullptr, I, s, mode, seed, (hipStream_t)stream);
+}
+
+int tucker_rand_colnorms(int dtype, const void* X, int64_t L, int64_t I, int64_t R,
+                         double* norms, uint64_t* max_bits, void* stream) {
+  if ((dtype != TR_F64 && dtype != TR_F32) || !X || !norms || L < 1 || I < 1 || R < 1)
+    return TR_EINVAL;
+  return launch_colnorms(dtype == TR_F64, X, L, I, R, norms, (unsigned long long*)max_bits,
+                         (hipStream_t)stream);
+}
+
+size_t tucker_rand_sample_workspace_size(int64_t J) { return J < 1 ? 0 : sample_ws_bytes(J); }
+
+int tucker_rand_sample(const double* norms, int64_t J, int64_t T, int prob, uint64_t seed,
+                       int32_t mode, int64_t* idx, double* scale, void* workspace,
+                       size_t workspace_bytes, uint32_t* status, void* stream) {
+  if (J < 1 || T < 1 || !idx || !scale || mode < 0) return TR_EINVAL;
+  if (prob != TR_PROB_NEARLY_OPTIMAL && prob != TR_PROB_UNIFORM) return TR_EINVAL;
+  if (prob == TR_PROB_NEARLY_OPTIMAL && !norms) return TR_EINVAL;
+  if (!workspace || workspace_bytes < sample_ws_bytes(J)) return TR_ENOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  auto* w = (unsigned long long*)ws;
+  auto* cdf = (unsigned long long*)(ws + align_up(8 * (size_t)J));
+  auto* bsum = (unsigned long long*)(ws + 2 * align_up(8 * (size_t)J));
+  auto* maxb = (unsigned long long*)(ws + 2 * align_up(8 * (size_t)J) +
+                                     align_up(8 * (size_t)(cdiv(J, trk::kScanChunk) + 1)));
+  if (prob == TR_PROB_NEARLY_OPTIMAL) {
+    // max over the given norms (order-free: integer max of the bit patterns)
+    TR_TRY(launch_fill(maxb, 1, 0ull, st));
+    hipLaunchKernelGGL(trk::k_max_bits, dim3((unsigned)cdiv(J, kNT)), dim3(kNT), 0, st, norms,
+                       J, maxb);
+    TR_TRY(check_launch());
+  }
+  return launch_sample(norms, maxb, J, T, prob, seed, mode, w, cdf, bsum, idx, scale, nullptr,
+                       status, st);
+}
+
+int tucker_rand_gather(int dtype, const void* X, int64_t L, int64_t I, int64_t R,
+                       const int64_t* idx, int64_t T, void* Cp, void* stream) {
+  if ((dtype != TR_F64 && dtype != TR_F32) || !X || !idx || !Cp || L < 1 || I < 1 || R < 1 ||
+      T < 1)
+    return TR_EINVAL;
+  return launch_gather(dtype == TR_F64, X, L, I, idx, T, Cp, (hipStream_t)stream);
+}
+
+size_t tucker_rand_power_workspace_size(int64_t L, int64_t I, int64_t R, int64_t s) {
+  if (L < 1 || I < 1 || R < 1 || s < 1) return 0;
+  return power_ws_bytes(L, I, R, s);
+}
+
+int tucker_rand_power(int dtype, const void* X, int64_t L, int64_t I, int64_t R,
+                      const double* colweight, int32_t q, const double* G, int64_t s, double* C,
+                      void* workspace, size_t workspace_bytes, void* stream) {
+  if ((dtype != TR_F64 && dtype != TR_F32) || !X || !G || !C || L < 1 || I < 1 || R < 1 ||
+      s < 1 || q < 1)
+    return TR_EINVAL;
+  if (s > 64) return TR_ENOTSUP;
+  if (!workspace || workspace_bytes < power_ws_bytes(L, I, R, s)) return TR_ENOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t J = L * R;
+  char* ws = (char*)workspace;
+  double* Z = (double*)ws;
+  double* part = (double*)(ws + align_up(8 * (size_t)(J * s)));
+  double* Yt = (double*)(ws + align_up(8 * (size_t)(J * s)) +
+                         align_up(8 * (size_t)(gram_parts(J) * I * s)));
+  hipLaunchKernelGGL(trk::k_transpose, dim3((unsigned)cdiv(I * s, kNT)), dim3(kNT), 0, st, G, I,
+                     s, Yt);
+  TR_TRY(check_launch());
+  return run_power(dtype == TR_F64, X, L, I, R, colweight, q, s, C, Yt, Z, part, nullptr, st);
+}
+
+int tucker_rand_factor(const double* C, int64_t I, int64_t s, int64_t mu, double* Q,
+                       double* sigma, void* stream) {
+  if (!C || !Q || I < 1 || s < 1 || s > I || mu < 1 || mu > s) return TR_EINVAL;
+  return launch_factor(C, I, s, mu, Q, nullptr, sigma, nullptr, 0, nullptr, (hipStream_t)stream);
+}
+
+int tucker_rand_ttm(int in_dtype, const void* X, int64_t L, int64_t I, int64_t R,
+                    const double* Q, int64_t mu, double* Qt, int out_dtype, void* Y,
+                    void* stream) {
+  if ((in_dtype != TR_F64 && in_dtype != TR_F32) || (out_dtype != TR_F64 && out_dtype != TR_F32))
+    return TR_EINVAL;
+  if (!X || !Q || !Qt || !Y || L < 1 || I < 1 || R < 1 || mu < 1) return TR_EINVAL;
+  if (mu > 64) return TR_ENOTSUP;
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(trk::k_transpose, dim3((unsigned)cdiv(I * mu, kNT)), dim3(kNT), 0, st, Q, I,
+                     mu, Qt);
+  TR_TRY(check_launch());
+  return launch_ttm(in_dtype == TR_F64, X, L, I, R, Qt, mu, nullptr, out_dtype == TR_F64, Y, st);
+}
+
+int tucker_rand_timer_create(int capacity, uint32_t class_mask, tr_timer** out) {
+  if (!out || capacity < 1) return TR_EINVAL;
+  tr_timer* t = new (std::nothrow) tr_timer();
+  if (!t) return TR_EINVAL;
+  t->mask = class_mask;
+  t->pool.resize(2 * (size_t)capacity);
+  for (auto& e : t->pool) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      delete t;
+      return TR_EDEVICE;
+    }
+  }
+  *out = t;
+  return TR_OK;
+}
+
+int tucker_rand_timer_destroy(tr_timer* t) {
+  if (!t) return TR_EINVAL;
+  for (auto& e : t->pool) (void)hipEventDestroy(e);
+  delete t;
+  return TR_OK;
+}
+
+int tucker_rand_timer_reset(tr_timer* t) {
+  if (!t) return TR_EINVAL;
+  t->used.clear();
+  return TR_OK;
+}
+
+int tucker_rand_timer_read(tr_timer* t, int kernel_class, double* total_ms, int64_t* launches,
+                           double* mode0_ms, int64_t* mode0_launches) {
+  if (!t || kernel_class < 0 || kernel_class >= TR_KC_COUNT) return TR_EINVAL;
+  double tot = 0.0, tot0 = 0.0;
+  int64_t cnt = 0, cnt0 = 0;
+  for (const auto& u : t->used) {
+    if (u.cls != kernel_class) continue;
+    if (hipEventSynchronize(u.stop) != hipSuccess) return TR_EDEVICE;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, u.start, u.stop) != hipSuccess) return TR_EDEVICE;
+    tot += ms;
+    ++cnt;
+    if (u.mode == 0) {
+      tot0 += ms;
+      ++cnt0;
+    }
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = cnt;
+  if (mode0_ms) *mode0_ms = tot0;
+  if (mode0_launches) *mode0_launches = cnt0;
+  return TR_OK;
+}
+
+}  // extern "C"

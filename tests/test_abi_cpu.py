@@ -1,0 +1,96 @@
+"""Host-only checks of the C ABI (no device work): the library loads, exports
+every function include/tucker_rand.h declares, and validates arguments the
+way the header documents (workspace sizing runs the same validation as the
+drivers, without launching anything)."""
+import ctypes
+
+import pytest
+import torch
+
+import paper_2303_11612_amd as tr
+from paper_2303_11612_amd import _abi
+
+
+def test_library_exports_every_header_symbol():
+    L = _abi.lib()
+    syms = _abi.header_symbols()
+    assert "tucker_rand_thosvd" in syms and "tucker_rand_sthosvd" in syms
+    assert "tucker_rand_sample" in syms and "tucker_rand_workspace_size" in syms
+    missing = [s for s in syms if not hasattr(L, s)]
+    assert missing == []
+    assert set(_abi._SIGS) == set(syms)
+
+
+def test_status_strings():
+    assert tr.tucker_rand_status_string(0) == "ok"
+    assert "invalid" in tr.tucker_rand_status_string(1)
+    assert "workspace" in tr.tucker_rand_status_string(2)
+    assert tr.tucker_rand_status_string(99) == "unknown status"
+
+
+def _ws(*a, **k):
+    return tr.tucker_rand_workspace_size(*a, **k)
+
+
+def test_workspace_sizes_grow_with_problem():
+    a = _ws((64, 64, 64), (5, 5, 5), 5, 1, dtype=torch.float64, sthosvd=False)
+    b = _ws((128, 64, 64), (5, 5, 5), 5, 1, dtype=torch.float64, sthosvd=False)
+    assert 0 < a < b
+    c = _ws((400, 400, 400), (10, 10, 10), 10, 1, "nearly_optimal", (4000,) * 3)
+    # norms, weights and prefix sums of 160000 columns plus two shrunk tensors
+    assert c >= 3 * 8 * 160000 + 2 * 8 * 10 * 400 * 400
+
+
+@pytest.mark.parametrize("bad", [
+    dict(dims=(4, 4, 4), ranks=(5, 2, 2)),            # mu > I
+    dict(dims=(4, 4, 4), ranks=(0, 2, 2)),            # mu < 1
+    dict(dims=(4, 4, 4), ranks=(2, 2)),               # wrong length
+    dict(dims=(4, 4, 4), ranks=(2, 2, 2), power=0),   # q < 1
+    dict(dims=(4, 4, 4), ranks=(2, 2, 2), oversample=-1),
+    dict(dims=(4, 4, 4), ranks=(2, 2, 2), prob="uniform", samples=(0, 1, 1)),
+    dict(dims=(0, 4, 4), ranks=(1, 2, 2)),
+])
+def test_invalid_arguments_rejected(bad):
+    kw = dict(oversample=2, power=1, prob="none", samples=None)
+    kw.update({k: v for k, v in bad.items() if k not in ("dims", "ranks")})
+    with pytest.raises((_abi.TuckerRandError, ValueError)) as e:
+        _ws(bad["dims"], bad["ranks"], **kw)
+    if isinstance(e.value, _abi.TuckerRandError):
+        assert e.value.code == _abi.TR_EINVAL
+
+
+def test_sthosvd_rank_checked_against_shrunk_unfolding():
+    # mode 3 of the shrunk 1 x 1 x 9 tensor has J_3 = 1 < mu_3 = 2
+    _ws((6, 6, 9), (1, 1, 1), 2, 1)
+    with pytest.raises(_abi.TuckerRandError):
+        _ws((6, 6, 9), (1, 1, 2), 2, 1, sthosvd=True)
+    _ws((6, 6, 9), (1, 1, 2), 2, 1, sthosvd=False)   # T-HOSVD: J_3 = 36
+
+
+def test_unsupported_requests():
+    with pytest.raises(_abi.TuckerRandError) as e:
+        _ws((200, 200, 200), (60, 10, 10), 10, 1)        # s = 70 > 64
+    assert e.value.code == _abi.TR_ENOTSUP
+    with pytest.raises(_abi.TuckerRandError) as e:
+        _ws((20, 20, 20), (4, 4, 4), 4, 1, precision="bf16")
+    assert e.value.code == _abi.TR_ENOTSUP
+
+
+def test_null_pointers_rejected_before_launch():
+    L = _abi.lib()
+    assert L.tucker_rand_workspace_size(None, 0, 0, None) == _abi.TR_EINVAL
+    assert L.tucker_rand_gaussian(4, 2, 0, 0, None, None) == _abi.TR_EINVAL
+    assert L.tucker_rand_factor(None, 4, 2, 1, None, None, None) == _abi.TR_EINVAL
+    assert L.tucker_rand_sample(None, 10, 5, 1, 0, 0, None, None, None, 0, None, None) == \
+        _abi.TR_EINVAL
+    p, keep = tr._params((8, 8), (2, 2), 2, 1, "none", None, 0, "native")
+    q = (ctypes.c_void_p * 2)(None, None)
+    rc = L.tucker_rand_thosvd(ctypes.byref(p), 0, None, q, None, None, 0, None, None)
+    assert rc == _abi.TR_EINVAL
+    assert L.tucker_rand_timer_read(None, 0, None, None, None, None) == _abi.TR_EINVAL
+
+
+def test_binding_refuses_host_tensors():
+    A = torch.zeros(4, 4, 4, dtype=torch.float64)
+    with pytest.raises(ValueError):
+        tr.tucker_rand_thosvd(A, (2, 2, 2), 1, 1)
