@@ -196,9 +196,10 @@ int tucker_rand_gather(int dtype, const void *X, int64_t L, int64_t I,
                        int64_t R, const int64_t *idx, int64_t T, void *Cp,
                        void *stream);
 
-/* Device workspace bytes needed by tucker_rand_power for these sizes. */
-size_t tucker_rand_power_workspace_size(int64_t L, int64_t I, int64_t R,
-                                        int64_t s);
+/* Device workspace bytes needed by tucker_rand_power for these sizes
+ * (0 for invalid sizes). */
+size_t tucker_rand_power_workspace_size(int dtype, int64_t L, int64_t I,
+                                        int64_t R, int64_t s);
 
 /*
  * Power-scheme products (Alg. 1 step 4 by Strategy A of the Remark after
@@ -214,28 +215,40 @@ int tucker_rand_power(int dtype, const void *X, int64_t L, int64_t I,
                       size_t workspace_bytes, void *stream);
 
 /*
+/* Device workspace bytes needed by tucker_rand_factor (0 when the working
+ * matrices fit in the workgroup's LDS). */
+size_t tucker_rand_factor_workspace_size(int64_t I, int64_t s, int64_t mu);
+
+/*
  * Factor of a sketch (Remark after Alg. 5): Q = the mu leading left singular
- * vectors of C (device float64 I x s, 1 <= mu <= s <= I), each column's
- * largest-magnitude entry made positive (lowest row on ties).  Computed with
- * a Householder QR C = P R, a one-sided Jacobi SVD of R and Q = P U_R(:, 1:mu),
- * all in float64 on one workgroup.  Q: device float64 I x mu; sigma: device
- * float64 [s] singular values in descending order (may be NULL).
- * Supported sizes: s <= 64 and I*s <= 32768 (TR_ENOTSUP otherwise).
+ * vectors of C (device float64 I x s, 1 <= mu <= s <= I, s <= 64), each
+ * column's largest-magnitude entry made positive (lowest row on ties).
+ * Computed on one workgroup in float64: Householder QR C = Q1 R1, a QR of
+ * R1^T = Q2 R2, one-sided Jacobi on the columns of R2^T (whose rotated,
+ * normalised columns are the left singular vectors U of R1), and
+ * Q = Q1 U(:, 1:mu).  Q: device float64 I x mu; sigma: device float64 [s]
+ * singular values in descending order (may be NULL).
  */
 int tucker_rand_factor(const double *C, int64_t I, int64_t s, int64_t mu,
-                       double *Q, double *sigma, void *stream);
+                       double *Q, double *sigma, void *workspace,
+                       size_t workspace_bytes, void *stream);
+
+/* Device workspace bytes needed by tucker_rand_ttm (0 for invalid sizes). */
+size_t tucker_rand_ttm_workspace_size(int64_t L, int64_t I, int64_t R,
+                                      int64_t mu);
 
 /*
  * Mode-n product Y = X x_n Q^T (Section 2): for the L x I x R view of X
- * (device, in_dtype) and Q (device float64 I x mu), Y is L x mu x R (device,
- * out_dtype) with Y(l, k, r) = sum_i Q(i, k) X(l, i, r), float64 accumulation.
- * This is the ST-HOSVD shrink (Alg. 2 step 6) and each link of the T-HOSVD
- * core chain.  Q is transposed into Qt (device float64 mu*I, row i holds Q(i,:))
- * first; Qt must be provided by the caller as scratch.
+ * (device, in_dtype) and Q (device float64 I x mu, mu <= 64), Y is
+ * L x mu x R (device, out_dtype) with Y(l, k, r) = sum_i Q(i, k) X(l, i, r),
+ * float64 accumulation.  This is the ST-HOSVD shrink (Alg. 2 step 6) and each
+ * link of the T-HOSVD core chain.  workspace: device scratch of
+ * tucker_rand_ttm_workspace_size bytes (Q^T rows and a float64 result).
  */
 int tucker_rand_ttm(int in_dtype, const void *X, int64_t L, int64_t I,
-                    int64_t R, const double *Q, int64_t mu, double *Qt,
-                    int out_dtype, void *Y, void *stream);
+                    int64_t R, const double *Q, int64_t mu, int out_dtype,
+                    void *Y, void *workspace, size_t workspace_bytes,
+                    void *stream);
 
 /* ---------------------------------------------------------------------------
  * Kernel timing (benchmarking aid).  A timer owns a pool of HIP events; when it

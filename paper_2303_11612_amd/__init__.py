@@ -298,7 +298,7 @@ def tucker_rand_power(X: torch.Tensor, L: int, I: int, R: int, G: torch.Tensor, 
         raise ValueError("G must be column-major float64")
     s = G.shape[1]
     C = colmajor_empty((I, s), torch.float64, X.device)
-    wsn = lib().tucker_rand_power_workspace_size(L, I, R, s)
+    wsn = lib().tucker_rand_power_workspace_size(_dtype_code(X), L, I, R, s)
     ws = torch.empty(max(1, wsn), dtype=torch.uint8, device=X.device)
     check("tucker_rand_power",
           lib().tucker_rand_power(_dtype_code(X), c_void_p(X.data_ptr()), L, I, R,
@@ -315,9 +315,12 @@ def tucker_rand_factor(C: torch.Tensor, mu: int, stream=None):
     I, s = C.shape
     Q = colmajor_empty((I, mu), torch.float64, C.device)
     sig = torch.empty(s, dtype=torch.float64, device=C.device)
+    wsn = lib().tucker_rand_factor_workspace_size(I, s, mu)
+    ws = torch.empty(max(1, wsn), dtype=torch.uint8, device=C.device)
     check("tucker_rand_factor",
           lib().tucker_rand_factor(c_void_p(C.data_ptr()), I, s, mu, c_void_p(Q.data_ptr()),
-                                   c_void_p(sig.data_ptr()), _stream(stream)))
+                                   c_void_p(sig.data_ptr()), c_void_p(ws.data_ptr()),
+                                   c_size_t(ws.numel()), _stream(stream)))
     return Q, sig
 
 
@@ -328,10 +331,12 @@ def tucker_rand_ttm(X: torch.Tensor, L: int, I: int, R: int, Q: torch.Tensor,
     if not is_colmajor(Q) or Q.dtype != torch.float64:
         raise ValueError("Q must be column-major float64")
     mu = Q.shape[1]
-    Qt = torch.empty(I * mu, dtype=torch.float64, device=X.device)
+    wsn = lib().tucker_rand_ttm_workspace_size(L, I, R, mu)
+    ws = torch.empty(max(1, wsn), dtype=torch.uint8, device=X.device)
     Y = torch.empty(L * mu * R, dtype=out_dtype, device=X.device)
     check("tucker_rand_ttm",
           lib().tucker_rand_ttm(_dtype_code(X), c_void_p(X.data_ptr()), L, I, R,
-                                c_void_p(Q.data_ptr()), mu, c_void_p(Qt.data_ptr()),
-                                _DT[out_dtype], c_void_p(Y.data_ptr()), _stream(stream)))
+                                c_void_p(Q.data_ptr()), mu, _DT[out_dtype],
+                                c_void_p(Y.data_ptr()), c_void_p(ws.data_ptr()),
+                                c_size_t(ws.numel()), _stream(stream)))
     return Y

@@ -54,13 +54,15 @@ _SIGS = {
                                    c_void_p, c_void_p, c_void_p, c_size_t, c_void_p, c_void_p]),
     "tucker_rand_gather": (c_int, [c_int, c_void_p, c_int64, c_int64, c_int64, c_void_p,
                                    c_int64, c_void_p, c_void_p]),
-    "tucker_rand_power_workspace_size": (c_size_t, [c_int64, c_int64, c_int64, c_int64]),
+    "tucker_rand_power_workspace_size": (c_size_t, [c_int, c_int64, c_int64, c_int64, c_int64]),
     "tucker_rand_power": (c_int, [c_int, c_void_p, c_int64, c_int64, c_int64, c_void_p, c_int32,
                                   c_void_p, c_int64, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "tucker_rand_factor_workspace_size": (c_size_t, [c_int64, c_int64, c_int64]),
     "tucker_rand_factor": (c_int, [c_void_p, c_int64, c_int64, c_int64, c_void_p, c_void_p,
-                                   c_void_p]),
+                                   c_void_p, c_size_t, c_void_p]),
+    "tucker_rand_ttm_workspace_size": (c_size_t, [c_int64, c_int64, c_int64, c_int64]),
     "tucker_rand_ttm": (c_int, [c_int, c_void_p, c_int64, c_int64, c_int64, c_void_p, c_int64,
-                                c_void_p, c_int, c_void_p, c_void_p]),
+                                c_int, c_void_p, c_void_p, c_size_t, c_void_p]),
     "tucker_rand_timer_create": (c_int, [c_int, c_uint32, POINTER(c_void_p)]),
     "tucker_rand_timer_destroy": (c_int, [c_void_p]),
     "tucker_rand_timer_reset": (c_int, [c_void_p]),

@@ -52,10 +52,43 @@ constexpr uint64_t kTagSample = 1;
 // Reductions.  All combine in a fixed pattern, so results are bitwise
 // reproducible run to run.
 // ---------------------------------------------------------------------------
+
+// Lane permutations through DPP (no LDS round trip).  A double moves as two
+// 32-bit halves with the same control word.
+template <int CTRL, int ROW_MASK = 0xf, bool BOUND_CTRL = false>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, ROW_MASK, 0xf,
+                                             BOUND_CTRL);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, BOUND_CTRL);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// DPP control words (GFX9 encoding).
+constexpr int kDppQuadXor1 = 0xb1;      // quad_perm [1,0,3,2]
+constexpr int kDppQuadXor2 = 0x4e;      // quad_perm [2,3,0,1]
+constexpr int kDppRowHalfMirror = 0x141;
+constexpr int kDppRowMirror = 0x140;
+constexpr int kDppRowBcast15 = 0x142;
+constexpr int kDppRowBcast31 = 0x143;
+
+// Sum over the 64 lanes; every lane gets the total.  Quad, half-row and row
+// stages by DPP, the two cross-row stages by row broadcasts, then the total
+// (complete in lane 63) is read back to all lanes.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int m = 1; m < kWave; m <<= 1) v += __shfl_xor(v, m, kWave);
-  return v;
+  v += dpp_f64<kDppQuadXor1>(v);
+  v += dpp_f64<kDppQuadXor2>(v);
+  v += dpp_f64<kDppRowHalfMirror>(v);
+  v += dpp_f64<kDppRowMirror>(v);
+  // rows 1 and 3 add lane 15 of rows 0 and 2; rows 2 and 3 then add lane 31
+  const double b15 = dpp_f64<kDppRowBcast15, 0xa>(v);
+  v += ((threadIdx.x >> 4) & 1) ? b15 : 0.0;
+  const double b31 = dpp_f64<kDppRowBcast31, 0xc>(v);
+  v += ((threadIdx.x >> 5) & 1) ? b31 : 0.0;
+  const long long t = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(t & 0xffffffff), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(t >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
 __device__ __forceinline__ double wave_max(double v) {
@@ -82,7 +115,8 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
 
 // Transpose-reduce of M values (M a power of two <= 64) across one wave: on
 // return lane l holds the wave-wide sum of value index wave_vec_index<M>(l).
-// Uses M-1 + (6 - log2 M) shuffles instead of 6*M.
+// Uses M-1 + (6 - log2 M) shuffles instead of 6*M.  Every index is a
+// compile-time constant (the halving stages are unrolled by recursion).
 template <int M>
 __device__ __forceinline__ int wave_vec_index(int lane) {
   int idx = 0;
@@ -93,21 +127,24 @@ __device__ __forceinline__ int wave_vec_index(int lane) {
   return idx;
 }
 
+template <int M, int HALF, int B>
+__device__ __forceinline__ void wave_vec_stage(double (&v)[M], int lane) {
+  if constexpr (HALF >= 1) {
+    const bool up = ((lane >> B) & 1) != 0;
+#pragma unroll
+    for (int q = 0; q < HALF; ++q) {
+      const double send = up ? v[q] : v[q + HALF];
+      const double keep = up ? v[q + HALF] : v[q];
+      v[q] = keep + __shfl_xor(send, 1 << B, kWave);
+    }
+    wave_vec_stage<M, HALF / 2, B + 1>(v, lane);
+  }
+}
+
 template <int M>
 __device__ __forceinline__ double wave_vec_sum(double (&v)[M], int lane) {
   static_assert(M >= 1 && M <= kWave && (M & (M - 1)) == 0, "M power of 2");
-  int b = 0;
-#pragma unroll
-  for (int half = M / 2; half >= 1; half /= 2, ++b) {
-    const int mask = 1 << b;
-    const bool up = (lane & mask) != 0;
-#pragma unroll
-    for (int q = 0; q < half; ++q) {
-      const double send = up ? v[q] : v[q + half];
-      const double keep = up ? v[q + half] : v[q];
-      v[q] = keep + __shfl_xor(send, mask, kWave);
-    }
-  }
+  wave_vec_stage<M, M / 2, 0>(v, lane);
   double r = v[0];
 #pragma unroll
   for (int mask = M; mask < kWave; mask <<= 1) r += __shfl_xor(r, mask, kWave);

@@ -36,7 +36,7 @@ struct RowsPerChunk {
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kNT)
 k_gaussian(double* __restrict__ G, double* __restrict__ Gt, int64_t I, int64_t s,
-           uint64_t mode, uint64_t seed) {
+           int64_t ldgt, uint64_t mode, uint64_t seed) {
   const int64_t total = I * s;
   const int64_t b = (int64_t)blockIdx.x * kNT + threadIdx.x;
   if (4 * b >= total) return;
@@ -56,7 +56,7 @@ k_gaussian(double* __restrict__ G, double* __restrict__ Gt, int64_t I, int64_t s
         G[e] = z[h];
         if (Gt) {
           const int64_t i = e % I, c = e / I;
-          Gt[i * s + c] = z[h];
+          Gt[i * ldgt + c] = z[h];
         }
       }
     }
@@ -91,6 +91,29 @@ __device__ __forceinline__ void block_max_bits(double v, unsigned long long* out
   }
 }
 
+// Stages rows [i0, i0 + TI) of the kNT consecutive columns starting at `base`
+// (an L == 1 view: column c is contiguous, length I) into tile[ii][c].  All
+// TI loads of a thread are issued before any is consumed (out-of-range
+// elements read a clamped in-range address and are not stored).
+template <typename T, int TI>
+__device__ __forceinline__ void stage_fiber_chunk(const T* __restrict__ base, int64_t I,
+                                                  int64_t i0, int ncol, T (*tile)[kNT + 1]) {
+  T v[TI];
+  bool ok[TI];
+#pragma unroll
+  for (int m = 0; m < TI; ++m) {
+    const int e = threadIdx.x + kNT * m;
+    const int cc = e / TI, ii = e % TI;
+    ok[m] = cc < ncol && i0 + ii < I;
+    v[m] = base[ok[m] ? (int64_t)cc * I + i0 + ii : 0];
+  }
+#pragma unroll
+  for (int m = 0; m < TI; ++m) {
+    const int e = threadIdx.x + kNT * m;
+    if (ok[m]) tile[e % TI][e / TI] = v[m];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // K3  Column norms n_j = ||A_(n)(:, j)||^2, rows summed in increasing order.
 // ---------------------------------------------------------------------------
@@ -107,12 +130,7 @@ k_colnorms_l1(const T* __restrict__ X, int64_t I, int64_t J,
   const T* base = X + j0 * I;
   double acc = 0.0;
   for (int64_t i0 = 0; i0 < I; i0 += TI) {
-#pragma unroll
-    for (int m = 0; m < TI; ++m) {
-      const int e = c + kNT * m;
-      const int cc = e / TI, ii = e % TI;
-      if (cc < ncol && i0 + ii < I) tile[ii][cc] = base[(int64_t)cc * I + i0 + ii];
-    }
+    stage_fiber_chunk<T, TI>(base, I, i0, ncol, tile);
     __syncthreads();
     const int ti = (int)min((int64_t)TI, I - i0);
     if (c < ncol)
@@ -134,7 +152,15 @@ k_colnorms_ln(const T* __restrict__ X, int64_t L, int64_t I, int64_t R,
   if (j < J) {
     const int64_t r = j / L, l = j - r * L;
     const T* p = X + l + L * I * r;
-    for (int64_t i = 0; i < I; ++i) acc = sq_add(acc, (double)p[L * i]);
+    constexpr int B = 16;  // loads in flight per thread; the sum stays in row order
+    for (int64_t i0 = 0; i0 < I; i0 += B) {
+      T v[B];
+#pragma unroll
+      for (int b = 0; b < B; ++b) v[b] = p[L * min(i0 + b, I - 1)];
+#pragma unroll
+      for (int b = 0; b < B; ++b)
+        if (i0 + b < I) acc = sq_add(acc, (double)v[b]);
+    }
     norms[j] = acc;
   }
   if (max_bits) block_max_bits(acc, max_bits, scr);
@@ -335,14 +361,17 @@ k_gather(const T* __restrict__ X, int64_t L, int64_t I, const int64_t* __restric
 }
 
 // ---------------------------------------------------------------------------
-// K9 (and the first half of each power step)  Y = X x_n Q^T, column-streaming:
-// Y(l, k, r) = colscale_j * sum_i Qt[i*mu + k] X(l, i, r), float64 accumulation.
-// MU is a compile-time bound on mu (accumulators live in registers).
+// K9 (and the first half of a power step on an L > 1 view)  Y = X x_n Q^T,
+// column-streaming: Y(l, k, r) = colscale_j * sum_i Qt[i*MU + k] X(l, i, r),
+// float64 accumulation.  Qt rows are padded to the compile-time stride MU with
+// zeros, so each row is one batched scalar load and the inner loop has no
+// branches.  Outputs k < kout are written with row stride kout (kout = mu for
+// a mode product; kout = MU keeps the zero padding for the power steps).
 // ---------------------------------------------------------------------------
-template <typename Tin, typename Tout, int MU>
+template <typename Tin, int MU>
 __global__ void __launch_bounds__(kNT)
 k_ttm_l1(const Tin* __restrict__ X, int64_t I, int64_t R, const double* __restrict__ Qt,
-         int mu, const double* __restrict__ colscale, Tout* __restrict__ Y) {
+         int kout, const double* __restrict__ colscale, double* __restrict__ Y) {
   constexpr int TI = RowsPerChunk<Tin>::value;
   __shared__ Tin tile[TI][kNT + 1];
   const int c = threadIdx.x;
@@ -353,20 +382,14 @@ k_ttm_l1(const Tin* __restrict__ X, int64_t I, int64_t R, const double* __restri
 #pragma unroll
   for (int k = 0; k < MU; ++k) acc[k] = 0.0;
   for (int64_t i0 = 0; i0 < I; i0 += TI) {
-#pragma unroll
-    for (int m = 0; m < TI; ++m) {
-      const int e = c + kNT * m;
-      const int cc = e / TI, ii = e % TI;
-      if (cc < ncol && i0 + ii < I) tile[ii][cc] = base[(int64_t)cc * I + i0 + ii];
-    }
+    stage_fiber_chunk<Tin, TI>(base, I, i0, ncol, tile);
     __syncthreads();
     const int ti = (int)min((int64_t)TI, I - i0);
     for (int ii = 0; ii < ti; ++ii) {
       const double x = (double)tile[ii][c];
-      const double* q = Qt + (i0 + ii) * mu;
+      const double* q = Qt + (i0 + ii) * MU;
 #pragma unroll
-      for (int k = 0; k < MU; ++k)
-        if (k < mu) acc[k] = fma(q[k], x, acc[k]);
+      for (int k = 0; k < MU; ++k) acc[k] = fma(q[k], x, acc[k]);
     }
     __syncthreads();
   }
@@ -375,15 +398,15 @@ k_ttm_l1(const Tin* __restrict__ X, int64_t I, int64_t R, const double* __restri
     const double d = colscale ? colscale[j] : 1.0;
 #pragma unroll
     for (int k = 0; k < MU; ++k)
-      if (k < mu) Y[k + (int64_t)mu * j] = (Tout)(acc[k] * d);
+      if (k < kout) Y[k + (int64_t)kout * j] = acc[k] * d;
   }
 }
 
-template <typename Tin, typename Tout, int MU>
+template <typename Tin, int MU>
 __global__ void __launch_bounds__(kNT)
 k_ttm_ln(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
-         const double* __restrict__ Qt, int mu, const double* __restrict__ colscale,
-         Tout* __restrict__ Y) {
+         const double* __restrict__ Qt, int kout, const double* __restrict__ colscale,
+         double* __restrict__ Y) {
   const int64_t J = L * R;
   const int64_t j = (int64_t)blockIdx.x * kNT + threadIdx.x;
   const bool act = j < J;
@@ -393,55 +416,98 @@ k_ttm_ln(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
   double acc[MU];
 #pragma unroll
   for (int k = 0; k < MU; ++k) acc[k] = 0.0;
-  for (int64_t i = 0; i < I; ++i) {
-    const double x = act ? (double)p[L * i] : 0.0;
-    const double* q = Qt + i * mu;
+  constexpr int B = 8;  // loads in flight per thread
+  for (int64_t i0 = 0; i0 < I; i0 += B) {
+    Tin v[B];
 #pragma unroll
-    for (int k = 0; k < MU; ++k)
-      if (k < mu) acc[k] = fma(q[k], x, acc[k]);
+    for (int b = 0; b < B; ++b) v[b] = p[L * min(i0 + b, I - 1)];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      if (i0 + b < I) {
+        const double x = act ? (double)v[b] : 0.0;
+        const double* q = Qt + (i0 + b) * MU;
+#pragma unroll
+        for (int k = 0; k < MU; ++k) acc[k] = fma(q[k], x, acc[k]);
+      }
+    }
   }
   if (act) {
     const double d = colscale ? colscale[j] : 1.0;
 #pragma unroll
     for (int k = 0; k < MU; ++k)
-      if (k < mu) Y[l + L * (k + (int64_t)mu * r)] = (Tout)(acc[k] * d);
+      if (k < kout) Y[l + L * (k + (int64_t)kout * r)] = acc[k] * d;
   }
 }
 
-// ---------------------------------------------------------------------------
-// Second half of a power step, row-streaming: part_b(i, k) = sum over the
-// columns j of block b of X(i, j) Z(j, k), where Z is the L x s x R output of
-// the first half (Z(j, k) at l + L*(k + s*r)).  Partials are reduced in a
-// fixed order by k_reduce_parts, so the result is reproducible.
-// ---------------------------------------------------------------------------
-template <typename Tin, int SM>
+// Mode product for views with few columns: block (x, y) covers kNT columns
+// and the rows [y*ich, (y+1)*ich); partial sums over its rows go to
+// part[y][j*MU + k] and are added in increasing y by k_sum_splits.
+template <typename Tin, int MU>
 __global__ void __launch_bounds__(kNT)
-k_gramb_l1(const Tin* __restrict__ X, int64_t I, int64_t R, const double* __restrict__ Z,
-           int s, int64_t chunk, double* __restrict__ part) {
-  const int64_t r0 = (int64_t)blockIdx.x * chunk;
-  const int64_t r1 = min(R, r0 + chunk);
-  double* out = part + (int64_t)blockIdx.x * I * s;
-  for (int64_t ib = 0; ib < I; ib += kNT) {
-    const int64_t i = ib + threadIdx.x;
-    const bool act = i < I;
-    double acc[SM];
+k_ttm_split(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
+            const double* __restrict__ Qt, int64_t ich, double* __restrict__ part) {
+  const int64_t J = L * R;
+  const int64_t j = (int64_t)blockIdx.x * kNT + threadIdx.x;
+  const bool act = j < J;
+  const int64_t jj = act ? j : 0;
+  const int64_t r = jj / L, l = jj - r * L;
+  const Tin* p = X + l + L * I * r;
+  const int64_t ia = (int64_t)blockIdx.y * ich, ib = min(I, ia + ich);
+  double acc[MU];
 #pragma unroll
-    for (int k = 0; k < SM; ++k) acc[k] = 0.0;
-    for (int64_t r = r0; r < r1; ++r) {
-      const double x = act ? (double)X[i + I * r] : 0.0;
-      const double* z = Z + (int64_t)s * r;
+  for (int k = 0; k < MU; ++k) acc[k] = 0.0;
+  constexpr int B = 8;
+  for (int64_t i0 = ia; i0 < ib; i0 += B) {
+    Tin v[B];
 #pragma unroll
-      for (int k = 0; k < SM; ++k)
-        if (k < s) acc[k] = fma(x, z[k], acc[k]);
+    for (int b = 0; b < B; ++b) v[b] = p[L * min(i0 + b, ib - 1)];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      if (i0 + b < ib) {
+        const double x = act ? (double)v[b] : 0.0;
+        const double* q = Qt + (i0 + b) * MU;
+#pragma unroll
+        for (int k = 0; k < MU; ++k) acc[k] = fma(q[k], x, acc[k]);
+      }
     }
-    if (act) {
+  }
+  if (act) {
+    double* out = part + ((int64_t)blockIdx.y * J + j) * MU;
 #pragma unroll
-      for (int k = 0; k < SM; ++k)
-        if (k < s) out[i + I * k] = acc[k];
-    }
+    for (int k = 0; k < MU; ++k) out[k] = acc[k];
   }
 }
 
+// Y(l, k, r) = colscale_j * sum_y part[y][j*MU + k] for k < kout, row stride kout.
+__global__ void __launch_bounds__(kNT)
+k_sum_splits(const double* __restrict__ part, int64_t nsplit, int64_t L, int64_t R, int MU,
+             int kout, const double* __restrict__ colscale, double* __restrict__ Y) {
+  const int64_t J = L * R;
+  const int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x;
+  if (e >= J * kout) return;
+  const int64_t j = e / kout, k = e - j * kout;
+  double acc = 0.0;
+  constexpr int B = 8;
+  for (int64_t y0 = 0; y0 < nsplit; y0 += B) {
+    double v[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) v[u] = part[(min(y0 + u, nsplit - 1) * J + j) * MU + k];
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+      if (y0 + u < nsplit) acc += v[u];
+  }
+  if (colscale) acc *= colscale[j];
+  const int64_t r = j / L, l = j - r * L;
+  Y[l + L * (k + (int64_t)kout * r)] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Second half of a power step on an L > 1 view, row-streaming:
+// part_b(i, k) = sum over the columns j of block b of X(i, j) Z(j, k), with Z
+// the L x SM x R output of k_ttm_ln (zero-padded to SM).  A workgroup stages
+// 32 consecutive l of 256 rows through LDS.  Partials are summed in a fixed
+// order by k_reduce_parts.
+// ---------------------------------------------------------------------------
 template <typename Tin, int SM>
 __global__ void __launch_bounds__(kNT)
 k_gramb_ln(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
@@ -460,19 +526,28 @@ k_gramb_ln(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
     for (int64_t j = ja; j < jb;) {
       const int64_t r = j / L, l0 = j - r * L;
       const int tl = (int)min((int64_t)TL, min(L - l0, jb - j));
+      {
+        Tin v[TL];
+        bool ok[TL];
 #pragma unroll
-      for (int m = 0; m < TL; ++m) {
-        const int e = threadIdx.x + kNT * m;
-        const int ll = e % TL, ii = e / TL;
-        if (ll < tl && ib + ii < I) tile[ll][ii] = X[l0 + ll + L * (ib + ii + I * r)];
+        for (int m = 0; m < TL; ++m) {
+          const int e = threadIdx.x + kNT * m;
+          const int ll = e % TL, ii = e / TL;
+          ok[m] = ll < tl && ib + ii < I;
+          v[m] = X[ok[m] ? l0 + ll + L * (ib + ii + I * r) : 0];
+        }
+#pragma unroll
+        for (int m = 0; m < TL; ++m) {
+          const int e = threadIdx.x + kNT * m;
+          if (ok[m]) tile[e % TL][e / TL] = v[m];
+        }
       }
       __syncthreads();
       for (int ll = 0; ll < tl; ++ll) {
         const double x = (double)tile[ll][threadIdx.x];
-        const double* z = Z + (l0 + ll) + L * (int64_t)s * r;
+        const double* z = Z + (l0 + ll) + L * (int64_t)SM * r;
 #pragma unroll
-        for (int k = 0; k < SM; ++k)
-          if (k < s) acc[k] = fma(x, z[L * k], acc[k]);
+        for (int k = 0; k < SM; ++k) acc[k] = fma(x, z[L * k], acc[k]);
       }
       __syncthreads();
       j += tl;
@@ -485,114 +560,250 @@ k_gramb_ln(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
   }
 }
 
-// Y(e) = sum_b part_b(e) in increasing b; also the row-major copy Yt.
+// ---------------------------------------------------------------------------
+// Both halves of a power step for an L == 1 source (the gathered C' of the
+// sampled products, or a mode-1 unfolding), fused per column tile:
+//   W_b = D_b X_b^T Y   (tile of tj columns staged in LDS, Y read row-major)
+//   part += X_b W_b     (accumulated in registers across the tiles of a block)
+// RPT rows per thread (I <= 256 * RPT), SM >= s padded; one partial per block.
+// ---------------------------------------------------------------------------
+template <typename Tin, int SM, int RPT>
 __global__ void __launch_bounds__(kNT)
-k_reduce_parts(const double* __restrict__ part, int64_t nparts, int64_t I, int s,
+k_gram_tile_l1(const Tin* __restrict__ X, int64_t I, int64_t J,
+               const double* __restrict__ colw, const double* __restrict__ Yt, int s,
+               int tj, int64_t tiles_per_block, double* __restrict__ part) {
+  extern __shared__ double gsm[];
+  double* Ys = gsm;                                     // I x SM (row-major copy of Y)
+  double* W = Ys + (size_t)I * SM;                      // tj x SM, row c at W[c*SM]
+  Tin* T = reinterpret_cast<Tin*>(W + (size_t)tj * SM); // I x tj, column-major
+  const int ldT = (int)(I | 1);  // odd column stride: phase-1 reads hit distinct banks
+  constexpr int KG = 4;                                 // outputs per phase-1 thread
+  constexpr int B = 8;                                  // loads in flight per thread
+  for (int64_t e = threadIdx.x; e < I * SM; e += kNT) Ys[e] = Yt[e];
+  double acc[RPT][SM];
+#pragma unroll
+  for (int p = 0; p < RPT; ++p)
+#pragma unroll
+    for (int k = 0; k < SM; ++k) acc[p][k] = 0.0;
+  const int64_t ntiles = (J + tj - 1) / tj;
+  const int64_t t0 = (int64_t)blockIdx.x * tiles_per_block;
+  const int64_t t1 = min(ntiles, t0 + tiles_per_block);
+  for (int64_t t = t0; t < t1; ++t) {
+    const int64_t c0 = t * tj;
+    const int nc = (int)min((int64_t)tj, J - c0);
+    const int64_t n = (int64_t)nc * I;
+    const Tin* src = X + c0 * I;                        // contiguous I*nc elements
+    for (int64_t e0 = 0; e0 < n; e0 += (int64_t)kNT * B) {
+      Tin v[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) v[u] = src[min(e0 + threadIdx.x + (int64_t)kNT * u, n - 1)];
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int64_t e = e0 + threadIdx.x + (int64_t)kNT * u;
+        if (e < n) {
+          const int c = (int)(e / I), i = (int)(e - (int64_t)c * I);
+          T[c * ldT + i] = v[u];
+        }
+      }
+    }
+    __syncthreads();
+    // phase 1: thread (c, kg) forms W(c, 4kg .. 4kg+3) = d_c sum_i T(i, c) Y(i, .)
+    for (int e = threadIdx.x; e < nc * (SM / KG); e += kNT) {
+      const int c = e % nc, kg = e / nc;
+      const Tin* tc = T + c * ldT;
+      double w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+      for (int64_t i = 0; i < I; ++i) {
+        const double x = (double)tc[i];
+        const double* y = Ys + i * SM + KG * kg;
+        w0 = fma(x, y[0], w0);
+        w1 = fma(x, y[1], w1);
+        w2 = fma(x, y[2], w2);
+        w3 = fma(x, y[3], w3);
+      }
+      const double d = colw ? colw[c0 + c] : 1.0;
+      double* wr = W + c * SM + KG * kg;
+      wr[0] = w0 * d;
+      wr[1] = w1 * d;
+      wr[2] = w2 * d;
+      wr[3] = w3 * d;
+    }
+    __syncthreads();
+    // phase 2: rows of this thread accumulate X_b W_b
+#pragma unroll
+    for (int p = 0; p < RPT; ++p) {
+      const int64_t i = threadIdx.x + (int64_t)kNT * p;
+      if (i < I) {
+        for (int c = 0; c < nc; ++c) {
+          const double x = (double)T[c * ldT + i];
+          const double* wr = W + c * SM;
+#pragma unroll
+          for (int k = 0; k < SM; ++k) acc[p][k] = fma(x, wr[k], acc[p][k]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double* out = part + (int64_t)blockIdx.x * I * s;
+#pragma unroll
+  for (int p = 0; p < RPT; ++p) {
+    const int64_t i = threadIdx.x + (int64_t)kNT * p;
+    if (i < I) {
+#pragma unroll
+      for (int k = 0; k < SM; ++k)
+        if (k < s) out[i + I * k] = acc[p][k];
+    }
+  }
+}
+
+// Y(e) = sum_b part_b(e) in increasing b; also the row-major copy Yt (stride
+// ldyt >= s; its padding columns are left untouched, i.e. zero).
+__global__ void __launch_bounds__(kNT)
+k_reduce_parts(const double* __restrict__ part, int64_t nparts, int64_t I, int s, int ldyt,
                double* __restrict__ Y, double* __restrict__ Yt, uint32_t* __restrict__ status) {
   const int64_t n = I * s;
   const int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x;
   if (e >= n) return;
   double acc = 0.0;
-  for (int64_t b = 0; b < nparts; ++b) acc += part[b * n + e];
+  constexpr int B = 16;  // loads in flight; the sum stays in increasing b
+  for (int64_t b0 = 0; b0 < nparts; b0 += B) {
+    double v[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) v[u] = part[min(b0 + u, nparts - 1) * n + e];
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+      if (b0 + u < nparts) acc += v[u];
+  }
   Y[e] = acc;
   const int64_t i = e % I, k = e / I;
-  Yt[i * s + k] = acc;
+  Yt[i * ldyt + k] = acc;
   if (!isfinite(acc) && status) atomicOr(status, kDevNonFinite);
 }
 
+__global__ void k_fill_f64(double* __restrict__ p, int64_t n, double v) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) p[e] = v;
+}
+
 // ---------------------------------------------------------------------------
-// K7 + K8  Factor of a sketch on one workgroup of 512 threads: Householder QR
-// C = P R, one-sided Jacobi SVD of R (columns rotated until orthogonal), sort,
-// P formed in place of the reflectors, Q = P U_R(:, 1:mu), canonical signs.
-// Thread t holds rows t + 512 p (p < RPT) of C in registers; SM >= s.
+// K7 + K8  Factor of a sketch C (I x s, float64) on one workgroup of 256
+// threads: Q = the mu leading left singular vectors of C.
+//   1. Householder QR  C = H_0 ... H_{s-1} [R1; 0]          (block-wide)
+//   2. QR of R1^T = Q2 R2                                    (one wave)
+//   3. one-sided Jacobi on the columns of X = R2^T           (four waves)
+//      C = Q1 R1 = Q1 X Q2^T, so the left singular vectors of C are
+//      Q1 U_X with U_X the normalised rotated columns of X; the second QR
+//      makes the Jacobi sweeps converge about twice as fast.
+//   4. sort by singular value, U = U_X(:, 1:mu)
+//   5. Q = H_0 ... H_{s-1} [U; 0]                            (block-wide)
+//   6. sign of each column: largest |entry| (lowest row on ties) positive.
+// The I x s and I x mu working matrices live in LDS, or (kGlobal) in global
+// scratch supplied by the caller when they do not fit.  Thread t owns rows
+// t + 256 m throughout, so only reductions cross threads.
 // ---------------------------------------------------------------------------
-constexpr int kFactorNT = 512;
+constexpr int kFactorNT = 256;
 
 template <int SM>
-__device__ __forceinline__ double pick(const double (&a)[SM], int k) {
-  double r = 0.0;
-#pragma unroll
-  for (int j = 0; j < SM; ++j) r = (j == k) ? a[j] : r;
-  return r;
-}
-
-template <int SM>
-__device__ __forceinline__ void put(double (&a)[SM], int k, double v) {
-#pragma unroll
-  for (int j = 0; j < SM; ++j) a[j] = (j == k) ? v : a[j];
-}
-
-// Workgroup sum of the vector part(j), j in [jlo, s), computed by `f(j)` per
-// thread; the result lands in vec[j].  Chunks of 16 values go through the
-// wave transpose-reduce.  Two barriers.
-template <int SM, typename F>
-__device__ __forceinline__ void block_vec_sum(F f, double* scr, double* vec) {
-  constexpr int NW = kFactorNT / kWave;
-  constexpr int CH = SM < 16 ? SM : 16;
-  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-#pragma unroll
-  for (int c0 = 0; c0 < SM; c0 += CH) {
-    double v[CH];
-#pragma unroll
-    for (int q = 0; q < CH; ++q) v[q] = f(c0 + q);
-    const double r = wave_vec_sum<CH>(v, lane);
-    if (lane < CH) scr[wid * SM + c0 + wave_vec_index<CH>(lane)] = r;
+struct FactorShape {
+  static constexpr int NT = kFactorNT, NW = NT / kWave, LDR = SM + 1;
+  // always-LDS part (doubles): M/X, U, scratch, vec and small vectors
+  static constexpr int kSmall = 2 * SM * LDR + NW * SM + 11 * SM + 16 + SM * SM / 2;
+  static size_t lds_bytes(int I, int s, int mu, bool global_mats) {
+    return 8 * ((global_mats ? 0 : (size_t)I * (s + mu)) + kSmall);
   }
-  __syncthreads();
-  if (threadIdx.x < SM) {
-    double t = 0.0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) t += scr[w * SM + threadIdx.x];
-    vec[threadIdx.x] = t;
-  }
-  __syncthreads();
+};
+
+__device__ __forceinline__ void lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
 }
 
-template <int RPT, int SM>
+// Circle-method pairing: at step t of a sweep over se (even) columns, pair g
+// joins positions g and se-1-g; position 0 is fixed, the others rotate.
+__device__ __forceinline__ void jacobi_pair(int g, int step, int se, int* pp, int* qq) {
+  const int x1 = se - 1 - g;
+  const int p = g == 0 ? 0 : ((g - 1 + step) % (se - 1)) + 1;
+  const int q = ((x1 - 1 + step) % (se - 1)) + 1;
+  *pp = p < q ? p : q;
+  *qq = p < q ? q : p;
+}
+
+template <int SM, bool kGlobal>
 __global__ void __launch_bounds__(kFactorNT)
 k_factor(const double* __restrict__ C, int I, int s, int mu, double* __restrict__ Q,
-         double* __restrict__ Qt, double* __restrict__ sig_out, void* __restrict__ Qcast,
-         int cast_f32, uint32_t* __restrict__ status) {
-  constexpr int NT = kFactorNT, NW = NT / kWave, LD = SM + 1;
-  __shared__ double s_scr[NW * SM];
-  __shared__ double s_vec[SM];
-  __shared__ double s_R[SM * LD];   // R, then the rotated R; column c at s_R[c*LD]
-  __shared__ double s_U[SM * LD];   // leading left singular vectors of R
-  __shared__ double s_tau[SM];
-  __shared__ double s_sig[SM];
-  __shared__ int s_perm[SM];
-  __shared__ int s_flag;
-  __shared__ double s_bval[NW * SM];
-  __shared__ double s_babs[NW * SM];
-  __shared__ int s_bidx[NW * SM];
-  __shared__ double s_sign[SM];
+         double* __restrict__ Qt, int ldqt, double* __restrict__ sig_out,
+         void* __restrict__ Qcast, int cast_f32, uint32_t* __restrict__ status,
+         double* __restrict__ gA, double* __restrict__ gZ) {
+  using F = FactorShape<SM>;
+  constexpr int NT = F::NT, NW = F::NW, LDR = F::LDR, H = SM / 2, HW = (H + NW - 1) / NW;
+  extern __shared__ double smem[];
+  double* sp = smem;
+  double* A = kGlobal ? gA : sp;                    // I x s, column-major
+  double* Z = kGlobal ? gZ : sp + (size_t)I * s;    // I x mu, column-major
+  if (!kGlobal) sp += (size_t)I * (s + mu);
+  double* M = sp;                  // R1^T, then X = R2^T (column c at M[c*LDR])
+  double* U = M + SM * LDR;        // leading left singular vectors of X
+  double* scr = U + SM * LDR;      // NW x SM reduction scratch
+  double* vec = scr + NW * SM;     // reduced vector
+  double* tau = vec + SM;
+  double* rowk = tau + SM;
+  double* vec2 = rowk + SM;        // single-wave reductions
+  double* sig = vec2 + SM;
+  double* sgn = sig + SM;
+  double* jn = sgn + SM;           // Jacobi column norms^2
+  int* perm = reinterpret_cast<int*>(jn + SM);
+  int* flag = reinterpret_cast<int*>(jn + 2 * SM);
+  // pair table of a sweep: pairs[step * (SM/2) + g] = p | q << 8
+  int* pairs = reinterpret_cast<int*>(jn + 2 * SM + 8);
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
 
-  double a[RPT][SM];
-#pragma unroll
-  for (int p = 0; p < RPT; ++p) {
-    const int i = tid + NT * p;
-#pragma unroll
-    for (int j = 0; j < SM; ++j) a[p][j] = (i < I && j < s) ? C[i + (int64_t)I * j] : 0.0;
-  }
-  for (int e = tid; e < SM * LD; e += NT) {
-    s_R[e] = 0.0;
-    s_U[e] = 0.0;
+  for (int e = tid; e < I * s; e += NT) A[e] = C[e];
+  for (int e = tid; e < SM * LDR; e += NT) {
+    M[e] = 0.0;
+    U[e] = 0.0;
   }
   __syncthreads();
 
-  // ---- Householder QR (LAPACK dgeqr2 conventions: H = I - tau v v^T) ----
-  for (int k = 0; k < s; ++k) {
-    double part = 0.0, al = 0.0;
+  // Workgroup sum of part[j] (j < SM) into vec[]; two barriers.
+  auto vec_sum = [&](double (&part)[SM]) {
+    constexpr int CH = SM < 16 ? SM : 16;
 #pragma unroll
-    for (int p = 0; p < RPT; ++p) {
-      const int i = tid + NT * p;
-      const double x = pick<SM>(a[p], k);
-      if (i > k && i < I) part += x * x;
-      if (i == k) al = x;
+    for (int c0 = 0; c0 < SM; c0 += CH) {
+      double v[CH];
+#pragma unroll
+      for (int q = 0; q < CH; ++q) v[q] = part[c0 + q];
+      const double r = wave_vec_sum<CH>(v, lane);
+      if (lane < CH) scr[wid * SM + c0 + wave_vec_index<CH>(lane)] = r;
     }
-    block_vec_sum<2>([&](int j) { return j == 0 ? part : al; }, s_scr, s_vec);
-    const double sum2 = s_vec[0], alpha = s_vec[1];
+    __syncthreads();
+    if (tid < SM) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) t += scr[w * SM + tid];
+      vec[tid] = t;
+    }
+    __syncthreads();
+  };
+
+  // ---- 1. Householder QR of C: v_k = 1, H_k = I - tau_k v v^T ----
+  for (int k = 0; k < s; ++k) {
+    const double* xk = A + (size_t)k * I;
+    const double alpha = xk[k];
+    if (tid < s) rowk[tid] = tid > k ? A[(size_t)tid * I + k] : 0.0;
+    double part[SM];
+#pragma unroll
+    for (int j = 0; j < SM; ++j) part[j] = 0.0;
+    for (int i = tid; i < I; i += NT) {
+      if (i > k) {
+        const double x = xk[i];
+        double av[SM];
+#pragma unroll
+        for (int j = 0; j < SM; ++j)  // clamped column: every load in bounds
+          av[j] = A[(size_t)min(j, s - 1) * I + i] * ((j > k && j < s) ? 1.0 : 0.0);
+#pragma unroll
+        for (int j = 0; j < SM; ++j) part[j] += (j == k ? x : av[j]) * x;
+      }
+    }
+    vec_sum(part);
+    const double sum2 = vec[k];
     double beta, tk, inv;
     if (sum2 == 0.0) {
       beta = alpha;
@@ -603,232 +814,246 @@ k_factor(const double* __restrict__ C, int I, int s, int mu, double* __restrict_
       tk = (beta - alpha) / beta;
       inv = 1.0 / (alpha - beta);
     }
-    double v[RPT];
-#pragma unroll
-    for (int p = 0; p < RPT; ++p) {
-      const int i = tid + NT * p;
-      const double x = pick<SM>(a[p], k);
-      v[p] = (i == k) ? 1.0 : ((i > k && i < I) ? x * inv : 0.0);
-    }
-    block_vec_sum<SM>(
-        [&](int j) {
-          double t = 0.0;
-          if (j > k && j < s) {
-#pragma unroll
-            for (int p = 0; p < RPT; ++p) t += v[p] * a[p][j];
-          }
-          return t;
-        },
-        s_scr, s_vec);
-#pragma unroll
-    for (int p = 0; p < RPT; ++p) {
-#pragma unroll
-      for (int j = 0; j < SM; ++j)
-        if (j > k && j < s) a[p][j] -= tk * v[p] * s_vec[j];
-    }
-#pragma unroll
-    for (int p = 0; p < RPT; ++p) {
-      const int i = tid + NT * p;
-      if (i == k) {
-        s_R[k * LD + k] = beta;
+    for (int i = tid; i < I; i += NT) {
+      if (i > k) {
+        const double v = xk[i] * inv;
 #pragma unroll
         for (int j = 0; j < SM; ++j)
-          if (j > k && j < s) s_R[j * LD + k] = a[p][j];
+          if (j > k && j < s) A[(size_t)j * I + i] -= tk * v * (rowk[j] + inv * vec[j]);
+        A[(size_t)k * I + i] = v;
       }
-      put<SM>(a[p], k, v[p]);
     }
-    if (tid == 0) s_tau[k] = tk;
+    if (tid == 0) {
+      tau[k] = tk;
+      M[k * LDR + k] = beta;  // M = R1^T: M(j, k) = R1(k, j)
+      for (int j = k + 1; j < s; ++j) M[k * LDR + j] = rowk[j] - tk * (rowk[j] + inv * vec[j]);
+    }
+    __syncthreads();
+  }
+
+  // ---- 2. QR of M = R1^T (s x s) by wave 0, lane = row; X = R2^T ----
+  if (wid == 0) {
+    for (int k = 0; k < s; ++k) {
+      const double mk = lane < s ? M[k * LDR + min(lane, s - 1)] : 0.0;  // my entry of column k
+      const double alpha = M[k * LDR + k];
+      double part[SM];
+#pragma unroll
+      for (int j = 0; j < SM; ++j) {
+        const double mij = M[min(j, s - 1) * LDR + min(lane, s - 1)] *
+                           ((lane > k && lane < s && j > k && j < s) ? 1.0 : 0.0);
+        part[j] = (j == k) ? ((lane > k && lane < s) ? mk * mk : 0.0) : mk * mij;
+      }
+      constexpr int CH = SM < 16 ? SM : 16;
+#pragma unroll
+      for (int c0 = 0; c0 < SM; c0 += CH) {
+        double v[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) v[q] = part[c0 + q];
+        const double r = wave_vec_sum<CH>(v, lane);
+        if (lane < CH) vec2[c0 + wave_vec_index<CH>(lane)] = r;
+      }
+      lds_fence();
+      const double sum2 = vec2[k];
+      double beta, tk, inv;
+      if (sum2 == 0.0) {
+        beta = alpha;
+        tk = 0.0;
+        inv = 0.0;
+      } else {
+        beta = -copysign(sqrt(alpha * alpha + sum2), alpha);
+        tk = (beta - alpha) / beta;
+        inv = 1.0 / (alpha - beta);
+      }
+      // w_j = M(k, j) + inv * d_j; rows i > k updated, row k becomes R2(k, :)
+      if (lane > k && lane < s) {
+        const double v = mk * inv;
+        for (int j = k + 1; j < s; ++j)
+          M[j * LDR + lane] -= tk * v * (M[j * LDR + k] + inv * vec2[j]);
+      }
+      lds_fence();
+      if (lane == 0) {
+        U[k * LDR + k] = beta;   // U holds X = R2^T for now: X(j, k) = R2(k, j)
+        for (int j = k + 1; j < s; ++j)
+          U[k * LDR + j] = M[j * LDR + k] - tk * (M[j * LDR + k] + inv * vec2[j]);
+      }
+      lds_fence();
+    }
+    // X = R2^T as the Jacobi matrix: copy U -> M (column c of X at M[c*LDR])
+    for (int e = lane; e < SM * LDR; e += kWave) {
+      M[e] = U[e];
+      U[e] = 0.0;
+    }
   }
   __syncthreads();
 
-  // ---- one-sided Jacobi on the columns of R (circle-method pair order) ----
-  const int se = s + (s & 1);
-  const int np = se / 2;
-  const int G = np <= NT / 64 ? 64 : (np <= NT / 32 ? 32 : 16);
-  const int g = tid / G, gl = tid % G;
-  for (int sweep = 0; sweep < 40 && se > 1; ++sweep) {
-    if (tid == 0) s_flag = 0;
-    __syncthreads();
-    for (int step = 0; step < se - 1; ++step) {
-      if (g < np) {
-        const int x0 = g, x1 = se - 1 - g;
-        int p = (x0 == 0) ? 0 : ((x0 - 1 + step) % (se - 1)) + 1;
-        int q = ((x1 - 1 + step) % (se - 1)) + 1;
-        if (p > q) {
-          const int t = p;
-          p = q;
-          q = t;
-        }
-        double aa = 0.0, bb = 0.0, cc = 0.0;
-        for (int i = gl; i < s; i += G) {
-          const double x = s_R[p * LD + i], y = s_R[q * LD + i];
-          aa += x * x;
-          bb += y * y;
-          cc += x * y;
-        }
-        for (int m = 1; m < G; m <<= 1) {
-          aa += __shfl_xor(aa, m, kWave);
-          bb += __shfl_xor(bb, m, kWave);
-          cc += __shfl_xor(cc, m, kWave);
-        }
-        if (cc != 0.0 && fabs(cc) > 1e-15 * sqrt(aa) * sqrt(bb)) {
-          const double zeta = (bb - aa) / (2.0 * cc);
-          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
-          const double cs = 1.0 / sqrt(1.0 + t * t);
-          const double sn = cs * t;
-          for (int i = gl; i < s; i += G) {
-            const double x = s_R[p * LD + i], y = s_R[q * LD + i];
-            s_R[p * LD + i] = cs * x - sn * y;
-            s_R[q * LD + i] = sn * x + cs * y;
-          }
-          if (gl == 0) s_flag = 1;
-        }
+  // ---- 3. one-sided Jacobi on the columns of X; pair g on wave g % NW ----
+  {
+    const int se = s + (s & 1);
+    const int np = se / 2;
+    const double tol = 2.0 * s * 2.220446049250313e-16;
+    for (int e = tid; e < (se - 1) * np; e += NT) {
+      int pp, qq;
+      jacobi_pair(e % np, e / np, se, &pp, &qq);
+      pairs[(e / np) * H + (e % np)] = pp | (qq << 8);
+    }
+    for (int sweep = 0; sweep < 40 && se > 1; ++sweep) {
+      // exact column norms at the start of every sweep; updated per rotation
+      if (tid < se) {
+        double a = 0.0;
+        for (int i = 0; i < s; ++i) a += M[tid * LDR + i] * M[tid * LDR + i];
+        jn[tid] = a;
       }
+      if (tid == 0) *flag = 0;
       __syncthreads();
+      for (int step = 0; step < se - 1; ++step) {
+        double xs[HW], ys[HW], cc[HW];
+        int ps[HW], qs[HW];
+#pragma unroll
+        for (int h = 0; h < HW; ++h) {
+          const int g = wid + NW * h;
+          const int pq = g < np ? pairs[step * H + g] : 0;
+          ps[h] = pq & 0xff;
+          qs[h] = pq >> 8;
+          xs[h] = (g < np && lane < s) ? M[ps[h] * LDR + lane] : 0.0;
+          ys[h] = (g < np && lane < s) ? M[qs[h] * LDR + lane] : 0.0;
+          cc[h] = xs[h] * ys[h];
+        }
+#pragma unroll
+        for (int h = 0; h < HW; ++h) cc[h] = wave_sum(cc[h]);
+#pragma unroll
+        for (int h = 0; h < HW; ++h) {
+          const int g = wid + NW * h;
+          if (g < np) {
+            const double a = jn[ps[h]], b = jn[qs[h]];
+            if (cc[h] != 0.0 && fabs(cc[h]) > tol * sqrt(a) * sqrt(b)) {
+              const double zeta = (b - a) / (2.0 * cc[h]);
+              const double t =
+                  (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+              const double cs = 1.0 / sqrt(1.0 + t * t);
+              const double sn = cs * t;
+              if (lane < s) {
+                M[ps[h] * LDR + lane] = cs * xs[h] - sn * ys[h];
+                M[qs[h] * LDR + lane] = sn * xs[h] + cs * ys[h];
+              }
+              if (lane == 0) {
+                jn[ps[h]] = a - t * cc[h];
+                jn[qs[h]] = b + t * cc[h];
+                *flag = 1;
+              }
+            }
+          }
+        }
+        __syncthreads();
+      }
+      const int more = *flag;
+      __syncthreads();
+      if (!more) break;
     }
-    const int more = s_flag;
-    __syncthreads();
-    if (!more) break;
   }
 
-  // ---- singular values, descending order, U_R = normalised columns ----
+  // ---- 4. singular values, descending order (ties: lower column first) ----
   if (tid < s) {
-    double n2 = 0.0;
-    for (int i = 0; i < s; ++i) n2 += s_R[tid * LD + i] * s_R[tid * LD + i];
-    s_sig[tid] = sqrt(n2);
+    double a = 0.0;
+    for (int i = 0; i < s; ++i) a += M[tid * LDR + i] * M[tid * LDR + i];
+    sig[tid] = sqrt(a);
   }
   __syncthreads();
   if (tid < s) {
-    const double me = s_sig[tid];
+    const double me = sig[tid];
     int rank = 0;
     for (int q = 0; q < s; ++q) {
-      const double o = s_sig[q];
+      const double o = sig[q];
       if (o > me || (o == me && q < tid)) ++rank;
     }
-    s_perm[rank] = tid;
+    perm[rank] = tid;
     if (sig_out) sig_out[rank] = me;
     if (!isfinite(me) && status) atomicOr(status, kDevNonFinite);
   }
   __syncthreads();
   for (int e = tid; e < mu * s; e += NT) {
     const int c = e / s, i = e % s;
-    const int pc = s_perm[c];
-    const double sg = s_sig[pc];
-    s_U[c * LD + i] = sg > 0.0 ? s_R[pc * LD + i] / sg : (i == pc ? 1.0 : 0.0);
+    const int pc = perm[c];
+    const double sg = sig[pc];
+    U[c * LDR + i] = sg > 0.0 ? M[pc * LDR + i] / sg : (i == pc ? 1.0 : 0.0);
   }
   __syncthreads();
 
-  // ---- P = H_0 ... H_{s-1} [I_s; 0] in place of the reflectors (dorg2r) ----
+  // ---- 5. Z = H_0 ... H_{s-1} [U; 0] ----
+  for (int e = tid; e < I * mu; e += NT) {
+    const int c = e / I, i = e % I;
+    Z[e] = i < s ? U[c * LDR + i] : 0.0;
+  }
+  __syncthreads();
   for (int k = s - 1; k >= 0; --k) {
-    const double tk = s_tau[k];
-    double vk[RPT];
+    const double tk = tau[k];
+    const double* vk = A + (size_t)k * I;
+    double part[SM];
 #pragma unroll
-    for (int p = 0; p < RPT; ++p) vk[p] = pick<SM>(a[p], k);
-    if (k < s - 1) {
-      block_vec_sum<SM>(
-          [&](int j) {
-            double t = 0.0;
-            if (j > k && j < s) {
+    for (int c = 0; c < SM; ++c) part[c] = 0.0;
+    for (int i = tid; i < I; i += NT) {
+      if (i >= k) {
+        const double v = i == k ? 1.0 : vk[i];
+        double zv[SM];
 #pragma unroll
-              for (int p = 0; p < RPT; ++p) t += vk[p] * a[p][j];
-            }
-            return t;
-          },
-          s_scr, s_vec);
+        for (int c = 0; c < SM; ++c)
+          zv[c] = Z[(size_t)min(c, mu - 1) * I + i] * (c < mu ? 1.0 : 0.0);
 #pragma unroll
-      for (int p = 0; p < RPT; ++p) {
-#pragma unroll
-        for (int j = 0; j < SM; ++j)
-          if (j > k && j < s) a[p][j] -= tk * vk[p] * s_vec[j];
+        for (int c = 0; c < SM; ++c) part[c] += v * zv[c];
       }
     }
+    vec_sum(part);
+    for (int i = tid; i < I; i += NT) {
+      if (i >= k) {
+        const double v = i == k ? 1.0 : vk[i];
 #pragma unroll
-    for (int p = 0; p < RPT; ++p) {
-      const int i = tid + NT * p;
-      const double nv = (i == k) ? 1.0 - tk : ((i > k) ? -tk * vk[p] : 0.0);
-      put<SM>(a[p], k, nv);
+        for (int c = 0; c < SM; ++c)
+          if (c < mu) Z[(size_t)c * I + i] -= tk * v * vec[c];
+      }
     }
   }
+  __syncthreads();
 
-  // ---- Q = P U_R(:, 1:mu); per column, the largest |entry| (lowest row) ----
-  for (int c = 0; c < mu; ++c) {
+  // ---- 6. signs and outputs ----
+  for (int c = wid; c < mu; c += NW) {
     double best = -1.0, bval = 0.0;
-    int bidx = 0x7fffffff;
-#pragma unroll
-    for (int p = 0; p < RPT; ++p) {
-      const int i = tid + NT * p;
-      double z = 0.0;
-#pragma unroll
-      for (int j = 0; j < SM; ++j)
-        if (j < s) z += a[p][j] * s_U[c * LD + j];
-      if (i < I && (fabs(z) > best)) {
-        best = fabs(z);
-        bval = z;
-        bidx = i;
+    for (int i0 = 0; i0 < I; i0 += kWave) {
+      const int i = i0 + lane;
+      const double z = i < I ? Z[(size_t)c * I + i] : 0.0;
+      const double az = i < I ? fabs(z) : -1.0;
+      const double m = wave_max(az);
+      if (m > best) {
+        const unsigned long long hit = __ballot(az == m);
+        const int l = __ffsll((long long)hit) - 1;
+        best = m;
+        bval = __shfl(z, l, kWave);
       }
     }
-#pragma unroll
-    for (int m = 1; m < kWave; m <<= 1) {
-      const double ob = __shfl_xor(best, m, kWave);
-      const double ov = __shfl_xor(bval, m, kWave);
-      const int oi = __shfl_xor(bidx, m, kWave);
-      if (ob > best || (ob == best && oi < bidx)) {
-        best = ob;
-        bval = ov;
-        bidx = oi;
-      }
-    }
-    if (lane == 0) {
-      s_babs[wid * SM + c] = best;
-      s_bval[wid * SM + c] = bval;
-      s_bidx[wid * SM + c] = bidx;
-    }
+    if (lane == 0) sgn[c] = bval < 0.0 ? -1.0 : 1.0;
   }
   __syncthreads();
-  if (tid < mu) {
-    double best = -1.0, bval = 0.0;
-    int bidx = 0x7fffffff;
-    for (int w = 0; w < NW; ++w) {
-      const double ob = s_babs[w * SM + tid];
-      const int oi = s_bidx[w * SM + tid];
-      if (ob > best || (ob == best && oi < bidx)) {
-        best = ob;
-        bval = s_bval[w * SM + tid];
-        bidx = oi;
+  for (int e = tid; e < I * ldqt; e += NT) {
+    const int i = e / ldqt, c = e % ldqt;
+    double z = 0.0;
+    if (c < mu) {
+      z = Z[(size_t)c * I + i] * sgn[c];
+      Q[i + (int64_t)I * c] = z;
+      if (Qcast) {
+        if (cast_f32) ((float*)Qcast)[i + (int64_t)I * c] = (float)z;
+        else ((double*)Qcast)[i + (int64_t)I * c] = z;
       }
     }
-    s_sign[tid] = bval < 0.0 ? -1.0 : 1.0;
-  }
-  __syncthreads();
-  for (int c = 0; c < mu; ++c) {
-    const double sg = s_sign[c];
-#pragma unroll
-    for (int p = 0; p < RPT; ++p) {
-      const int i = tid + NT * p;
-      if (i < I) {
-        double z = 0.0;
-#pragma unroll
-        for (int j = 0; j < SM; ++j)
-          if (j < s) z += a[p][j] * s_U[c * LD + j];
-        z *= sg;
-        Q[i + (int64_t)I * c] = z;
-        if (Qt) Qt[(int64_t)i * mu + c] = z;
-        if (Qcast) {
-          if (cast_f32) ((float*)Qcast)[i + (int64_t)I * c] = (float)z;
-          else ((double*)Qcast)[i + (int64_t)I * c] = z;
-        }
-      }
-    }
+    if (Qt) Qt[(int64_t)i * ldqt + c] = z;  // padding columns are zero
   }
 }
 
-// Row-major copy Qt of a column-major I x mu matrix Q.
-__global__ void k_transpose(const double* __restrict__ Q, int64_t I, int64_t mu,
+// Row-major copy Qt (row stride ldqt >= mu, padding zero) of a column-major
+// I x mu matrix Q.
+__global__ void k_transpose(const double* __restrict__ Q, int64_t I, int64_t mu, int64_t ldqt,
                             double* __restrict__ Qt) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= I * mu) return;
-  const int64_t i = e % I, k = e / I;
-  Qt[i * mu + k] = Q[e];
+  if (e >= I * ldqt) return;
+  const int64_t i = e / ldqt, k = e % ldqt;
+  Qt[e] = k < mu ? Q[i + I * k] : 0.0;
 }
 
 template <typename Tout>

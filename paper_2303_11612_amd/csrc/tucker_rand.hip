@@ -63,11 +63,90 @@ struct TimeScope {
 };
 
 // ---------------------------------------------------------------------------
+// Compile-time widths: a row of Q^T or of the sketch is padded with zeros to
+// the next width in this list, which the kernels are instantiated for.
+// ---------------------------------------------------------------------------
+constexpr int kWidths[] = {4, 8, 12, 16, 20, 24, 32, 40, 48, 64};
+inline int pad_width(int64_t m) {
+  for (int w : kWidths)
+    if (m <= w) return w;
+  return 0;
+}
+
+// Power steps on an L == 1 source use the fused tile kernel when a thread's
+// rows fit in registers; otherwise (and for L > 1) the two-kernel form.
+inline int tile_rpt(int64_t I) { return (int)cdiv(I, kNT); }
+inline bool tile_ok_lds(int64_t I, int64_t s, bool f64);
+inline bool tile_ok(int64_t I, int64_t s, bool f64) {
+  const int sm = pad_width(s);
+  const int rpt = tile_rpt(I);
+  return sm > 0 && rpt <= 4 && rpt * sm <= 64 && tile_ok_lds(I, s, f64);
+}
+// LDS of the tile kernel: Y (I x sm) + W (tj x sm) + tile (I x tj).
+inline int64_t tile_budget() { return 163840 - 1024; }
+inline bool tile_ok_lds(int64_t I, int64_t s, bool f64) {
+  const int sm = pad_width(s);
+  return 8 * I * sm + (8 * sm + (I | 1) * (f64 ? 8 : 4)) * 4 <= tile_budget();
+}
+inline int tile_cols(int64_t I, int64_t s, bool f64) {
+  const int sm = pad_width(s);
+  const int64_t per = 8 * sm + (I | 1) * (f64 ? 8 : 4);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(64, (tile_budget() - 8 * I * sm) / per));
+}
+inline size_t tile_lds(int64_t I, int64_t s, int tj, bool f64) {
+  const int sm = pad_width(s);
+  return 8 * (size_t)(I * sm) + 8 * (size_t)tj * sm + (size_t)(I | 1) * tj * (f64 ? 8 : 4);
+}
+inline int64_t tile_blocks(int64_t J, int tj) {
+  return std::min<int64_t>(512, cdiv(J, tj));
+}
+inline int64_t gram_parts(int64_t jsrc) {
+  return std::min<int64_t>(256, std::max<int64_t>(1, cdiv(jsrc, 64)));
+}
+// Number of partial sketches a power step on this source produces.
+inline int64_t power_parts(int64_t L, int64_t I, int64_t J, int64_t s, bool f64) {
+  if (L == 1 && tile_ok(I, s, f64)) {
+    const int tj = tile_cols(I, s, f64);
+    const int64_t ntiles = cdiv(J, tj);
+    const int64_t per = cdiv(ntiles, tile_blocks(J, tj));
+    return cdiv(ntiles, per);
+  }
+  const int64_t nparts = gram_parts(J);
+  return cdiv(J, cdiv(J, nparts));
+}
+
+// Views with few columns split their rows over blocks (k_ttm_split) so that
+// about 512 blocks run; 1 means the one-pass kernels.
+inline int64_t ttm_splits(int64_t J, int64_t I) {
+  const int64_t bx = cdiv(J, kNT);
+  if (bx >= 256 || I < 32) return 1;
+  return std::max<int64_t>(1, std::min<int64_t>(cdiv(512, bx), I / 16));
+}
+
+inline int factor_sm(int64_t s) { return s <= 16 ? 16 : (s <= 32 ? 32 : 64); }
+constexpr size_t kMaxLds = 163840;
+
+// LDS bytes of the factor kernel; `global_mats` keeps the I x s and I x mu
+// working matrices in global scratch instead.
+inline size_t factor_lds_bytes(int64_t I, int64_t s, int64_t mu, bool global_mats) {
+  switch (factor_sm(s)) {
+    case 16: return trk::FactorShape<16>::lds_bytes((int)I, (int)s, (int)mu, global_mats);
+    case 32: return trk::FactorShape<32>::lds_bytes((int)I, (int)s, (int)mu, global_mats);
+    default: return trk::FactorShape<64>::lds_bytes((int)I, (int)s, (int)mu, global_mats);
+  }
+}
+inline bool factor_in_lds(int64_t I, int64_t s, int64_t mu) {
+  return factor_lds_bytes(I, s, mu, false) <= kMaxLds;
+}
+inline bool factor_supported(int64_t I, int64_t s) { return s >= 1 && s <= 64 && I <= (1 << 24); }
+
+// ---------------------------------------------------------------------------
 // Plan: per-mode shapes and the workspace layout.
 // ---------------------------------------------------------------------------
 struct ModePlan {
   int64_t L, I, R, J;   // 3-D view of the tensor the mode is computed from
   int64_t s, mu, T;     // sketch width, rank, samples (T = 0: exact)
+  int sw, muw;          // padded widths of the sketch rows and of Q^T rows
   bool sampled;
   bool src_f64;         // the tensor of this mode is float64
 };
@@ -83,22 +162,9 @@ struct Plan {
   ModePlan m[TR_MAX_ORDER];
   // workspace offsets (bytes)
   size_t oG, oY, oYt, oZ, oPart, oNorms, oW, oCdf, oBsum, oIdx, oScale, oScale2, oCp,
-      oMax, oSig, oX0, oX1, total;
+      oMax, oSig, oX0, oX1, oCore, oSplit, total;
   size_t oQ[TR_MAX_ORDER], oQt[TR_MAX_ORDER];
 };
-
-inline int64_t gram_parts(int64_t jsrc) {
-  return std::min<int64_t>(256, std::max<int64_t>(1, cdiv(jsrc, 64)));
-}
-
-inline int factor_sm(int64_t s) { return s <= 16 ? 16 : (s <= 32 ? 32 : 64); }
-
-inline bool factor_supported(int64_t I, int64_t s) {
-  if (s < 1 || s > 64) return false;
-  const int64_t rpt = cdiv(I, trk::kFactorNT);
-  const int sm = factor_sm(s);
-  return rpt * sm <= 64 && rpt <= 4;
-}
 
 // Validates and fills the plan; returns TR_OK or an error code.
 int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
@@ -131,7 +197,8 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
   for (int n = 0; n < N; ++n) total_el *= (double)cur[n];
   if (total_el > 9.0e15) return TR_EINVAL;
 
-  size_t maxIs = 0, maxZ = 0, maxPart = 0, maxJs = 0, maxT = 0, maxCp = 0, maxInter = 0;
+  size_t maxIs = 0, maxZ = 0, maxPart = 0, maxJs = 0, maxT = 0, maxCp = 0, maxInter = 0,
+         maxSplit = 0;
   int64_t maxS = 0;
   for (int n = 0; n < N; ++n) {
     ModePlan& M = P->m[n];
@@ -155,10 +222,20 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
       }
     }
     if (!factor_supported(M.I, M.s)) return TR_ENOTSUP;
+    M.sw = pad_width(M.s);
+    M.muw = pad_width(M.mu);
+    if (M.sw == 0 || M.muw == 0) return TR_ENOTSUP;
     const int64_t jsrc = M.sampled ? M.T : M.J;
-    maxIs = std::max(maxIs, (size_t)(M.I * M.s));
-    maxZ = std::max(maxZ, (size_t)(jsrc * M.s));
-    maxPart = std::max(maxPart, (size_t)(gram_parts(jsrc) * M.I * M.s));
+    const int64_t lsrc = M.sampled ? 1 : M.L;
+    const bool fsrc = M.src_f64;
+    maxIs = std::max(maxIs, (size_t)(M.I * M.sw));
+    if (!(lsrc == 1 && tile_ok(M.I, M.s, fsrc))) {
+      maxZ = std::max(maxZ, (size_t)(jsrc * M.sw));
+      maxSplit = std::max(maxSplit, (size_t)(ttm_splits(jsrc, M.I) * jsrc * M.sw));
+    }
+    // the shrink of this mode reads the tensor the mode is computed from
+    maxSplit = std::max(maxSplit, (size_t)(ttm_splits(M.J, M.I) * M.J * M.muw));
+    maxPart = std::max(maxPart, (size_t)(power_parts(lsrc, M.I, jsrc, M.s, fsrc) * M.I * M.s));
     maxS = std::max(maxS, M.s);
     if (M.sampled) {
       maxJs = std::max(maxJs, (size_t)M.J);
@@ -167,15 +244,22 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
     }
     if (sthosvd) cur[n] = M.mu;  // the next mode sees the shrunk tensor
   }
-  // intermediate tensors: after the n-th shrink of the chain (n < N-1)
+  // intermediate tensors: after each shrink of the chain (the last one is the
+  // core, kept in float64 before the cast to the caller's dtype)
+  size_t core_el = 1;
   {
     int64_t shp[TR_MAX_ORDER];
     for (int n = 0; n < N; ++n) shp[n] = P->dims[n];
-    for (int n = 0; n + 1 < N; ++n) {
+    for (int n = 0; n < N; ++n) {
+      int64_t Jc = 1;
+      for (int k2 = 0; k2 < N; ++k2)
+        if (k2 != n) Jc *= shp[k2];
+      maxSplit = std::max(maxSplit, (size_t)(ttm_splits(Jc, shp[n]) * Jc * P->m[n].muw));
       shp[n] = P->m[n].mu;
       size_t e = 1;
       for (int k = 0; k < N; ++k) e *= (size_t)shp[k];
-      maxInter = std::max(maxInter, e);
+      if (n + 1 < N) maxInter = std::max(maxInter, e);
+      else core_el = e;
     }
   }
   size_t off = 0;
@@ -201,10 +285,12 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
   P->oSig = take(8 * (size_t)maxS);
   for (int n = 0; n < N; ++n) {
     P->oQ[n] = take(8 * (size_t)(P->m[n].I * P->m[n].mu));
-    P->oQt[n] = take(8 * (size_t)(P->m[n].I * P->m[n].mu));
+    P->oQt[n] = take(8 * (size_t)(P->m[n].I * P->m[n].muw));
   }
   P->oX0 = take(8 * maxInter);
   P->oX1 = take(8 * maxInter);
+  P->oCore = take(8 * core_el);
+  P->oSplit = take(8 * maxSplit);
   P->total = off;
   return TR_OK;
 }
@@ -220,11 +306,19 @@ inline int check_launch() { return hipGetLastError() == hipSuccess ? TR_OK : TR_
 // ---------------------------------------------------------------------------
 // Launchers (all asynchronous on `st`).
 // ---------------------------------------------------------------------------
-int launch_gaussian(double* G, double* Gt, int64_t I, int64_t s, int mode, uint64_t seed,
-                    hipStream_t st) {
+int launch_fill_f64(double* p, int64_t n, double v, hipStream_t st) {
+  if (n <= 0) return TR_OK;
+  hipLaunchKernelGGL(trk::k_fill_f64, dim3((unsigned)cdiv(n, kNT)), dim3(kNT), 0, st, p, n, v);
+  return check_launch();
+}
+
+// G (I x s) and its row-major copy Gt with zero padding to stride ldgt.
+int launch_gaussian(double* G, double* Gt, int64_t I, int64_t s, int64_t ldgt, int mode,
+                    uint64_t seed, hipStream_t st) {
+  if (Gt && ldgt > s) TR_TRY(launch_fill_f64(Gt, I * ldgt, 0.0, st));
   const int64_t blocks4 = cdiv(I * s, 4);
   hipLaunchKernelGGL(trk::k_gaussian, dim3((unsigned)cdiv(blocks4, kNT)), dim3(kNT), 0, st,
-                     G, Gt, I, s, (uint64_t)mode, seed);
+                     G, Gt, I, s, ldgt, (uint64_t)mode, seed);
   return check_launch();
 }
 
@@ -293,108 +387,207 @@ int launch_gather(bool f64, const void* X, int64_t L, int64_t I, const int64_t* 
   return check_launch();
 }
 
-template <typename Tin, typename Tout, int MU>
-void ttm_mu(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Qt, int mu,
-            const double* colscale, Tout* Y, hipStream_t st) {
-  const dim3 grid((unsigned)cdiv(L * R, kNT));
+template <typename Tin, int MU>
+void ttm_w(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Qt, int kout,
+           const double* colscale, double* Y, double* split, hipStream_t st) {
+  const int64_t J = L * R;
+  const dim3 grid((unsigned)cdiv(J, kNT));
+  const int64_t ns = split ? ttm_splits(J, I) : 1;
+  if (ns > 1) {
+    const int64_t ich = cdiv(I, ns);
+    const int64_t nsu = cdiv(I, ich);
+    hipLaunchKernelGGL((trk::k_ttm_split<Tin, MU>), dim3((unsigned)cdiv(J, kNT), (unsigned)nsu),
+                       dim3(kNT), 0, st, X, L, I, R, Qt, ich, split);
+    hipLaunchKernelGGL(trk::k_sum_splits, dim3((unsigned)cdiv(J * kout, kNT)), dim3(kNT), 0, st,
+                       split, nsu, L, R, MU, kout, colscale, Y);
+    return;
+  }
   if (L == 1)
-    hipLaunchKernelGGL((trk::k_ttm_l1<Tin, Tout, MU>), grid, dim3(kNT), 0, st, X, I, R, Qt, mu,
+    hipLaunchKernelGGL((trk::k_ttm_l1<Tin, MU>), grid, dim3(kNT), 0, st, X, I, R, Qt, kout,
                        colscale, Y);
   else
-    hipLaunchKernelGGL((trk::k_ttm_ln<Tin, Tout, MU>), grid, dim3(kNT), 0, st, X, L, I, R, Qt,
-                       mu, colscale, Y);
+    hipLaunchKernelGGL((trk::k_ttm_ln<Tin, MU>), grid, dim3(kNT), 0, st, X, L, I, R, Qt, kout,
+                       colscale, Y);
 }
 
-template <typename Tin, typename Tout>
-int ttm_t(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Qt, int64_t mu,
-          const double* colscale, Tout* Y, hipStream_t st) {
-  if (mu <= 8) ttm_mu<Tin, Tout, 8>(X, L, I, R, Qt, (int)mu, colscale, Y, st);
-  else if (mu <= 16) ttm_mu<Tin, Tout, 16>(X, L, I, R, Qt, (int)mu, colscale, Y, st);
-  else if (mu <= 32) ttm_mu<Tin, Tout, 32>(X, L, I, R, Qt, (int)mu, colscale, Y, st);
-  else if (mu <= 64) ttm_mu<Tin, Tout, 64>(X, L, I, R, Qt, (int)mu, colscale, Y, st);
-  else return TR_ENOTSUP;
+// Y = X x_n Q^T with Qt of row stride `width` (zero-padded); outputs k < kout.
+template <typename Tin>
+int ttm_t(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Qt, int width, int kout,
+          const double* colscale, double* Y, double* split, hipStream_t st) {
+  switch (width) {
+    case 4: ttm_w<Tin, 4>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
+    case 8: ttm_w<Tin, 8>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
+    case 12: ttm_w<Tin, 12>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
+    case 16: ttm_w<Tin, 16>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
+    case 20: ttm_w<Tin, 20>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
+    case 24: ttm_w<Tin, 24>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
+    case 32: ttm_w<Tin, 32>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
+    case 40: ttm_w<Tin, 40>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
+    case 48: ttm_w<Tin, 48>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
+    case 64: ttm_w<Tin, 64>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
+    default: return TR_ENOTSUP;
+  }
   return check_launch();
 }
 
+// split: scratch for the split-rows form (ttm_splits(J, I) * J * width
+// doubles), or NULL to always use the one-pass kernels.
 int launch_ttm(bool in_f64, const void* X, int64_t L, int64_t I, int64_t R, const double* Qt,
-               int64_t mu, const double* colscale, bool out_f64, void* Y, hipStream_t st) {
-  if (in_f64) {
-    if (out_f64) return ttm_t((const double*)X, L, I, R, Qt, mu, colscale, (double*)Y, st);
-    return ttm_t((const double*)X, L, I, R, Qt, mu, colscale, (float*)Y, st);
-  }
-  if (out_f64) return ttm_t((const float*)X, L, I, R, Qt, mu, colscale, (double*)Y, st);
-  return ttm_t((const float*)X, L, I, R, Qt, mu, colscale, (float*)Y, st);
+               int width, int kout, const double* colscale, double* Y, double* split,
+               hipStream_t st) {
+  if (in_f64) return ttm_t((const double*)X, L, I, R, Qt, width, kout, colscale, Y, split, st);
+  return ttm_t((const float*)X, L, I, R, Qt, width, kout, colscale, Y, split, st);
+}
+
+int launch_cast(const double* src, int64_t n, bool to_f32, void* dst, hipStream_t st) {
+  if (to_f32)
+    hipLaunchKernelGGL(trk::k_cast<float>, dim3((unsigned)cdiv(n, kNT)), dim3(kNT), 0, st, src,
+                       n, (float*)dst);
+  else
+    hipLaunchKernelGGL(trk::k_cast<double>, dim3((unsigned)cdiv(n, kNT)), dim3(kNT), 0, st, src,
+                       n, (double*)dst);
+  return check_launch();
 }
 
 template <typename Tin, int SM>
-void gramb_sm(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Z, int s,
-              int64_t nparts, int64_t chunk, double* part, hipStream_t st) {
-  if (L == 1)
-    hipLaunchKernelGGL((trk::k_gramb_l1<Tin, SM>), dim3((unsigned)nparts), dim3(kNT), 0, st, X,
-                       I, R, Z, s, chunk, part);
-  else
-    hipLaunchKernelGGL((trk::k_gramb_ln<Tin, SM>), dim3((unsigned)nparts), dim3(kNT), 0, st, X,
-                       L, I, R, Z, s, chunk, part);
+void gramb_w(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Z, int s,
+             int64_t nparts, int64_t chunk, double* part, hipStream_t st) {
+  hipLaunchKernelGGL((trk::k_gramb_ln<Tin, SM>), dim3((unsigned)nparts), dim3(kNT), 0, st, X, L,
+                     I, R, Z, s, chunk, part);
 }
 
 template <typename Tin>
-int gramb_t(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Z, int64_t s,
+int gramb_t(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Z, int64_t s, int sw,
             int64_t nparts, int64_t chunk, double* part, hipStream_t st) {
-  if (s <= 8) gramb_sm<Tin, 8>(X, L, I, R, Z, (int)s, nparts, chunk, part, st);
-  else if (s <= 16) gramb_sm<Tin, 16>(X, L, I, R, Z, (int)s, nparts, chunk, part, st);
-  else if (s <= 32) gramb_sm<Tin, 32>(X, L, I, R, Z, (int)s, nparts, chunk, part, st);
-  else if (s <= 64) gramb_sm<Tin, 64>(X, L, I, R, Z, (int)s, nparts, chunk, part, st);
-  else return TR_ENOTSUP;
+  const int si = (int)s;
+  switch (sw) {
+    case 4: gramb_w<Tin, 4>(X, L, I, R, Z, si, nparts, chunk, part, st); break;
+    case 8: gramb_w<Tin, 8>(X, L, I, R, Z, si, nparts, chunk, part, st); break;
+    case 12: gramb_w<Tin, 12>(X, L, I, R, Z, si, nparts, chunk, part, st); break;
+    case 16: gramb_w<Tin, 16>(X, L, I, R, Z, si, nparts, chunk, part, st); break;
+    case 20: gramb_w<Tin, 20>(X, L, I, R, Z, si, nparts, chunk, part, st); break;
+    case 24: gramb_w<Tin, 24>(X, L, I, R, Z, si, nparts, chunk, part, st); break;
+    case 32: gramb_w<Tin, 32>(X, L, I, R, Z, si, nparts, chunk, part, st); break;
+    case 40: gramb_w<Tin, 40>(X, L, I, R, Z, si, nparts, chunk, part, st); break;
+    case 48: gramb_w<Tin, 48>(X, L, I, R, Z, si, nparts, chunk, part, st); break;
+    case 64: gramb_w<Tin, 64>(X, L, I, R, Z, si, nparts, chunk, part, st); break;
+    default: return TR_ENOTSUP;
+  }
   return check_launch();
 }
 
-size_t power_ws_bytes(int64_t L, int64_t I, int64_t R, int64_t s) {
-  const int64_t J = L * R;
-  return align_up(8 * (size_t)(J * s)) + align_up(8 * (size_t)(gram_parts(J) * I * s)) +
-         align_up(8 * (size_t)(I * s));
+template <typename Tin, int SM, int RPT>
+void tile_w(const Tin* X, int64_t I, int64_t J, const double* colw, const double* Yt, int s,
+            int tj, int64_t per, int64_t nblk, double* part, hipStream_t st) {
+  const size_t lds = tile_lds(I, s, tj, sizeof(Tin) == 8);
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)&trk::k_gram_tile_l1<Tin, SM, RPT>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((trk::k_gram_tile_l1<Tin, SM, RPT>), dim3((unsigned)nblk), dim3(kNT), lds,
+                     st, X, I, J, colw, Yt, s, tj, per, part);
 }
 
-// C = (X_(n) D X_(n)^T)^q G by alternating the two halves of Strategy A.
-// Yt: row-major copy of the current sketch (initially of G); Z, part: scratch.
-int run_power(bool f64, const void* X, int64_t L, int64_t I, int64_t R, const double* colw,
-              int q, int64_t s, double* Y, double* Yt, double* Z, double* part,
-              uint32_t* status, hipStream_t st) {
+template <typename Tin, int SM>
+void tile_sm(const Tin* X, int64_t I, int64_t J, const double* colw, const double* Yt, int s,
+             int tj, int64_t per, int64_t nblk, double* part, hipStream_t st) {
+  switch (tile_rpt(I)) {
+    case 1: tile_w<Tin, SM, 1>(X, I, J, colw, Yt, s, tj, per, nblk, part, st); break;
+    case 2: if constexpr (SM <= 32) tile_w<Tin, SM, 2>(X, I, J, colw, Yt, s, tj, per, nblk, part, st); break;
+    case 3: if constexpr (SM <= 20) tile_w<Tin, SM, 3>(X, I, J, colw, Yt, s, tj, per, nblk, part, st); break;
+    default: if constexpr (SM <= 16) tile_w<Tin, SM, 4>(X, I, J, colw, Yt, s, tj, per, nblk, part, st); break;
+  }
+}
+
+template <typename Tin>
+int tile_t(const Tin* X, int64_t I, int64_t J, const double* colw, const double* Yt, int64_t s,
+           int sw, int tj, int64_t per, int64_t nblk, double* part, hipStream_t st) {
+  const int si = (int)s;
+  switch (sw) {
+    case 4: tile_sm<Tin, 4>(X, I, J, colw, Yt, si, tj, per, nblk, part, st); break;
+    case 8: tile_sm<Tin, 8>(X, I, J, colw, Yt, si, tj, per, nblk, part, st); break;
+    case 12: tile_sm<Tin, 12>(X, I, J, colw, Yt, si, tj, per, nblk, part, st); break;
+    case 16: tile_sm<Tin, 16>(X, I, J, colw, Yt, si, tj, per, nblk, part, st); break;
+    case 20: tile_sm<Tin, 20>(X, I, J, colw, Yt, si, tj, per, nblk, part, st); break;
+    case 24: tile_sm<Tin, 24>(X, I, J, colw, Yt, si, tj, per, nblk, part, st); break;
+    case 32: tile_sm<Tin, 32>(X, I, J, colw, Yt, si, tj, per, nblk, part, st); break;
+    case 40: tile_sm<Tin, 40>(X, I, J, colw, Yt, si, tj, per, nblk, part, st); break;
+    case 48: tile_sm<Tin, 48>(X, I, J, colw, Yt, si, tj, per, nblk, part, st); break;
+    case 64: tile_sm<Tin, 64>(X, I, J, colw, Yt, si, tj, per, nblk, part, st); break;
+    default: return TR_ENOTSUP;
+  }
+  return check_launch();
+}
+
+size_t power_ws_bytes(int64_t L, int64_t I, int64_t R, int64_t s, bool f64) {
   const int64_t J = L * R;
-  const int64_t nparts = gram_parts(J);
-  const int64_t chunk = cdiv(J, nparts);
-  const int64_t nused = cdiv(J, chunk);
+  const int sw = pad_width(s);
+  return align_up(8 * (size_t)(J * sw)) + align_up(8 * (size_t)(power_parts(L, I, J, s, f64) * I * s)) +
+         align_up(8 * (size_t)(I * sw));
+}
+
+// C = (X_(n) D X_(n)^T)^q G by the two halves of Strategy A, starting from
+// Yt = G^T (row stride sw, zero-padded).  Z, part: scratch.
+int run_power(bool f64, const void* X, int64_t L, int64_t I, int64_t R, const double* colw,
+              int q, int64_t s, int sw, double* Y, double* Yt, double* Z, double* part,
+              double* split, uint32_t* status, hipStream_t st) {
+  const int64_t J = L * R;
+  const bool tiled = L == 1 && tile_ok(I, s, f64);
   for (int step = 0; step < q; ++step) {
-    TR_TRY(launch_ttm(f64, X, L, I, R, Yt, s, colw, true, Z, st));
-    if (f64) TR_TRY(gramb_t((const double*)X, L, I, R, Z, s, nused, chunk, part, st));
-    else TR_TRY(gramb_t((const float*)X, L, I, R, Z, s, nused, chunk, part, st));
+    int64_t nused;
+    if (tiled) {
+      const int tj = tile_cols(I, s, f64);
+      const int64_t ntiles = cdiv(J, tj);
+      const int64_t per = cdiv(ntiles, tile_blocks(J, tj));
+      nused = cdiv(ntiles, per);
+      if (f64) TR_TRY(tile_t((const double*)X, I, J, colw, Yt, s, sw, tj, per, nused, part, st));
+      else TR_TRY(tile_t((const float*)X, I, J, colw, Yt, s, sw, tj, per, nused, part, st));
+    } else {
+      const int64_t nparts = gram_parts(J);
+      const int64_t chunk = cdiv(J, nparts);
+      nused = cdiv(J, chunk);
+      TR_TRY(launch_ttm(f64, X, L, I, R, Yt, sw, sw, colw, Z, split, st));
+      if (f64) TR_TRY(gramb_t((const double*)X, L, I, R, Z, s, sw, nused, chunk, part, st));
+      else TR_TRY(gramb_t((const float*)X, L, I, R, Z, s, sw, nused, chunk, part, st));
+    }
     hipLaunchKernelGGL(trk::k_reduce_parts, dim3((unsigned)cdiv(I * s, kNT)), dim3(kNT), 0, st,
-                       part, nused, I, (int)s, Y, Yt, status);
+                       part, nused, I, (int)s, sw, Y, Yt, status);
     TR_TRY(check_launch());
   }
   return TR_OK;
 }
 
-template <int RPT, int SM>
-void factor_k(const double* C, int I, int s, int mu, double* Q, double* Qt, double* sig,
-              void* Qcast, int cast_f32, uint32_t* status, hipStream_t st) {
-  hipLaunchKernelGGL((trk::k_factor<RPT, SM>), dim3(1), dim3(trk::kFactorNT), 0, st, C, I, s,
-                     mu, Q, Qt, sig, Qcast, cast_f32, status);
+template <int SM, bool G>
+int factor_k(const double* C, int I, int s, int mu, double* Q, double* Qt, int ldqt, double* sig,
+             void* Qcast, int cast_f32, uint32_t* status, double* gA, hipStream_t st) {
+  const size_t lds = trk::FactorShape<SM>::lds_bytes(I, s, mu, G);
+  if (lds > 65536 &&
+      hipFuncSetAttribute((const void*)&trk::k_factor<SM, G>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return TR_EDEVICE;
+  hipLaunchKernelGGL((trk::k_factor<SM, G>), dim3(1), dim3(trk::kFactorNT), lds, st, C, I, s,
+                     mu, Q, Qt, ldqt, sig, Qcast, cast_f32, status, gA, Q);
+  return check_launch();
 }
 
+// Q (I x mu, float64), Qt (row stride ldqt, zero padding), sigma, optional
+// cast copy of Q in the caller's dtype.  gA: I x s float64 scratch, needed
+// only when the working matrices do not fit in LDS (may equal C).
 int launch_factor(const double* C, int64_t I, int64_t s, int64_t mu, double* Q, double* Qt,
-                  double* sig, void* Qcast, int cast_f32, uint32_t* status, hipStream_t st) {
+                  int ldqt, double* sig, void* Qcast, int cast_f32, uint32_t* status,
+                  double* gA, hipStream_t st) {
   if (!factor_supported(I, s) || mu < 1 || mu > s) return TR_ENOTSUP;
-  const int64_t rpt = cdiv(I, trk::kFactorNT);
+  const bool lds = factor_in_lds(I, s, mu);
+  if (!lds && !gA) return TR_ENOMEM;
   const int sm = factor_sm(s);
   const int Ii = (int)I, si = (int)s, mi = (int)mu;
-  if (rpt == 1 && sm == 16) factor_k<1, 16>(C, Ii, si, mi, Q, Qt, sig, Qcast, cast_f32, status, st);
-  else if (rpt == 1 && sm == 32) factor_k<1, 32>(C, Ii, si, mi, Q, Qt, sig, Qcast, cast_f32, status, st);
-  else if (rpt == 1 && sm == 64) factor_k<1, 64>(C, Ii, si, mi, Q, Qt, sig, Qcast, cast_f32, status, st);
-  else if (rpt == 2 && sm == 16) factor_k<2, 16>(C, Ii, si, mi, Q, Qt, sig, Qcast, cast_f32, status, st);
-  else if (rpt == 2 && sm == 32) factor_k<2, 32>(C, Ii, si, mi, Q, Qt, sig, Qcast, cast_f32, status, st);
-  else if (rpt <= 4 && sm == 16) factor_k<4, 16>(C, Ii, si, mi, Q, Qt, sig, Qcast, cast_f32, status, st);
-  else return TR_ENOTSUP;
-  return check_launch();
+  if (lds) {
+    if (sm == 16) return factor_k<16, false>(C, Ii, si, mi, Q, Qt, ldqt, sig, Qcast, cast_f32, status, nullptr, st);
+    if (sm == 32) return factor_k<32, false>(C, Ii, si, mi, Q, Qt, ldqt, sig, Qcast, cast_f32, status, nullptr, st);
+    return factor_k<64, false>(C, Ii, si, mi, Q, Qt, ldqt, sig, Qcast, cast_f32, status, nullptr, st);
+  }
+  if (sm == 16) return factor_k<16, true>(C, Ii, si, mi, Q, Qt, ldqt, sig, Qcast, cast_f32, status, gA, st);
+  if (sm == 32) return factor_k<32, true>(C, Ii, si, mi, Q, Qt, ldqt, sig, Qcast, cast_f32, status, gA, st);
+  return factor_k<64, true>(C, Ii, si, mi, Q, Qt, ldqt, sig, Qcast, cast_f32, status, gA, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -426,7 +619,7 @@ int range_finder(const Plan& P, int n, const void* X, void* ws, void* Qout,
   double* part = at<double>(ws, P.oPart);
   {
     TimeScope ts(tm, TR_KC_GAUSSIAN, n, st);
-    TR_TRY(launch_gaussian(G, Yt, M.I, M.s, n, P.seed, st));
+    TR_TRY(launch_gaussian(G, Yt, M.I, M.s, M.sw, n, P.seed, st));
   }
   const void* src = X;
   bool src_f64 = M.src_f64;
@@ -462,18 +655,20 @@ int range_finder(const Plan& P, int n, const void* X, void* ws, void* Qout,
     R = M.T;
     colw = scale2;
   }
-  // C_n = (M M^T)^q G_n, starting from Y = G_n (Yt already holds G_n^T).
+  // C_n = (M M^T)^q G_n, starting from Yt = G_n^T.
   {
     TimeScope ts(tm, TR_KC_POWER, n, st);
-    TR_TRY(run_power(src_f64, src, L, M.I, R, colw, P.q, M.s, Y, Yt, Z, part, status, st));
+    TR_TRY(run_power(src_f64, src, L, M.I, R, colw, P.q, M.s, M.sw, Y, Yt, Z, part,
+                     at<double>(ws, P.oSplit), status, st));
   }
   if (diag && diag->sketch && diag->sketch[n])
     TR_TRY(copy_d2d(diag->sketch[n], Y, 8 * (size_t)(M.I * M.s), st));
   double* sig = (diag && diag->sigma && diag->sigma[n]) ? diag->sigma[n] : at<double>(ws, P.oSig);
   {
     TimeScope ts(tm, TR_KC_FACTOR, n, st);
+    // the sketch Y is dead after this call: it doubles as the factor's scratch
     TR_TRY(launch_factor(Y, M.I, M.s, M.mu, at<double>(ws, P.oQ[n]), at<double>(ws, P.oQt[n]),
-                         sig, Qout, P.dtype == TR_F32, status, st));
+                         M.muw, sig, Qout, P.dtype == TR_F32, status, Y, st));
   }
   return TR_OK;
 }
@@ -488,31 +683,21 @@ int check_buffers(const Plan& P, const void* A, void* const* Q, const void* core
   return TR_OK;
 }
 
-// Shrink chain X x_n Q_n^T over modes [n0, N): intermediates in float64
-// workspace buffers, the last one written to `core` in the caller's dtype.
-int core_chain(const Plan& P, const void* X, bool x_f64, int n0, const int64_t* shape_in,
-               void* ws, void* core, const tr_diag* diag, hipStream_t st) {
-  int64_t shp[TR_MAX_ORDER];
-  for (int k = 0; k < P.N; ++k) shp[k] = shape_in[k];
-  const void* cur = X;
-  bool cur_f64 = x_f64;
-  tr_timer* tm = diag ? diag->timer : nullptr;
-  for (int n = n0; n < P.N; ++n) {
-    int64_t L = 1, R = 1;
-    for (int k = 0; k < n; ++k) L *= shp[k];
-    for (int k = n + 1; k < P.N; ++k) R *= shp[k];
-    const bool last = n == P.N - 1;
-    void* out = last ? core : at<void>(ws, ((n - n0) % 2 == 0) ? P.oX0 : P.oX1);
-    const bool out_f64 = last ? (P.dtype == TR_F64) : true;
-    {
-      TimeScope ts(tm, TR_KC_TTM, n, st);
-      TR_TRY(launch_ttm(cur_f64, cur, L, shp[n], R, at<double>(ws, P.oQt[n]), P.m[n].mu,
-                        nullptr, out_f64, out, st));
-    }
-    shp[n] = P.m[n].mu;
-    cur = out;
-    cur_f64 = true;
+// One shrink X x_n Q_n^T of the chain; the last one goes through the float64
+// core buffer and is cast into the caller's core.
+int shrink(const Plan& P, int n, int step, const void* cur, bool cur_f64, int64_t L,
+           int64_t I, int64_t R, void* ws, void* core, tr_timer* tm, void** out,
+           hipStream_t st) {
+  const ModePlan& M = P.m[n];
+  const bool last = n == P.N - 1;
+  double* dst = at<double>(ws, last ? P.oCore : ((step % 2 == 0) ? P.oX0 : P.oX1));
+  {
+    TimeScope ts(tm, TR_KC_TTM, n, st);
+    TR_TRY(launch_ttm(cur_f64, cur, L, I, R, at<double>(ws, P.oQt[n]), M.muw, (int)M.mu,
+                      nullptr, dst, at<double>(ws, P.oSplit), st));
   }
+  if (last) TR_TRY(launch_cast(dst, L * M.mu * R, P.dtype == TR_F32, core, st));
+  *out = dst;
   return TR_OK;
 }
 
@@ -522,7 +707,22 @@ int run_thosvd(const tr_params* p, int dtype, const void* A, void* const* Q, voi
   TR_TRY(make_plan(p, dtype, false, &P));
   TR_TRY(check_buffers(P, A, Q, core, ws, ws_bytes));
   for (int n = 0; n < P.N; ++n) TR_TRY(range_finder(P, n, A, ws, Q[n], diag, st));
-  return core_chain(P, A, dtype == TR_F64, 0, P.dims, ws, core, diag, st);
+  int64_t shp[TR_MAX_ORDER];
+  for (int k = 0; k < P.N; ++k) shp[k] = P.dims[k];
+  const void* cur = A;
+  bool cur_f64 = dtype == TR_F64;
+  tr_timer* tm = diag ? diag->timer : nullptr;
+  for (int n = 0; n < P.N; ++n) {
+    int64_t L = 1, R = 1;
+    for (int k = 0; k < n; ++k) L *= shp[k];
+    for (int k = n + 1; k < P.N; ++k) R *= shp[k];
+    void* out = nullptr;
+    TR_TRY(shrink(P, n, n, cur, cur_f64, L, shp[n], R, ws, core, tm, &out, st));
+    shp[n] = P.m[n].mu;
+    cur = out;
+    cur_f64 = true;
+  }
+  return TR_OK;
 }
 
 int run_sthosvd(const tr_params* p, int dtype, const void* A, void* const* Q, void* core,
@@ -530,23 +730,14 @@ int run_sthosvd(const tr_params* p, int dtype, const void* A, void* const* Q, vo
   Plan P;
   TR_TRY(make_plan(p, dtype, true, &P));
   TR_TRY(check_buffers(P, A, Q, core, ws, ws_bytes));
-  int64_t shp[TR_MAX_ORDER];
-  for (int k = 0; k < P.N; ++k) shp[k] = P.dims[k];
   const void* cur = A;
   bool cur_f64 = dtype == TR_F64;
   tr_timer* tm = diag ? diag->timer : nullptr;
   for (int n = 0; n < P.N; ++n) {
     TR_TRY(range_finder(P, n, cur, ws, Q[n], diag, st));
     const ModePlan& M = P.m[n];
-    const bool last = n == P.N - 1;
-    void* out = last ? core : at<void>(ws, (n % 2 == 0) ? P.oX0 : P.oX1);
-    const bool out_f64 = last ? (dtype == TR_F64) : true;
-    {
-      TimeScope ts(tm, TR_KC_TTM, n, st);
-      TR_TRY(launch_ttm(cur_f64, cur, M.L, M.I, M.R, at<double>(ws, P.oQt[n]), M.mu, nullptr,
-                        out_f64, out, st));
-    }
-    shp[n] = M.mu;
+    void* out = nullptr;
+    TR_TRY(shrink(P, n, n, cur, cur_f64, M.L, M.I, M.R, ws, core, tm, &out, st));
     cur = out;
     cur_f64 = true;
   }
@@ -597,7 +788,7 @@ int tucker_rand_sthosvd(const tr_params* p, int dtype, const void* A, void* cons
 int tucker_rand_gaussian(int64_t I, int64_t s, int32_t mode, uint64_t seed, double* G,
                          void* stream) {
   if (I < 1 || s < 1 || !G || mode < 0) return TR_EINVAL;
-  return launch_gaussian(G, nullptr, I, s, mode, seed, (hipStream_t)stream);
+  return launch_gaussian(G, nullptr, I, s, s, mode, seed, (hipStream_t)stream);
 }
 
 int tucker_rand_colnorms(int dtype, const void* X, int64_t L, int64_t I, int64_t R,
@@ -643,9 +834,10 @@ int tucker_rand_gather(int dtype, const void* X, int64_t L, int64_t I, int64_t R
   return launch_gather(dtype == TR_F64, X, L, I, idx, T, Cp, (hipStream_t)stream);
 }
 
-size_t tucker_rand_power_workspace_size(int64_t L, int64_t I, int64_t R, int64_t s) {
-  if (L < 1 || I < 1 || R < 1 || s < 1) return 0;
-  return power_ws_bytes(L, I, R, s);
+size_t tucker_rand_power_workspace_size(int dtype, int64_t L, int64_t I, int64_t R,
+                                        int64_t s) {
+  if (L < 1 || I < 1 || R < 1 || s < 1 || s > 64) return 0;
+  return power_ws_bytes(L, I, R, s, dtype == TR_F64);
 }
 
 int tucker_rand_power(int dtype, const void* X, int64_t L, int64_t I, int64_t R,
@@ -655,38 +847,59 @@ int tucker_rand_power(int dtype, const void* X, int64_t L, int64_t I, int64_t R,
       s < 1 || q < 1)
     return TR_EINVAL;
   if (s > 64) return TR_ENOTSUP;
-  if (!workspace || workspace_bytes < power_ws_bytes(L, I, R, s)) return TR_ENOMEM;
+  const bool f64 = dtype == TR_F64;
+  if (!workspace || workspace_bytes < power_ws_bytes(L, I, R, s, f64)) return TR_ENOMEM;
   hipStream_t st = (hipStream_t)stream;
   const int64_t J = L * R;
+  const int sw = pad_width(s);
   char* ws = (char*)workspace;
   double* Z = (double*)ws;
-  double* part = (double*)(ws + align_up(8 * (size_t)(J * s)));
-  double* Yt = (double*)(ws + align_up(8 * (size_t)(J * s)) +
-                         align_up(8 * (size_t)(gram_parts(J) * I * s)));
-  hipLaunchKernelGGL(trk::k_transpose, dim3((unsigned)cdiv(I * s, kNT)), dim3(kNT), 0, st, G, I,
-                     s, Yt);
+  double* part = (double*)(ws + align_up(8 * (size_t)(J * sw)));
+  double* Yt = (double*)(ws + align_up(8 * (size_t)(J * sw)) +
+                         align_up(8 * (size_t)(power_parts(L, I, J, s, f64) * I * s)));
+  hipLaunchKernelGGL(trk::k_transpose, dim3((unsigned)cdiv(I * sw, kNT)), dim3(kNT), 0, st, G, I,
+                     s, (int64_t)sw, Yt);
   TR_TRY(check_launch());
-  return run_power(dtype == TR_F64, X, L, I, R, colweight, q, s, C, Yt, Z, part, nullptr, st);
+  return run_power(f64, X, L, I, R, colweight, q, s, sw, C, Yt, Z, part, nullptr, nullptr, st);
+}
+
+size_t tucker_rand_factor_workspace_size(int64_t I, int64_t s, int64_t mu) {
+  if (I < 1 || s < 1 || s > 64 || mu < 1 || mu > s) return 0;
+  return factor_in_lds(I, s, mu) ? 0 : 8 * (size_t)(I * s);
 }
 
 int tucker_rand_factor(const double* C, int64_t I, int64_t s, int64_t mu, double* Q,
-                       double* sigma, void* stream) {
+                       double* sigma, void* workspace, size_t workspace_bytes, void* stream) {
   if (!C || !Q || I < 1 || s < 1 || s > I || mu < 1 || mu > s) return TR_EINVAL;
-  return launch_factor(C, I, s, mu, Q, nullptr, sigma, nullptr, 0, nullptr, (hipStream_t)stream);
+  if (s > 64) return TR_ENOTSUP;
+  const size_t need = tucker_rand_factor_workspace_size(I, s, mu);
+  if (need > 0 && (!workspace || workspace_bytes < need)) return TR_ENOMEM;
+  return launch_factor(C, I, s, mu, Q, nullptr, (int)mu, sigma, nullptr, 0, nullptr,
+                       (double*)workspace, (hipStream_t)stream);
+}
+
+size_t tucker_rand_ttm_workspace_size(int64_t L, int64_t I, int64_t R, int64_t mu) {
+  if (L < 1 || I < 1 || R < 1 || mu < 1 || mu > 64) return 0;
+  return align_up(8 * (size_t)(I * pad_width(mu))) + align_up(8 * (size_t)(L * mu * R));
 }
 
 int tucker_rand_ttm(int in_dtype, const void* X, int64_t L, int64_t I, int64_t R,
-                    const double* Q, int64_t mu, double* Qt, int out_dtype, void* Y,
-                    void* stream) {
+                    const double* Q, int64_t mu, int out_dtype, void* Y, void* workspace,
+                    size_t workspace_bytes, void* stream) {
   if ((in_dtype != TR_F64 && in_dtype != TR_F32) || (out_dtype != TR_F64 && out_dtype != TR_F32))
     return TR_EINVAL;
-  if (!X || !Q || !Qt || !Y || L < 1 || I < 1 || R < 1 || mu < 1) return TR_EINVAL;
+  if (!X || !Q || !Y || L < 1 || I < 1 || R < 1 || mu < 1) return TR_EINVAL;
   if (mu > 64) return TR_ENOTSUP;
+  if (!workspace || workspace_bytes < tucker_rand_ttm_workspace_size(L, I, R, mu)) return TR_ENOMEM;
   hipStream_t st = (hipStream_t)stream;
-  hipLaunchKernelGGL(trk::k_transpose, dim3((unsigned)cdiv(I * mu, kNT)), dim3(kNT), 0, st, Q, I,
-                     mu, Qt);
+  const int w = pad_width(mu);
+  double* Qt = (double*)workspace;
+  double* Y64 = (double*)((char*)workspace + align_up(8 * (size_t)(I * w)));
+  hipLaunchKernelGGL(trk::k_transpose, dim3((unsigned)cdiv(I * w, kNT)), dim3(kNT), 0, st, Q, I,
+                     mu, (int64_t)w, Qt);
   TR_TRY(check_launch());
-  return launch_ttm(in_dtype == TR_F64, X, L, I, R, Qt, mu, nullptr, out_dtype == TR_F64, Y, st);
+  TR_TRY(launch_ttm(in_dtype == TR_F64, X, L, I, R, Qt, w, (int)mu, nullptr, Y64, nullptr, st));
+  return launch_cast(Y64, L * mu * R, out_dtype == TR_F32, Y, st);
 }
 
 int tucker_rand_timer_create(int capacity, uint32_t class_mask, tr_timer** out) {

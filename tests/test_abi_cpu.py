@@ -80,7 +80,7 @@ def test_null_pointers_rejected_before_launch():
     L = _abi.lib()
     assert L.tucker_rand_workspace_size(None, 0, 0, None) == _abi.TR_EINVAL
     assert L.tucker_rand_gaussian(4, 2, 0, 0, None, None) == _abi.TR_EINVAL
-    assert L.tucker_rand_factor(None, 4, 2, 1, None, None, None) == _abi.TR_EINVAL
+    assert L.tucker_rand_factor(None, 4, 2, 1, None, None, None, 0, None) == _abi.TR_EINVAL
     assert L.tucker_rand_sample(None, 10, 5, 1, 0, 0, None, None, None, 0, None, None) == \
         _abi.TR_EINVAL
     p, keep = tr._params((8, 8), (2, 2), 2, 1, "none", None, 0, "native")

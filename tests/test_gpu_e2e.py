@@ -68,7 +68,7 @@ def _compare(A, algo, ranks, K, q, prob="none", samples=None, seed=0, tol=None,
         else:
             assert _rel(Qg[n], Qo[n]) <= tol, (n, _rel(Qg[n], Qo[n]))
         gsig = _np(info["sigma"][n])
-        assert np.allclose(gsig, sig, rtol=1e-9 if not f32 else 1e-6,
+        assert np.allclose(gsig, sig, rtol=1e-9 if not f32 else 1e-4,
                            atol=1e-12 * sig[0]), n
         if prob != "none" and not infos[n]["exact"]:
             gi = _np(info["indices"][n])
