@@ -734,13 +734,14 @@ k_factor(const double* __restrict__ C, int I, int s, int mu, double* __restrict_
          double* __restrict__ gA, double* __restrict__ gZ) {
   using F = FactorShape<SM>;
   constexpr int NT = F::NT, NW = F::NW, LDR = F::LDR, H = SM / 2, HW = (H + NW - 1) / NW;
+  constexpr int CH = SM < 16 ? SM : 16;  // columns per register chunk
   extern __shared__ double smem[];
   double* sp = smem;
   double* A = kGlobal ? gA : sp;                    // I x s, column-major
   double* Z = kGlobal ? gZ : sp + (size_t)I * s;    // I x mu, column-major
   if (!kGlobal) sp += (size_t)I * (s + mu);
   double* M = sp;                  // R1^T, then X = R2^T (column c at M[c*LDR])
-  double* U = M + SM * LDR;        // leading left singular vectors of X
+  double* U = M + SM * LDR;        // R2^T while it is built, then U_X(:, 1:mu)
   double* scr = U + SM * LDR;      // NW x SM reduction scratch
   double* vec = scr + NW * SM;     // reduced vector
   double* tau = vec + SM;
@@ -751,28 +752,25 @@ k_factor(const double* __restrict__ C, int I, int s, int mu, double* __restrict_
   double* jn = sgn + SM;           // Jacobi column norms^2
   int* perm = reinterpret_cast<int*>(jn + SM);
   int* flag = reinterpret_cast<int*>(jn + 2 * SM);
-  // pair table of a sweep: pairs[step * (SM/2) + g] = p | q << 8
-  int* pairs = reinterpret_cast<int*>(jn + 2 * SM + 8);
+  int* pairs = reinterpret_cast<int*>(jn + 2 * SM + 8);  // p | q << 8 per (step, g)
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  const int s1 = s - 1, I1 = I - 1, mu1 = mu - 1;
 
   for (int e = tid; e < I * s; e += NT) A[e] = C[e];
   for (int e = tid; e < SM * LDR; e += NT) {
     M[e] = 0.0;
     U[e] = 0.0;
   }
+  for (int e = tid; e < (NW + 4) * SM; e += NT) scr[e] = 0.0;  // scr, vec, tau, rowk, vec2
   __syncthreads();
 
-  // Workgroup sum of part[j] (j < SM) into vec[]; two barriers.
-  auto vec_sum = [&](double (&part)[SM]) {
-    constexpr int CH = SM < 16 ? SM : 16;
-#pragma unroll
-    for (int c0 = 0; c0 < SM; c0 += CH) {
-      double v[CH];
-#pragma unroll
-      for (int q = 0; q < CH; ++q) v[q] = part[c0 + q];
-      const double r = wave_vec_sum<CH>(v, lane);
-      if (lane < CH) scr[wid * SM + c0 + wave_vec_index<CH>(lane)] = r;
-    }
+  // Chunk c0 of a workgroup vector sum: lane-wise partials part[q] (values
+  // c0 + q) go through the wave transpose-reduce into scr.
+  auto chunk_to_scr = [&](double (&part)[CH], int c0) {
+    const double r = wave_vec_sum<CH>(part, lane);
+    if (lane < CH) scr[wid * SM + c0 + wave_vec_index<CH>(lane)] = r;
+  };
+  auto finish_sum = [&]() {  // scr -> vec, two barriers
     __syncthreads();
     if (tid < SM) {
       double t = 0.0;
@@ -785,24 +783,30 @@ k_factor(const double* __restrict__ C, int I, int s, int mu, double* __restrict_
 
   // ---- 1. Householder QR of C: v_k = 1, H_k = I - tau_k v v^T ----
   for (int k = 0; k < s; ++k) {
-    const double* xk = A + (size_t)k * I;
-    const double alpha = xk[k];
-    if (tid < s) rowk[tid] = tid > k ? A[(size_t)tid * I + k] : 0.0;
-    double part[SM];
+    const double alpha = A[(size_t)k * I + k];
+    if (tid < SM) rowk[tid] = A[(size_t)min(tid, s1) * I + k];
+    // pass 1: part[k] = sum_{i>k} x_i^2, part[j] = sum_{i>k} x_i a_ij (j > k);
+    // chunks holding only columns j < k or j >= s are skipped
 #pragma unroll
-    for (int j = 0; j < SM; ++j) part[j] = 0.0;
-    for (int i = tid; i < I; i += NT) {
-      if (i > k) {
-        const double x = xk[i];
-        double av[SM];
+    for (int c0 = 0; c0 < SM; c0 += CH) {
+      if (c0 + CH <= k || c0 >= s) continue;
+      double part[CH];
 #pragma unroll
-        for (int j = 0; j < SM; ++j)  // clamped column: every load in bounds
-          av[j] = A[(size_t)min(j, s - 1) * I + i] * ((j > k && j < s) ? 1.0 : 0.0);
+      for (int q = 0; q < CH; ++q) part[q] = 0.0;
+      for (int i = tid; i < I; i += NT) {
+        const double x = A[(size_t)k * I + i] * (i > k ? 1.0 : 0.0);
+        double av[CH];
 #pragma unroll
-        for (int j = 0; j < SM; ++j) part[j] += (j == k ? x : av[j]) * x;
+        for (int q = 0; q < CH; ++q) av[q] = A[(size_t)min(c0 + q, s1) * I + i];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+          const int j = c0 + q;
+          part[q] += x * (j == k ? x : (j > k && j < s ? av[q] : 0.0));
+        }
       }
+      chunk_to_scr(part, c0);
     }
-    vec_sum(part);
+    finish_sum();
     const double sum2 = vec[k];
     double beta, tk, inv;
     if (sum2 == 0.0) {
@@ -814,42 +818,55 @@ k_factor(const double* __restrict__ C, int I, int s, int mu, double* __restrict_
       tk = (beta - alpha) / beta;
       inv = 1.0 / (alpha - beta);
     }
-    for (int i = tid; i < I; i += NT) {
-      if (i > k) {
-        const double v = xk[i] * inv;
+    // pass 2: a_ij -= tau v_i w_j with w_j = a_kj + inv * vec[j]; v_i into column k
 #pragma unroll
-        for (int j = 0; j < SM; ++j)
-          if (j > k && j < s) A[(size_t)j * I + i] -= tk * v * (rowk[j] + inv * vec[j]);
-        A[(size_t)k * I + i] = v;
+    for (int c0 = 0; c0 < SM; c0 += CH) {
+      if (c0 + CH <= k + 1 || c0 >= s) continue;
+      double w[CH];
+#pragma unroll
+      for (int q = 0; q < CH; ++q) w[q] = rowk[c0 + q] + inv * vec[c0 + q];
+      for (int i = tid; i < I; i += NT) {
+        const double v = A[(size_t)k * I + i] * inv;
+        double av[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) av[q] = A[(size_t)min(c0 + q, s1) * I + i];
+        if (i > k) {
+#pragma unroll
+          for (int q = 0; q < CH; ++q) {
+            const int j = c0 + q;
+            if (j > k && j < s) A[(size_t)j * I + i] = av[q] - tk * v * w[q];
+          }
+        }
       }
     }
-    if (tid == 0) {
-      tau[k] = tk;
-      M[k * LDR + k] = beta;  // M = R1^T: M(j, k) = R1(k, j)
-      for (int j = k + 1; j < s; ++j) M[k * LDR + j] = rowk[j] - tk * (rowk[j] + inv * vec[j]);
-    }
+    for (int i = tid; i < I; i += NT)
+      if (i > k) A[(size_t)k * I + i] *= inv;
+    // R1 row k -> column k of M = R1^T
+    if (tid < s) M[k * LDR + tid] = tid == k ? beta
+                                   : (tid > k ? rowk[tid] - tk * (rowk[tid] + inv * vec[tid]) : 0.0);
+    if (tid == 0) tau[k] = tk;
     __syncthreads();
   }
 
-  // ---- 2. QR of M = R1^T (s x s) by wave 0, lane = row; X = R2^T ----
+  // ---- 2. QR of M = R1^T (s x s) by wave 0, lane = row; U = R2^T ----
   if (wid == 0) {
+    const int ln = min(lane, s1);
     for (int k = 0; k < s; ++k) {
-      const double mk = lane < s ? M[k * LDR + min(lane, s - 1)] : 0.0;  // my entry of column k
       const double alpha = M[k * LDR + k];
-      double part[SM];
-#pragma unroll
-      for (int j = 0; j < SM; ++j) {
-        const double mij = M[min(j, s - 1) * LDR + min(lane, s - 1)] *
-                           ((lane > k && lane < s && j > k && j < s) ? 1.0 : 0.0);
-        part[j] = (j == k) ? ((lane > k && lane < s) ? mk * mk : 0.0) : mk * mij;
-      }
-      constexpr int CH = SM < 16 ? SM : 16;
+      const double mk = M[k * LDR + ln] * (lane > k && lane < s ? 1.0 : 0.0);
 #pragma unroll
       for (int c0 = 0; c0 < SM; c0 += CH) {
-        double v[CH];
+        if (c0 + CH <= k || c0 >= s) continue;
+        double part[CH];
+        double mv[CH];
 #pragma unroll
-        for (int q = 0; q < CH; ++q) v[q] = part[c0 + q];
-        const double r = wave_vec_sum<CH>(v, lane);
+        for (int q = 0; q < CH; ++q) mv[q] = M[min(c0 + q, s1) * LDR + ln];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+          const int j = c0 + q;
+          part[q] = mk * (j == k ? mk : (j > k && j < s ? mv[q] : 0.0));
+        }
+        const double r = wave_vec_sum<CH>(part, lane);
         if (lane < CH) vec2[c0 + wave_vec_index<CH>(lane)] = r;
       }
       lds_fence();
@@ -864,21 +881,33 @@ k_factor(const double* __restrict__ C, int I, int s, int mu, double* __restrict_
         tk = (beta - alpha) / beta;
         inv = 1.0 / (alpha - beta);
       }
-      // w_j = M(k, j) + inv * d_j; rows i > k updated, row k becomes R2(k, :)
-      if (lane > k && lane < s) {
-        const double v = mk * inv;
-        for (int j = k + 1; j < s; ++j)
-          M[j * LDR + lane] -= tk * v * (M[j * LDR + k] + inv * vec2[j]);
+      // R2 row k (lane j holds entry j), read before rows > k change
+      const double mkj = M[ln * LDR + k];
+      const double r2 = lane == k ? beta
+                        : (lane > k && lane < s ? mkj - tk * (mkj + inv * vec2[ln]) : 0.0);
+      // rows i > k: M(i, j) -= tau v_i w_j, w_j = M(k, j) + inv vec2[j]
+      const double v = mk * inv;
+#pragma unroll
+      for (int c0 = 0; c0 < SM; c0 += CH) {
+        if (c0 + CH <= k + 1 || c0 >= s) continue;
+        double mv[CH], wk[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+          mv[q] = M[min(c0 + q, s1) * LDR + ln];
+          wk[q] = M[min(c0 + q, s1) * LDR + k] + inv * vec2[c0 + q];
+        }
+        if (lane > k && lane < s) {
+#pragma unroll
+          for (int q = 0; q < CH; ++q) {
+            const int j = c0 + q;
+            if (j > k && j < s) M[j * LDR + lane] = mv[q] - tk * v * wk[q];
+          }
+        }
       }
-      lds_fence();
-      if (lane == 0) {
-        U[k * LDR + k] = beta;   // U holds X = R2^T for now: X(j, k) = R2(k, j)
-        for (int j = k + 1; j < s; ++j)
-          U[k * LDR + j] = M[j * LDR + k] - tk * (M[j * LDR + k] + inv * vec2[j]);
-      }
+      if (lane < s) U[k * LDR + lane] = r2;   // X(j, k) = R2(k, j)
       lds_fence();
     }
-    // X = R2^T as the Jacobi matrix: copy U -> M (column c of X at M[c*LDR])
+    // X = R2^T becomes the Jacobi matrix
     for (int e = lane; e < SM * LDR; e += kWave) {
       M[e] = U[e];
       U[e] = 0.0;
@@ -890,6 +919,8 @@ k_factor(const double* __restrict__ C, int I, int s, int mu, double* __restrict_
   {
     const int se = s + (s & 1);
     const int np = se / 2;
+    const int np1 = np - 1;
+    const int ln = min(lane, s1);
     const double tol = 2.0 * s * 2.220446049250313e-16;
     for (int e = tid; e < (se - 1) * np; e += NT) {
       int pp, qq;
@@ -897,8 +928,7 @@ k_factor(const double* __restrict__ C, int I, int s, int mu, double* __restrict_
       pairs[(e / np) * H + (e % np)] = pp | (qq << 8);
     }
     for (int sweep = 0; sweep < 40 && se > 1; ++sweep) {
-      // exact column norms at the start of every sweep; updated per rotation
-      if (tid < se) {
+      if (tid < se) {  // exact column norms at the start of every sweep
         double a = 0.0;
         for (int i = 0; i < s; ++i) a += M[tid * LDR + i] * M[tid * LDR + i];
         jn[tid] = a;
@@ -906,40 +936,42 @@ k_factor(const double* __restrict__ C, int I, int s, int mu, double* __restrict_
       if (tid == 0) *flag = 0;
       __syncthreads();
       for (int step = 0; step < se - 1; ++step) {
-        double xs[HW], ys[HW], cc[HW];
+        double xs[HW], ys[HW], cc[HW], aa[HW], bb[HW];
         int ps[HW], qs[HW];
 #pragma unroll
         for (int h = 0; h < HW; ++h) {
           const int g = wid + NW * h;
-          const int pq = g < np ? pairs[step * H + g] : 0;
+          const int pq = pairs[step * H + min(g, np1)];
           ps[h] = pq & 0xff;
           qs[h] = pq >> 8;
-          xs[h] = (g < np && lane < s) ? M[ps[h] * LDR + lane] : 0.0;
-          ys[h] = (g < np && lane < s) ? M[qs[h] * LDR + lane] : 0.0;
-          cc[h] = xs[h] * ys[h];
         }
 #pragma unroll
-        for (int h = 0; h < HW; ++h) cc[h] = wave_sum(cc[h]);
+        for (int h = 0; h < HW; ++h) {
+          xs[h] = M[ps[h] * LDR + ln];
+          ys[h] = M[qs[h] * LDR + ln];
+          aa[h] = jn[ps[h]];
+          bb[h] = jn[qs[h]];
+        }
+#pragma unroll
+        for (int h = 0; h < HW; ++h) cc[h] = wave_sum(lane < s ? xs[h] * ys[h] : 0.0);
 #pragma unroll
         for (int h = 0; h < HW; ++h) {
           const int g = wid + NW * h;
-          if (g < np) {
-            const double a = jn[ps[h]], b = jn[qs[h]];
-            if (cc[h] != 0.0 && fabs(cc[h]) > tol * sqrt(a) * sqrt(b)) {
-              const double zeta = (b - a) / (2.0 * cc[h]);
-              const double t =
-                  (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-              const double cs = 1.0 / sqrt(1.0 + t * t);
-              const double sn = cs * t;
-              if (lane < s) {
-                M[ps[h] * LDR + lane] = cs * xs[h] - sn * ys[h];
-                M[qs[h] * LDR + lane] = sn * xs[h] + cs * ys[h];
-              }
-              if (lane == 0) {
-                jn[ps[h]] = a - t * cc[h];
-                jn[qs[h]] = b + t * cc[h];
-                *flag = 1;
-              }
+          const double a = aa[h], b = bb[h], c = cc[h];
+          if (g < np && c != 0.0 && fabs(c) > tol * sqrt(a) * sqrt(b)) {
+            const double zeta = (b - a) / (2.0 * c);
+            const double t =
+                (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double cs = 1.0 / sqrt(1.0 + t * t);
+            const double sn = cs * t;
+            if (lane < s) {
+              M[ps[h] * LDR + lane] = cs * xs[h] - sn * ys[h];
+              M[qs[h] * LDR + lane] = sn * xs[h] + cs * ys[h];
+            }
+            if (lane == 0) {
+              jn[ps[h]] = a - t * c;
+              jn[qs[h]] = b + t * c;
+              *flag = 1;
             }
           }
         }
@@ -981,33 +1013,44 @@ k_factor(const double* __restrict__ C, int I, int s, int mu, double* __restrict_
   // ---- 5. Z = H_0 ... H_{s-1} [U; 0] ----
   for (int e = tid; e < I * mu; e += NT) {
     const int c = e / I, i = e % I;
-    Z[e] = i < s ? U[c * LDR + i] : 0.0;
+    Z[e] = i < s ? U[c * LDR + min(i, s1)] : 0.0;
   }
   __syncthreads();
   for (int k = s - 1; k >= 0; --k) {
     const double tk = tau[k];
-    const double* vk = A + (size_t)k * I;
-    double part[SM];
 #pragma unroll
-    for (int c = 0; c < SM; ++c) part[c] = 0.0;
-    for (int i = tid; i < I; i += NT) {
-      if (i >= k) {
-        const double v = i == k ? 1.0 : vk[i];
-        double zv[SM];
+    for (int c0 = 0; c0 < SM; c0 += CH) {
+      if (c0 >= mu) continue;
+      double part[CH];
 #pragma unroll
-        for (int c = 0; c < SM; ++c)
-          zv[c] = Z[(size_t)min(c, mu - 1) * I + i] * (c < mu ? 1.0 : 0.0);
+      for (int q = 0; q < CH; ++q) part[q] = 0.0;
+      for (int i = tid; i < I; i += NT) {
+        const double v = i == k ? 1.0 : A[(size_t)k * I + i] * (i > k ? 1.0 : 0.0);
+        double zv[CH];
 #pragma unroll
-        for (int c = 0; c < SM; ++c) part[c] += v * zv[c];
+        for (int q = 0; q < CH; ++q) zv[q] = Z[(size_t)min(c0 + q, mu1) * I + i];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) part[q] += v * (c0 + q < mu ? zv[q] : 0.0);
       }
+      chunk_to_scr(part, c0);
     }
-    vec_sum(part);
-    for (int i = tid; i < I; i += NT) {
-      if (i >= k) {
-        const double v = i == k ? 1.0 : vk[i];
+    finish_sum();
 #pragma unroll
-        for (int c = 0; c < SM; ++c)
-          if (c < mu) Z[(size_t)c * I + i] -= tk * v * vec[c];
+    for (int c0 = 0; c0 < SM; c0 += CH) {
+      if (c0 >= mu) continue;
+      double w[CH];
+#pragma unroll
+      for (int q = 0; q < CH; ++q) w[q] = tk * vec[c0 + q];
+      for (int i = tid; i < I; i += NT) {
+        const double v = i == k ? 1.0 : A[(size_t)k * I + i] * (i > k ? 1.0 : 0.0);
+        double zv[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) zv[q] = Z[(size_t)min(c0 + q, mu1) * I + i];
+        if (i >= k) {
+#pragma unroll
+          for (int q = 0; q < CH; ++q)
+            if (c0 + q < mu) Z[(size_t)(c0 + q) * I + i] = zv[q] - v * w[q];
+        }
       }
     }
   }
@@ -1018,7 +1061,7 @@ k_factor(const double* __restrict__ C, int I, int s, int mu, double* __restrict_
     double best = -1.0, bval = 0.0;
     for (int i0 = 0; i0 < I; i0 += kWave) {
       const int i = i0 + lane;
-      const double z = i < I ? Z[(size_t)c * I + i] : 0.0;
+      const double z = Z[(size_t)c * I + min(i, I1)];
       const double az = i < I ? fabs(z) : -1.0;
       const double m = wave_max(az);
       if (m > best) {
@@ -1033,9 +1076,9 @@ k_factor(const double* __restrict__ C, int I, int s, int mu, double* __restrict_
   __syncthreads();
   for (int e = tid; e < I * ldqt; e += NT) {
     const int i = e / ldqt, c = e % ldqt;
-    double z = 0.0;
+    const double zz = Z[(size_t)min(c, mu1) * I + i] * sgn[min(c, mu1)];
+    const double z = c < mu ? zz : 0.0;
     if (c < mu) {
-      z = Z[(size_t)c * I + i] * sgn[c];
       Q[i + (int64_t)I * c] = z;
       if (Qcast) {
         if (cast_f32) ((float*)Qcast)[i + (int64_t)I * c] = (float)z;
