@@ -1,0 +1,445 @@
+// Register-resident factor kernel: Q_n = the mu leading left singular vectors
+// of the sketch C (I x s, float64), with the same decomposition as k_factor
+// (Householder QR of C, QR of R1^T, one-sided Jacobi on X = R2^T, Q_n =
+// Q1 [U_X(:, 1:mu); 0]) but laid out for instruction count rather than for
+// generality.  Thread t of the 256-thread workgroup keeps rows t and t + 256
+// of C (and later of Q_n) in VGPRs; every column index is a compile-time
+// constant (the column loops are instantiated per step), so nothing is
+// indexed dynamically.  Workgroup sums go through one LDS tile of per-thread
+// partials read back by 256/SM lanes per value and finished with DPP.
+// Supports s <= 32, I <= 512 (mu <= MU).
+#pragma once
+
+#include <type_traits>
+
+#include "tr_device.hpp"
+#include "tr_kernels.hpp"
+
+namespace trk {
+
+template <int SM>
+struct RfShape {
+  static constexpr int NT = 256;
+  static constexpr int SEG = NT / SM;      // reducer lanes per value
+  static constexpr int SEGLEN = NT / SEG;  // partial rows summed by one reducer lane
+  static constexpr int PS = SM + 2;        // partial row stride (16-byte aligned rows)
+  static constexpr int JW = kWave / SEG;   // values covered by one wave of reducers
+  static constexpr int LDX = SM + 1;       // column stride of X and U
+  // Segment g starts JW doubles after the end of segment g-1: the reducers of
+  // one wave (JW values x SEG segments) then spread over all 32 banks, and
+  // segments never overlap.
+  __host__ __device__ static constexpr int poff(int g) { return g * JW; }
+  static constexpr int kP = NT * PS + SEG * JW;
+  static constexpr int kTotal = kP + 2 * SM * LDX + 6 * SM + 16;  // doubles
+  static constexpr size_t lds_bytes() { return 8 * (size_t)kTotal; }
+};
+
+template <int K, int END>
+struct StaticFor {
+  template <class F>
+  __device__ __forceinline__ static void run(F& f) {
+    if constexpr (K < END) {
+      f(std::integral_constant<int, K>{});
+      StaticFor<K + 1, END>::run(f);
+    }
+  }
+};
+
+struct RfSum {
+  static constexpr double kId = 0.0;
+  __device__ static double f(double a, double b) { return a + b; }
+};
+struct RfMax {
+  static constexpr double kId = 0.0;  // operands are magnitudes
+  __device__ static double f(double a, double b) { return fmax(a, b); }
+};
+struct RfMin {
+  static constexpr double kId = 1.0e300;
+  __device__ static double f(double a, double b) { return fmin(a, b); }
+};
+
+// Combine over SEG consecutive lanes (SEG in {4, 8, 16}); every lane of the
+// group ends with the same value.  Must run with the whole wave active.
+template <int SEG, class Op>
+__device__ __forceinline__ double seg_reduce(double v) {
+  v = Op::f(v, dpp_f64<kDppQuadXor1>(v));
+  v = Op::f(v, dpp_f64<kDppQuadXor2>(v));
+  if constexpr (SEG >= 8) v = Op::f(v, dpp_f64<kDppRowHalfMirror>(v));
+  if constexpr (SEG >= 16) v = Op::f(v, dpp_f64<kDppRowMirror>(v));
+  return v;
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// vec[j] = Op over the 256 threads of p[j], for J0 <= j < jend (jend <= N).
+// Every thread must call it (two barriers).  Entries p[j] with j < J0 are not
+// read; the caller keeps them initialised.
+template <int SM, int N, int J0, class Op>
+__device__ __forceinline__ void rf_reduce(const double (&p)[N], int jend, double* P,
+                                          double* vec, int tid) {
+  using S = RfShape<SM>;
+  static_assert(N % 2 == 0 && N <= SM, "partials per thread");
+  const int prow = tid * S::PS + S::poff(tid / S::SEGLEN);
+  constexpr int JA = J0 & ~1;
+#pragma unroll
+  for (int j = JA; j < N; j += 2) {
+    if (j < jend) {
+      double2 v;
+      v.x = p[j];
+      v.y = p[j + 1];
+      *reinterpret_cast<double2*>(P + prow + j) = v;
+    }
+  }
+  __syncthreads();
+  const int rj = tid / S::SEG, rg = tid % S::SEG;
+  const bool mine = rj >= J0 && rj < jend;
+  double acc = Op::kId;
+  if (mine) {
+    const double* src = P + rg * S::SEGLEN * S::PS + S::poff(rg) + rj;
+    double a0 = src[0], a1 = src[S::PS];
+#pragma unroll
+    for (int t = 2; t < S::SEGLEN; t += 2) {
+      a0 = Op::f(a0, src[t * S::PS]);
+      a1 = Op::f(a1, src[(t + 1) * S::PS]);
+    }
+    acc = Op::f(a0, a1);
+  }
+  acc = seg_reduce<S::SEG, Op>(acc);
+  if (mine && rg == 0) vec[rj] = acc;
+  __syncthreads();
+}
+
+// Householder reflector for (alpha, sum of squares below): beta, tau and the
+// scale inv = 1 / (alpha - beta) of the vector below the unit entry.
+__device__ __forceinline__ void householder(double alpha, double sum2, double* beta,
+                                            double* tau, double* inv) {
+  if (sum2 == 0.0) {
+    *beta = alpha;
+    *tau = 0.0;
+    *inv = 0.0;
+  } else {
+    const double b = -copysign(sqrt(alpha * alpha + sum2), alpha);
+    *beta = b;
+    *tau = (b - alpha) / b;
+    *inv = 1.0 / (alpha - b);
+  }
+}
+
+template <int SM, int R, int MU>
+__global__ void __launch_bounds__(256)
+k_factor_rf(const double* __restrict__ C, int I, int s, int mu, double* __restrict__ Q,
+            double* __restrict__ Qt, int ldqt, double* __restrict__ sig_out,
+            void* __restrict__ Qcast, int cast_f32, uint32_t* __restrict__ status) {
+  using S = RfShape<SM>;
+  constexpr int NT = S::NT, LDX = S::LDX;
+  static_assert(MU <= SM && MU % 8 == 0, "column bound");
+  extern __shared__ double smem[];
+  double* P = smem;
+  double* X = P + S::kP;         // Jacobi matrix, column c at X[c * LDX]
+  double* U = X + SM * LDX;      // U_X(:, 1:mu)
+  double* vec = U + SM * LDX;    // reduced values
+  double* rowk = vec + SM;       // row k of the current step, double-buffered
+  double* tau = rowk + 2 * SM;
+  double* sig = tau + SM;
+  int* perm = reinterpret_cast<int*>(sig + SM);
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  const int s1 = s - 1, I1 = I - 1;
+
+  double a[R][SM];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = tid + NT * r;
+#pragma unroll
+    for (int j = 0; j < SM; ++j) {
+      const double v = C[(size_t)min(j, s1) * I + min(i, I1)];
+      a[r][j] = (i < I && j < s) ? v : 0.0;
+    }
+  }
+  for (int e = tid; e < SM * LDX; e += NT) X[e] = 0.0;
+  if (tid < SM) vec[tid] = 0.0;
+  __syncthreads();
+
+  // ---- 1. Householder QR of C; v_k (unit entry implied) overwrites column k
+  //         below the diagonal, R1 stays on and above it ----
+  auto qr_step = [&](auto kc) __attribute__((always_inline)) {
+    constexpr int k = decltype(kc)::value;
+    if (k >= s) return;
+    double* rk = rowk + (k & 1) * SM;
+    if (tid == k) {
+#pragma unroll
+      for (int j = k; j < SM; ++j) rk[j] = a[0][j];
+    }
+    double x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[r] = tid + NT * r > k ? a[r][k] : 0.0;
+    double p[SM];
+#pragma unroll
+    for (int j = 0; j < SM; ++j) {
+      double t = 0.0;
+      if (j >= k) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) t = fma(x[r], a[r][j], t);
+      }
+      p[j] = t;
+    }
+    rf_reduce<SM, SM, k, RfSum>(p, s, P, vec, tid);
+    double beta, tk, inv;
+    householder(rk[k], vec[k], &beta, &tk, &inv);
+    double tv[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = tid + NT * r;
+      tv[r] = tk * (i > k ? inv * a[r][k] : (i == k ? 1.0 : 0.0));
+    }
+#pragma unroll
+    for (int c0 = 0; c0 < SM; c0 += 8) {
+      if (c0 + 8 > k + 1 && c0 < s) {
+#pragma unroll
+        for (int j = c0 > k ? c0 : k + 1; j < c0 + 8; ++j) {
+          const double w = rk[j] + inv * vec[j];
+#pragma unroll
+          for (int r = 0; r < R; ++r) a[r][j] = fma(-tv[r], w, a[r][j]);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = tid + NT * r;
+      a[r][k] = i > k ? inv * a[r][k] : (i == k ? beta : a[r][k]);
+    }
+    if (tid == 0) tau[k] = tk;
+  };
+  StaticFor<0, SM>::run(qr_step);
+
+  // ---- 2. QR of M = R1^T by wave 0: lane j holds column j of M (row j of
+  //         R1, in thread j's registers); column k is broadcast by readlane ----
+  if (wid == 0) {
+    double m[SM];
+#pragma unroll
+    for (int i = 0; i < SM; ++i) m[i] = (i >= lane && i < s) ? a[0][i] : 0.0;
+    auto lq_step = [&](auto kc) __attribute__((always_inline)) {
+      constexpr int k = decltype(kc)::value;
+      if (k >= s) return;
+      double xs[SM];
+      double pj = 0.0;
+#pragma unroll
+      for (int c0 = 0; c0 < SM; c0 += 8) {
+        if (c0 + 8 > k + 1 && c0 < s) {
+#pragma unroll
+          for (int i = c0 > k ? c0 : k + 1; i < c0 + 8; ++i) {
+            xs[i] = readlane_f64(m[i], k);
+            pj = fma(xs[i], m[i], pj);
+          }
+        }
+      }
+      const double alpha = readlane_f64(m[k], k);
+      const double sum2 = readlane_f64(pj, k);
+      double beta, tk, inv;
+      householder(alpha, sum2, &beta, &tk, &inv);
+      const double w = m[k] + inv * pj;
+      const double tw = tk * w;
+#pragma unroll
+      for (int c0 = 0; c0 < SM; c0 += 8) {
+        if (c0 + 8 > k + 1 && c0 < s) {
+#pragma unroll
+          for (int i = c0 > k ? c0 : k + 1; i < c0 + 8; ++i) m[i] = fma(-(inv * xs[i]), tw, m[i]);
+        }
+      }
+      m[k] = lane == k ? beta : m[k] - tw;
+    };
+    StaticFor<0, SM>::run(lq_step);
+    // X(j, c) = R2(c, j) for c <= j: lane j writes row j
+    if (lane < SM) {
+#pragma unroll
+      for (int c = 0; c < SM; ++c) X[c * LDX + lane] = (c <= lane && lane < s) ? m[c] : 0.0;
+    }
+  }
+  __syncthreads();
+
+  // ---- 3. one-sided Jacobi on the columns of X: pair g on DPP row g / 4 of
+  //         wave g % 4, 16 lanes per pair, rows l16 + 16 u ----
+  {
+    constexpr int RU = SM / 16;
+    const int se = s + (s & 1), np = se / 2, sm1 = se - 1;
+    const int l16 = lane & 15;
+    const int g = (lane >> 4) * 4 + wid;
+    const bool gact = g < np;
+    const int gg = gact ? g : 0;
+    const double tol = 2.0 * s * 2.220446049250313e-16;
+    for (int sweep = 0; sweep < 40 && se > 1; ++sweep) {
+      int rot = 0;
+      // circle method: position 0 fixed, positions 1..se-1 advance each step
+      int pp = gg == 0 ? -1 : gg - 1;  // -1: the fixed position
+      int qq = se - 2 - gg;
+      for (int step = 0; step < sm1; ++step) {
+        const int p0 = pp < 0 ? 0 : pp + 1, q0 = qq + 1;
+        const int p = min(p0, q0), q = max(p0, q0);
+        double xv[RU], yv[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+          xv[u] = X[p * LDX + l16 + 16 * u];
+          yv[u] = X[q * LDX + l16 + 16 * u];
+        }
+        double aa = 0.0, bb = 0.0, cc = 0.0;
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+          aa = fma(xv[u], xv[u], aa);
+          bb = fma(yv[u], yv[u], bb);
+          cc = fma(xv[u], yv[u], cc);
+        }
+        aa = seg_reduce<16, RfSum>(aa);
+        bb = seg_reduce<16, RfSum>(bb);
+        cc = seg_reduce<16, RfSum>(cc);
+        if (gact && cc != 0.0 && fabs(cc) > tol * sqrt(aa) * sqrt(bb)) {
+          const double zeta = (bb - aa) / (2.0 * cc);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + t * t);
+          const double sn = cs * t;
+#pragma unroll
+          for (int u = 0; u < RU; ++u) {
+            X[p * LDX + l16 + 16 * u] = cs * xv[u] - sn * yv[u];
+            X[q * LDX + l16 + 16 * u] = sn * xv[u] + cs * yv[u];
+          }
+          rot = 1;
+        }
+        __syncthreads();
+        if (pp >= 0) pp = pp + 1 == sm1 ? 0 : pp + 1;
+        qq = qq + 1 == sm1 ? 0 : qq + 1;
+      }
+      if (!__syncthreads_or(rot)) break;
+    }
+  }
+
+  // ---- 4. singular values, descending (ties: lower column first) ----
+  if (tid < s) {
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < SM; ++i) t = fma(X[tid * LDX + i], X[tid * LDX + i], t);
+    sig[tid] = sqrt(t);
+  }
+  __syncthreads();
+  if (tid < s) {
+    const double me = sig[tid];
+    int rank = 0;
+    for (int q = 0; q < s; ++q) {
+      const double o = sig[q];
+      rank += (o > me || (o == me && q < tid)) ? 1 : 0;
+    }
+    perm[rank] = tid;
+    if (sig_out) sig_out[rank] = me;
+    if (!isfinite(me) && status) atomicOr(status, kDevNonFinite);
+  }
+  if (tid < SM) vec[tid] = 0.0;
+  __syncthreads();
+  for (int e = tid; e < mu * SM; e += NT) {
+    const int c = e / SM, i = e % SM;
+    const int pc = perm[c];
+    const double sg = sig[pc];
+    const double xv = X[pc * LDX + i];
+    U[c * LDX + i] = i >= s ? 0.0 : (sg > 0.0 ? xv / sg : (i == pc ? 1.0 : 0.0));
+  }
+  __syncthreads();
+
+  // ---- 5. Z = H_0 ... H_{s-1} [U; 0], reflectors applied last-first ----
+  double z[R][MU];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = tid + NT * r;
+#pragma unroll
+    for (int c = 0; c < MU; ++c) {
+      const double u = U[min(c, mu - 1) * LDX + min(i, SM - 1)];
+      z[r][c] = (i < s && c < mu) ? u : 0.0;
+    }
+  }
+  auto q_step = [&](auto kc) __attribute__((always_inline)) {
+    constexpr int k = SM - 1 - decltype(kc)::value;
+    if (k >= s) return;
+    double v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = tid + NT * r;
+      v[r] = i > k ? a[r][k] : (i == k ? 1.0 : 0.0);
+    }
+    double p[MU];
+#pragma unroll
+    for (int c = 0; c < MU; ++c) {
+      double t = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) t = fma(v[r], z[r][c], t);
+      p[c] = t;
+    }
+    rf_reduce<SM, MU, 0, RfSum>(p, mu, P, vec, tid);
+    const double tk = tau[k];
+#pragma unroll
+    for (int c0 = 0; c0 < MU; c0 += 8) {
+      if (c0 < mu) {
+#pragma unroll
+        for (int c = c0; c < c0 + 8; ++c) {
+          const double w = tk * vec[c];
+#pragma unroll
+          for (int r = 0; r < R; ++r) z[r][c] = fma(-v[r], w, z[r][c]);
+        }
+      }
+    }
+  };
+  StaticFor<0, SM>::run(q_step);
+
+  // ---- 6. sign: the largest-magnitude entry of each column (lowest row on
+  //         ties) becomes positive ----
+  {
+    double pm[MU];
+#pragma unroll
+    for (int c = 0; c < MU; ++c) {
+      double t = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) t = fmax(t, fabs(z[r][c]));
+      pm[c] = t;
+    }
+    rf_reduce<SM, MU, 0, RfMax>(pm, mu, P, vec, tid);
+#pragma unroll
+    for (int c = 0; c < MU; ++c) {
+      const double mx = vec[c];
+      double t = RfMin::kId;
+#pragma unroll
+      for (int r = R - 1; r >= 0; --r) {
+        const int i = tid + NT * r;
+        if (i < I && fabs(z[r][c]) == mx) t = 2.0 * i + (z[r][c] < 0.0 ? 1.0 : 0.0);
+      }
+      pm[c] = t;
+    }
+    rf_reduce<SM, MU, 0, RfMin>(pm, mu, P, vec, tid);
+  }
+  double sg[MU];
+#pragma unroll
+  for (int c = 0; c < MU; ++c) {
+    const double key = vec[c];
+    sg[c] = (key - 2.0 * floor(0.5 * key)) != 0.0 ? -1.0 : 1.0;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = tid + NT * r;
+    if (i < I) {
+#pragma unroll
+      for (int c = 0; c < MU; ++c) {
+        if (c < mu) {
+          const double zz = z[r][c] * sg[c];
+          Q[i + (int64_t)I * c] = zz;
+          if (Qcast) {
+            if (cast_f32) ((float*)Qcast)[i + (int64_t)I * c] = (float)zz;
+            else ((double*)Qcast)[i + (int64_t)I * c] = zz;
+          }
+          if (Qt) Qt[(int64_t)i * ldqt + c] = zz;
+        }
+      }
+      if (Qt)
+        for (int c = mu; c < ldqt; ++c) Qt[(int64_t)i * ldqt + c] = 0.0;
+    }
+  }
+}
+
+}  // namespace trk

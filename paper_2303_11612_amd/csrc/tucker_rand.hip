@@ -9,11 +9,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
 
 #include "tr_kernels.hpp"
+#include "tr_factor_rf.hpp"
 #include "tucker_rand.h"
 
 namespace {
@@ -569,6 +571,45 @@ int factor_k(const double* C, int I, int s, int mu, double* Q, double* Qt, int l
   return check_launch();
 }
 
+// TUCKER_RAND_FACTOR=lds selects the LDS-resident factor kernel for every
+// shape (both variants are then testable on the same inputs).
+inline bool force_lds_factor() {
+  const char* v = std::getenv("TUCKER_RAND_FACTOR");
+  return v != nullptr && std::strcmp(v, "lds") == 0;
+}
+
+template <int SM, int R, int MU>
+int factor_rf(const double* C, int I, int s, int mu, double* Q, double* Qt, int ldqt, double* sig,
+              void* Qcast, int cast_f32, uint32_t* status, hipStream_t st) {
+  const size_t lds = trk::RfShape<SM>::lds_bytes();
+  if (lds > 65536 &&
+      hipFuncSetAttribute((const void*)&trk::k_factor_rf<SM, R, MU>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return TR_EDEVICE;
+  hipLaunchKernelGGL((trk::k_factor_rf<SM, R, MU>), dim3(1), dim3(trk::RfShape<SM>::NT), lds, st,
+                     C, I, s, mu, Q, Qt, ldqt, sig, Qcast, cast_f32, status);
+  return check_launch();
+}
+
+// Register-resident variant: s <= 32, I <= 512, and mu <= 16 when I > 256
+// with s > 16.  Returns TR_ENOTSUP for shapes it does not cover.
+int launch_factor_rf(const double* C, int I, int s, int mu, double* Q, double* Qt, int ldqt,
+                     double* sig, void* Qcast, int cast_f32, uint32_t* status, hipStream_t st) {
+  if (I > 512 || s > 32) return TR_ENOTSUP;
+  const bool r1 = I <= 256;
+  if (s <= 16)
+    return r1 ? factor_rf<16, 1, 16>(C, I, s, mu, Q, Qt, ldqt, sig, Qcast, cast_f32, status, st)
+              : factor_rf<16, 2, 16>(C, I, s, mu, Q, Qt, ldqt, sig, Qcast, cast_f32, status, st);
+  if (r1) return factor_rf<32, 1, 32>(C, I, s, mu, Q, Qt, ldqt, sig, Qcast, cast_f32, status, st);
+  if (mu <= 16)
+    return factor_rf<32, 2, 16>(C, I, s, mu, Q, Qt, ldqt, sig, Qcast, cast_f32, status, st);
+  return TR_ENOTSUP;
+}
+
+inline bool factor_rf_covers(int64_t I, int64_t s, int64_t mu) {
+  return I <= 512 && s <= 32 && (I <= 256 || s <= 16 || mu <= 16);
+}
+
 // Q (I x mu, float64), Qt (row stride ldqt, zero padding), sigma, optional
 // cast copy of Q in the caller's dtype.  gA: I x s float64 scratch, needed
 // only when the working matrices do not fit in LDS (may equal C).
@@ -576,6 +617,9 @@ int launch_factor(const double* C, int64_t I, int64_t s, int64_t mu, double* Q, 
                   int ldqt, double* sig, void* Qcast, int cast_f32, uint32_t* status,
                   double* gA, hipStream_t st) {
   if (!factor_supported(I, s) || mu < 1 || mu > s) return TR_ENOTSUP;
+  if (factor_rf_covers(I, s, mu) && !force_lds_factor())
+    return launch_factor_rf(C, (int)I, (int)s, (int)mu, Q, Qt, ldqt, sig, Qcast, cast_f32, status,
+                            st);
   const bool lds = factor_in_lds(I, s, mu);
   if (!lds && !gA) return TR_ENOMEM;
   const int sm = factor_sm(s);

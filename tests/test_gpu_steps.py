@@ -154,10 +154,20 @@ def _graded(I, s, seed, decay=0.6):
     return np.asfortranarray(U @ np.diag(decay ** np.arange(s)) @ V.T)
 
 
+@pytest.fixture(params=["reg", "lds"])
+def factor_variant(request, monkeypatch):
+    """Both factor kernels: the register-resident one (default for s <= 32,
+    I <= 512) and the LDS-resident one (every shape when forced)."""
+    monkeypatch.setenv("TUCKER_RAND_FACTOR", request.param)
+    return request.param
+
+
 @pytest.mark.parametrize("I,s,mu", [(64, 10, 5), (400, 20, 10), (512, 40, 30), (100, 30, 20),
                                     (513, 16, 9), (1000, 24, 12), (2000, 12, 4), (7, 7, 7),
-                                    (1, 1, 1), (33, 1, 1), (96, 64, 40)])
-def test_factor_matches_svd(I, s, mu):
+                                    (1, 1, 1), (33, 1, 1), (96, 64, 40), (256, 16, 16),
+                                    (300, 16, 8), (256, 32, 32), (512, 32, 16), (400, 30, 20),
+                                    (257, 17, 16), (2, 2, 1), (40, 31, 3)])
+def test_factor_matches_svd(I, s, mu, factor_variant):
     C = _graded(I, s, I + s)
     Q, sig = tr.tucker_rand_factor(tr.to_device(C), mu)
     Q, sig = _np(Q), _np(sig)
@@ -173,7 +183,7 @@ def test_factor_matches_svd(I, s, mu):
         assert np.linalg.norm(Q[:, c] - Qo[:, c]) <= bound, (c, bound)
 
 
-def test_factor_of_strongly_graded_sketch():
+def test_factor_of_strongly_graded_sketch(factor_variant):
     # spectrum like C_n = (A A^T) G_n for the 400^3 tensor: 0.25^k, then a noise floor
     I, s, mu = 400, 20, 10
     rng = np.random.default_rng(3)
@@ -188,6 +198,26 @@ def test_factor_of_strongly_graded_sketch():
     for c in range(mu):   # column c is determined to ~u * sigma_1 / gap_c
         gap = min(so[c - 1] - so[c] if c else np.inf, so[c] - so[c + 1])
         assert np.linalg.norm(Q[:, c] - Qo[:, c]) <= 1e-14 * so[0] / gap + 1e-13
+
+
+@pytest.mark.parametrize("I,s,mu,rank", [(50, 10, 5, 3), (400, 20, 10, 0), (300, 24, 12, 7)])
+def test_factor_of_rank_deficient_sketch(I, s, mu, rank, factor_variant):
+    # sigma_rank.. are exactly zero: the trailing columns of Q_n are any
+    # orthonormal completion, so only the leading ones and orthonormality are compared
+    rng = np.random.default_rng(I + rank)
+    C = np.asfortranarray(rng.standard_normal((I, rank)) @ rng.standard_normal((rank, s))
+                          if rank else np.zeros((I, s)))
+    Q, sig = tr.tucker_rand_factor(tr.to_device(C), mu)
+    Q, sig = _np(Q), _np(sig)
+    Qo, so = oracle.leading_left_singular_vectors(C, mu)
+    assert np.all(np.isfinite(Q)) and np.all(np.isfinite(sig))
+    assert np.max(np.abs(Q.T @ Q - np.eye(mu))) < 1e-13
+    scale = so[0] if rank else 1.0
+    assert np.allclose(sig[:rank], so[:rank], rtol=1e-12)
+    assert np.all(np.abs(sig[rank:]) <= 1e-13 * scale)
+    for c in range(min(rank, mu)):
+        gap = min(so[c - 1] - so[c] if c else np.inf, so[c] - so[c + 1] if c + 1 < rank else so[c])
+        assert np.linalg.norm(Q[:, c] - Qo[:, c]) <= max(1e-10, 20 * 2.2e-16 * so[0] / gap)
 
 
 @pytest.mark.parametrize("in_dt", [np.float32, np.float64])
