@@ -54,14 +54,39 @@ constexpr uint64_t kTagSample = 1;
 // ---------------------------------------------------------------------------
 
 // Lane permutations through DPP (no LDS round trip).  A double moves as two
-// 32-bit halves with the same control word.
+// 32-bit halves with the same control word.  Lanes outside ROW_MASK keep
+// their own value (the "old" operand is the source itself, so no register
+// has to be cleared first).
 template <int CTRL, int ROW_MASK = 0xf, bool BOUND_CTRL = false>
 __device__ __forceinline__ double dpp_f64(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, ROW_MASK, 0xf,
-                                             BOUND_CTRL);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, BOUND_CTRL);
+  const int l = (int)(b & 0xffffffff), h = (int)(b >> 32);
+  const int lo = __builtin_amdgcn_update_dpp(l, l, CTRL, ROW_MASK, 0xf, BOUND_CTRL);
+  const int hi = __builtin_amdgcn_update_dpp(h, h, CTRL, ROW_MASK, 0xf, BOUND_CTRL);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Reciprocal and reciprocal square root for arguments in a moderate range
+// (callers scale by powers of two first): the hardware estimate refined by
+// two Newton-Raphson steps, r <- r + r (1 - x r) and y <- y + y (1 - x y^2) / 2,
+// each of which squares the relative error.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return y;
+}
+// sqrt(x) = x / sqrt(x), with one Newton correction s <- s + (x - s^2) / (2 s).
+__device__ __forceinline__ double sqrt_nr(double x) {
+  const double y = rsqrt_nr(x);
+  const double s = x * y;
+  return fma(fma(-s, s, x), 0.5 * y, s);
 }
 
 // DPP control words (GFX9 encoding).

@@ -101,13 +101,15 @@ __device__ __forceinline__ void rf_reduce(const double (&p)[N], int jend, double
   double acc = Op::kId;
   if (mine) {
     const double* src = P + rg * S::SEGLEN * S::PS + S::poff(rg) + rj;
-    double a0 = src[0], a1 = src[S::PS];
+    double a0 = src[0], a1 = src[S::PS], a2 = src[2 * S::PS], a3 = src[3 * S::PS];
 #pragma unroll
-    for (int t = 2; t < S::SEGLEN; t += 2) {
+    for (int t = 4; t < S::SEGLEN; t += 4) {
       a0 = Op::f(a0, src[t * S::PS]);
       a1 = Op::f(a1, src[(t + 1) * S::PS]);
+      a2 = Op::f(a2, src[(t + 2) * S::PS]);
+      a3 = Op::f(a3, src[(t + 3) * S::PS]);
     }
-    acc = Op::f(a0, a1);
+    acc = Op::f(Op::f(a0, a1), Op::f(a2, a3));
   }
   acc = seg_reduce<S::SEG, Op>(acc);
   if (mine && rg == 0) vec[rj] = acc;
@@ -150,15 +152,21 @@ k_factor_rf(const double* __restrict__ C, int I, int s, int mu, double* __restri
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
   const int s1 = s - 1, I1 = I - 1;
 
+  // all loads first from clamped addresses, then the masks (a select on a
+  // loaded value would let the compiler branch around, and wait on, each load)
   double a[R][SM];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int ic = min(tid + NT * r, I1);
+#pragma unroll
+    for (int j = 0; j < SM; ++j) a[r][j] = C[(size_t)min(j, s1) * I + ic];
+  }
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int i = tid + NT * r;
 #pragma unroll
-    for (int j = 0; j < SM; ++j) {
-      const double v = C[(size_t)min(j, s1) * I + min(i, I1)];
-      a[r][j] = (i < I && j < s) ? v : 0.0;
-    }
+    for (int j = 0; j < SM; ++j) a[r][j] *= (i < I && j < s) ? 1.0 : 0.0;
   }
   for (int e = tid; e < SM * LDX; e += NT) X[e] = 0.0;
   if (tid < SM) vec[tid] = 0.0;
@@ -295,10 +303,18 @@ k_factor_rf(const double* __restrict__ C, int I, int s, int mu, double* __restri
         aa = seg_reduce<16, RfSum>(aa);
         bb = seg_reduce<16, RfSum>(bb);
         cc = seg_reduce<16, RfSum>(cc);
-        if (gact && cc != 0.0 && fabs(cc) > tol * sqrt(aa) * sqrt(bb)) {
-          const double zeta = (bb - aa) / (2.0 * cc);
-          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double cs = 1.0 / sqrt(1.0 + t * t);
+        // threshold on |x.y| / (|x| |y|); an estimate of the norms suffices
+        if (gact && cc != 0.0 &&
+            fabs(cc) * __builtin_amdgcn_rsq(aa) * __builtin_amdgcn_rsq(bb) > tol) {
+          // tan(theta) = sign(d) e / (|d| + hypot(d, e)) with d = |y|^2 - |x|^2,
+          // e = 2 x.y; d and e are first scaled by a common power of two into
+          // [1/2, 1) so that every operand below is of moderate size
+          double d = bb - aa, e = 2.0 * cc;
+          const int ex = max(__builtin_amdgcn_frexp_exp(d), __builtin_amdgcn_frexp_exp(e));
+          d = ldexp(d, -ex);
+          e = ldexp(e, -ex);
+          const double t = copysign(1.0, d) * e * rcp_nr(fabs(d) + sqrt_nr(fma(d, d, e * e)));
+          const double cs = rsqrt_nr(fma(t, t, 1.0));
           const double sn = cs * t;
 #pragma unroll
           for (int u = 0; u < RU; ++u) {

@@ -501,160 +501,6 @@ k_sum_splits(const double* __restrict__ part, int64_t nsplit, int64_t L, int64_t
   Y[l + L * (k + (int64_t)kout * r)] = acc;
 }
 
-// ---------------------------------------------------------------------------
-// Second half of a power step on an L > 1 view, row-streaming:
-// part_b(i, k) = sum over the columns j of block b of X(i, j) Z(j, k), with Z
-// the L x SM x R output of k_ttm_ln (zero-padded to SM).  A workgroup stages
-// 32 consecutive l of 256 rows through LDS.  Partials are summed in a fixed
-// order by k_reduce_parts.
-// ---------------------------------------------------------------------------
-template <typename Tin, int SM>
-__global__ void __launch_bounds__(kNT)
-k_gramb_ln(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
-           const double* __restrict__ Z, int s, int64_t chunk, double* __restrict__ part) {
-  constexpr int TL = 32;
-  __shared__ Tin tile[TL][kNT + 1];
-  const int64_t J = L * R;
-  const int64_t ja = (int64_t)blockIdx.x * chunk;
-  const int64_t jb = min(J, ja + chunk);
-  double* out = part + (int64_t)blockIdx.x * I * s;
-  for (int64_t ib = 0; ib < I; ib += kNT) {
-    const int64_t i = ib + threadIdx.x;
-    double acc[SM];
-#pragma unroll
-    for (int k = 0; k < SM; ++k) acc[k] = 0.0;
-    for (int64_t j = ja; j < jb;) {
-      const int64_t r = j / L, l0 = j - r * L;
-      const int tl = (int)min((int64_t)TL, min(L - l0, jb - j));
-      {
-        Tin v[TL];
-        bool ok[TL];
-#pragma unroll
-        for (int m = 0; m < TL; ++m) {
-          const int e = threadIdx.x + kNT * m;
-          const int ll = e % TL, ii = e / TL;
-          ok[m] = ll < tl && ib + ii < I;
-          v[m] = X[ok[m] ? l0 + ll + L * (ib + ii + I * r) : 0];
-        }
-#pragma unroll
-        for (int m = 0; m < TL; ++m) {
-          const int e = threadIdx.x + kNT * m;
-          if (ok[m]) tile[e % TL][e / TL] = v[m];
-        }
-      }
-      __syncthreads();
-      for (int ll = 0; ll < tl; ++ll) {
-        const double x = (double)tile[ll][threadIdx.x];
-        const double* z = Z + (l0 + ll) + L * (int64_t)SM * r;
-#pragma unroll
-        for (int k = 0; k < SM; ++k) acc[k] = fma(x, z[L * k], acc[k]);
-      }
-      __syncthreads();
-      j += tl;
-    }
-    if (i < I) {
-#pragma unroll
-      for (int k = 0; k < SM; ++k)
-        if (k < s) out[i + I * k] = acc[k];
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Both halves of a power step for an L == 1 source (the gathered C' of the
-// sampled products, or a mode-1 unfolding), fused per column tile:
-//   W_b = D_b X_b^T Y   (tile of tj columns staged in LDS, Y read row-major)
-//   part += X_b W_b     (accumulated in registers across the tiles of a block)
-// RPT rows per thread (I <= 256 * RPT), SM >= s padded; one partial per block.
-// ---------------------------------------------------------------------------
-template <typename Tin, int SM, int RPT>
-__global__ void __launch_bounds__(kNT)
-k_gram_tile_l1(const Tin* __restrict__ X, int64_t I, int64_t J,
-               const double* __restrict__ colw, const double* __restrict__ Yt, int s,
-               int tj, int64_t tiles_per_block, double* __restrict__ part) {
-  extern __shared__ double gsm[];
-  double* Ys = gsm;                                     // I x SM (row-major copy of Y)
-  double* W = Ys + (size_t)I * SM;                      // tj x SM, row c at W[c*SM]
-  Tin* T = reinterpret_cast<Tin*>(W + (size_t)tj * SM); // I x tj, column-major
-  const int ldT = (int)(I | 1);  // odd column stride: phase-1 reads hit distinct banks
-  constexpr int KG = 4;                                 // outputs per phase-1 thread
-  constexpr int B = 8;                                  // loads in flight per thread
-  for (int64_t e = threadIdx.x; e < I * SM; e += kNT) Ys[e] = Yt[e];
-  double acc[RPT][SM];
-#pragma unroll
-  for (int p = 0; p < RPT; ++p)
-#pragma unroll
-    for (int k = 0; k < SM; ++k) acc[p][k] = 0.0;
-  const int64_t ntiles = (J + tj - 1) / tj;
-  const int64_t t0 = (int64_t)blockIdx.x * tiles_per_block;
-  const int64_t t1 = min(ntiles, t0 + tiles_per_block);
-  for (int64_t t = t0; t < t1; ++t) {
-    const int64_t c0 = t * tj;
-    const int nc = (int)min((int64_t)tj, J - c0);
-    const int64_t n = (int64_t)nc * I;
-    const Tin* src = X + c0 * I;                        // contiguous I*nc elements
-    for (int64_t e0 = 0; e0 < n; e0 += (int64_t)kNT * B) {
-      Tin v[B];
-#pragma unroll
-      for (int u = 0; u < B; ++u) v[u] = src[min(e0 + threadIdx.x + (int64_t)kNT * u, n - 1)];
-#pragma unroll
-      for (int u = 0; u < B; ++u) {
-        const int64_t e = e0 + threadIdx.x + (int64_t)kNT * u;
-        if (e < n) {
-          const int c = (int)(e / I), i = (int)(e - (int64_t)c * I);
-          T[c * ldT + i] = v[u];
-        }
-      }
-    }
-    __syncthreads();
-    // phase 1: thread (c, kg) forms W(c, 4kg .. 4kg+3) = d_c sum_i T(i, c) Y(i, .)
-    for (int e = threadIdx.x; e < nc * (SM / KG); e += kNT) {
-      const int c = e % nc, kg = e / nc;
-      const Tin* tc = T + c * ldT;
-      double w0 = 0, w1 = 0, w2 = 0, w3 = 0;
-      for (int64_t i = 0; i < I; ++i) {
-        const double x = (double)tc[i];
-        const double* y = Ys + i * SM + KG * kg;
-        w0 = fma(x, y[0], w0);
-        w1 = fma(x, y[1], w1);
-        w2 = fma(x, y[2], w2);
-        w3 = fma(x, y[3], w3);
-      }
-      const double d = colw ? colw[c0 + c] : 1.0;
-      double* wr = W + c * SM + KG * kg;
-      wr[0] = w0 * d;
-      wr[1] = w1 * d;
-      wr[2] = w2 * d;
-      wr[3] = w3 * d;
-    }
-    __syncthreads();
-    // phase 2: rows of this thread accumulate X_b W_b
-#pragma unroll
-    for (int p = 0; p < RPT; ++p) {
-      const int64_t i = threadIdx.x + (int64_t)kNT * p;
-      if (i < I) {
-        for (int c = 0; c < nc; ++c) {
-          const double x = (double)T[c * ldT + i];
-          const double* wr = W + c * SM;
-#pragma unroll
-          for (int k = 0; k < SM; ++k) acc[p][k] = fma(x, wr[k], acc[p][k]);
-        }
-      }
-    }
-    __syncthreads();
-  }
-  double* out = part + (int64_t)blockIdx.x * I * s;
-#pragma unroll
-  for (int p = 0; p < RPT; ++p) {
-    const int64_t i = threadIdx.x + (int64_t)kNT * p;
-    if (i < I) {
-#pragma unroll
-      for (int k = 0; k < SM; ++k)
-        if (k < s) out[i + I * k] = acc[p][k];
-    }
-  }
-}
-
 // Y(e) = sum_b part_b(e) in increasing b; also the row-major copy Yt (stride
 // ldyt >= s; its padding columns are left untouched, i.e. zero).
 __global__ void __launch_bounds__(kNT)

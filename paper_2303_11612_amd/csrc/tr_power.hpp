@@ -1,0 +1,206 @@
+// Power-scheme products C <- X_(n) D X_(n)^T C (Strategy A: two skinny
+// products per step) on the FP64 matrix cores.  v_mfma_f64_16x16x4f64 lane
+// layout (lane l = 16 * g + h, h = l % 16, g = l / 16):
+//   A (16 x 4): lane l holds A[h][g];  B (4 x 16): lane l holds B[g][h];
+//   D (16 x 16): lane l, item v holds D[g + 4 v][h].
+// The source is the L x I x R column-major view of a mode-n unfolding,
+// X_(n)(i, j) = X[l + L (i + I r)], j = l + L r (L == 1: a plain I x J
+// matrix such as the gathered C'_n).  Inputs in float32 are widened to
+// float64 on load; every product and sum is float64.  Sums run in a fixed
+// order, so results are bitwise reproducible.  Out-of-range operands are
+// loaded from a clamped (valid, finite) address and multiplied by 0, which
+// keeps every load unconditional: a select on a loaded value would let the
+// compiler turn the load into a branch that waits for it on its own.
+#pragma once
+
+#include "tr_device.hpp"
+
+namespace trk {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int kPwWaves = 4;
+constexpr int kPwBatch = 4;  // loop iterations whose loads are issued together
+
+// W(j, k) = d_j sum_i X_(n)(i, j) Y(i, k) for j < J, k < 16 NKT (row-major,
+// row stride 16 NKT; columns k >= s come out zero).  Y is read from its
+// row-major copy Yt (row stride sw >= s, zero padding).  Block: one tile of
+// 16 columns j; its four waves take interleaved quarters of the rows i and
+// their partial tiles are added in LDS (wave order 0..3).
+template <typename Tin, int NKT>
+__global__ void __launch_bounds__(kPwWaves * kWave)
+k_pw_w(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
+       const double* __restrict__ colw, const double* __restrict__ Yt, int sw,
+       double* __restrict__ W) {
+  constexpr int SP = 16 * NKT;
+  __shared__ f64x4 red[kPwWaves - 1][NKT][kWave];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int h = lane & 15, g = lane >> 4;
+  const int64_t J = L * R;
+  const int64_t j = (int64_t)blockIdx.x * 16 + h;
+  const bool jok = j < J;
+  const int64_t jc = jok ? j : J - 1;
+  const int64_t r = jc / L;
+  const Tin* xc = X + (jc - r * L) + L * I * r;  // X_(n)(i, jc) = xc[L i]
+  const int64_t nch = (I + 15) / 16;             // chunks of 16 rows
+  f64x4 acc[NKT];
+#pragma unroll
+  for (int kt = 0; kt < NKT; ++kt) acc[kt] = f64x4{0.0, 0.0, 0.0, 0.0};
+  // chunks wid, wid + 4, ...; kPwBatch of them have their loads in flight together
+  for (int64_t c0 = wid; c0 < nch; c0 += kPwWaves * kPwBatch) {
+    // all loads of the batch first (raw values), then masks and products
+    Tin xr[kPwBatch][4];
+    double yr[kPwBatch][4][NKT];
+#pragma unroll
+    for (int u = 0; u < kPwBatch; ++u) {
+      const int64_t c = c0 + kPwWaves * u;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        // rows 16c + 4g + t feed the t-th product of chunk c
+        const int64_t i = 16 * c + 4 * g + t;
+        const int64_t ic = i < I ? i : I - 1;
+        xr[u][t] = xc[L * ic];
+#pragma unroll
+        for (int kt = 0; kt < NKT; ++kt) {
+          const int k = 16 * kt + h;
+          yr[u][t][kt] = Yt[ic * sw + (k < sw ? k : sw - 1)];
+        }
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < kPwBatch; ++u)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const bool iok = 16 * (c0 + kPwWaves * u) + 4 * g + t < I;
+        const double b = (double)xr[u][t] * ((jok && iok) ? 1.0 : 0.0);
+#pragma unroll
+        for (int kt = 0; kt < NKT; ++kt) {
+          const double a = yr[u][t][kt] * ((iok && 16 * kt + h < sw) ? 1.0 : 0.0);
+          acc[kt] = mfma_f64(a, b, acc[kt]);
+        }
+      }
+  }
+  if (wid > 0) {
+#pragma unroll
+    for (int kt = 0; kt < NKT; ++kt) red[wid - 1][kt][lane] = acc[kt];
+  }
+  __syncthreads();
+  if (wid == 0 && jok) {
+    const double d = colw ? colw[j] : 1.0;
+#pragma unroll
+    for (int kt = 0; kt < NKT; ++kt) {
+      f64x4 v = acc[kt];
+#pragma unroll
+      for (int w = 0; w < kPwWaves - 1; ++w) v += red[w][kt][lane];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) W[j * SP + 16 * kt + g + 4 * q] = v[q] * d;
+    }
+  }
+}
+
+// part_b(i, k) = sum over the columns j of range b of X_(n)(i, j) W(j, k),
+// for i < I, k < s (column-major I x s per range).  Block (x, y): rows
+// 16 MT x .. 16 MT (x + 1), column range [y jper, (y + 1) jper); its four
+// waves take consecutive quarters of the range (multiples of 4 columns) and
+// their tiles are added in LDS (wave order 0..3).  The partial sums of the
+// ranges are added by k_reduce_parts in increasing b.
+template <typename Tin, int NKT, int MT>
+__global__ void __launch_bounds__(kPwWaves * kWave)
+k_pw_y(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
+       const double* __restrict__ W, int s, int64_t jper, double* __restrict__ part) {
+  constexpr int SP = 16 * NKT;
+  __shared__ f64x4 red[kPwWaves - 1][MT][NKT][kWave];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int h = lane & 15, g = lane >> 4;
+  const int64_t J = L * R, LI = L * I, nX = L * I * R;
+  const int64_t ib = (int64_t)blockIdx.x * 16 * MT;
+  const int64_t jb = (int64_t)blockIdx.y * jper, je = min(J, jb + jper);
+  const int64_t wq = ((je - jb + 4 * kPwWaves - 1) / (4 * kPwWaves)) * 4;
+  const int64_t ja = jb + wid * wq, jz = min(je, ja + wq);
+  int64_t roff[MT];
+  bool rok[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    const int64_t i = ib + 16 * mt + h;
+    rok[mt] = i < I;
+    roff[mt] = L * (rok[mt] ? i : I - 1);
+  }
+  f64x4 acc[MT][NKT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int kt = 0; kt < NKT; ++kt) acc[mt][kt] = f64x4{0.0, 0.0, 0.0, 0.0};
+  if (ja < jz) {
+    // this lane's column j = j0 + g, tracked as (l, r) without dividing;
+    // kPwBatch groups of 4 columns have their loads in flight together
+    int64_t r = (ja + g) / L, l = ja + g - r * L;
+    for (int64_t j0 = ja; j0 < jz; j0 += 4 * kPwBatch) {
+      // all loads of the batch first (raw values), then masks and products
+      Tin xr[kPwBatch][MT];
+      double wr[kPwBatch][NKT];
+#pragma unroll
+      for (int u = 0; u < kPwBatch; ++u) {
+        const int64_t j = j0 + 4 * u + g;
+        const int64_t base = l + LI * r;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const int64_t e = base + roff[mt];
+          xr[u][mt] = X[e < nX ? e : nX - 1];
+        }
+        const int64_t jw = j < jz ? j : jz - 1;
+#pragma unroll
+        for (int kt = 0; kt < NKT; ++kt) wr[u][kt] = W[jw * SP + 16 * kt + h];
+        l += 4;
+        while (l >= L) {
+          l -= L;
+          ++r;
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < kPwBatch; ++u) {
+        const bool jok = j0 + 4 * u + g < jz;
+        double a[MT], b[NKT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) a[mt] = (double)xr[u][mt] * ((jok && rok[mt]) ? 1.0 : 0.0);
+#pragma unroll
+        for (int kt = 0; kt < NKT; ++kt) b[kt] = wr[u][kt] * (jok ? 1.0 : 0.0);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+          for (int kt = 0; kt < NKT; ++kt) acc[mt][kt] = mfma_f64(a[mt], b[kt], acc[mt][kt]);
+      }
+    }
+  }
+  if (wid > 0) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int kt = 0; kt < NKT; ++kt) red[wid - 1][mt][kt][lane] = acc[mt][kt];
+  }
+  __syncthreads();
+  if (wid == 0) {
+    double* out = part + (int64_t)blockIdx.y * I * s;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int kt = 0; kt < NKT; ++kt) {
+        f64x4 v = acc[mt][kt];
+#pragma unroll
+        for (int w = 0; w < kPwWaves - 1; ++w) v += red[w][mt][kt][lane];
+        const int k = 16 * kt + h;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t i = ib + 16 * mt + g + 4 * q;
+          if (i < I && k < s) out[i + I * k] = v[q];
+        }
+      }
+  }
+}
+
+}  // namespace trk

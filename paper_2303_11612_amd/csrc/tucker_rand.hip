@@ -16,6 +16,7 @@
 
 #include "tr_kernels.hpp"
 #include "tr_factor_rf.hpp"
+#include "tr_power.hpp"
 #include "tucker_rand.h"
 
 namespace {
@@ -75,46 +76,21 @@ inline int pad_width(int64_t m) {
   return 0;
 }
 
-// Power steps on an L == 1 source use the fused tile kernel when a thread's
-// rows fit in registers; otherwise (and for L > 1) the two-kernel form.
-inline int tile_rpt(int64_t I) { return (int)cdiv(I, kNT); }
-inline bool tile_ok_lds(int64_t I, int64_t s, bool f64);
-inline bool tile_ok(int64_t I, int64_t s, bool f64) {
-  const int sm = pad_width(s);
-  const int rpt = tile_rpt(I);
-  return sm > 0 && rpt <= 4 && rpt * sm <= 64 && tile_ok_lds(I, s, f64);
-}
-// LDS of the tile kernel: Y (I x sm) + W (tj x sm) + tile (I x tj).
-inline int64_t tile_budget() { return 163840 - 1024; }
-inline bool tile_ok_lds(int64_t I, int64_t s, bool f64) {
-  const int sm = pad_width(s);
-  return 8 * I * sm + (8 * sm + (I | 1) * (f64 ? 8 : 4)) * 4 <= tile_budget();
-}
-inline int tile_cols(int64_t I, int64_t s, bool f64) {
-  const int sm = pad_width(s);
-  const int64_t per = 8 * sm + (I | 1) * (f64 ? 8 : 4);
-  return (int)std::max<int64_t>(1, std::min<int64_t>(64, (tile_budget() - 8 * I * sm) / per));
-}
-inline size_t tile_lds(int64_t I, int64_t s, int tj, bool f64) {
-  const int sm = pad_width(s);
-  return 8 * (size_t)(I * sm) + 8 * (size_t)tj * sm + (size_t)(I | 1) * tj * (f64 ? 8 : 4);
-}
-inline int64_t tile_blocks(int64_t J, int tj) {
-  return std::min<int64_t>(512, cdiv(J, tj));
-}
-inline int64_t gram_parts(int64_t jsrc) {
-  return std::min<int64_t>(256, std::max<int64_t>(1, cdiv(jsrc, 64)));
+// Power steps: k_pw_w (one block per 16 columns) then k_pw_y over row tiles
+// of 32 and pw_splits(I, J) column ranges, whose partial sketches
+// k_reduce_parts adds.  W is J x pw_width(s), row-major.
+inline int pw_nkt(int64_t s) { return (int)cdiv(s, 16); }
+inline int64_t pw_width(int64_t s) { return 16 * cdiv(s, 16); }
+constexpr int kPwMT = 2;
+inline int64_t pw_itiles(int64_t I) { return cdiv(I, 16 * kPwMT); }
+inline int64_t pw_splits(int64_t I, int64_t J) {
+  // about one block per compute unit, at least 64 columns per range
+  return std::max<int64_t>(1, std::min<int64_t>(cdiv(256, pw_itiles(I)), cdiv(J, 64)));
 }
 // Number of partial sketches a power step on this source produces.
-inline int64_t power_parts(int64_t L, int64_t I, int64_t J, int64_t s, bool f64) {
-  if (L == 1 && tile_ok(I, s, f64)) {
-    const int tj = tile_cols(I, s, f64);
-    const int64_t ntiles = cdiv(J, tj);
-    const int64_t per = cdiv(ntiles, tile_blocks(J, tj));
-    return cdiv(ntiles, per);
-  }
-  const int64_t nparts = gram_parts(J);
-  return cdiv(J, cdiv(J, nparts));
+inline int64_t power_parts(int64_t I, int64_t J) {
+  const int64_t ns = pw_splits(I, J);
+  return cdiv(J, cdiv(J, ns));
 }
 
 // Views with few columns split their rows over blocks (k_ttm_split) so that
@@ -231,13 +207,12 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
     const int64_t lsrc = M.sampled ? 1 : M.L;
     const bool fsrc = M.src_f64;
     maxIs = std::max(maxIs, (size_t)(M.I * M.sw));
-    if (!(lsrc == 1 && tile_ok(M.I, M.s, fsrc))) {
-      maxZ = std::max(maxZ, (size_t)(jsrc * M.sw));
-      maxSplit = std::max(maxSplit, (size_t)(ttm_splits(jsrc, M.I) * jsrc * M.sw));
-    }
+    (void)lsrc;
+    (void)fsrc;
+    maxZ = std::max(maxZ, (size_t)(jsrc * pw_width(M.s)));
     // the shrink of this mode reads the tensor the mode is computed from
     maxSplit = std::max(maxSplit, (size_t)(ttm_splits(M.J, M.I) * M.J * M.muw));
-    maxPart = std::max(maxPart, (size_t)(power_parts(lsrc, M.I, jsrc, M.s, fsrc) * M.I * M.s));
+    maxPart = std::max(maxPart, (size_t)(power_parts(M.I, jsrc) * M.I * M.s));
     maxS = std::max(maxS, M.s);
     if (M.sampled) {
       maxJs = std::max(maxJs, (size_t)M.J);
@@ -451,79 +426,40 @@ int launch_cast(const double* src, int64_t n, bool to_f32, void* dst, hipStream_
   return check_launch();
 }
 
-template <typename Tin, int SM>
-void gramb_w(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Z, int s,
-             int64_t nparts, int64_t chunk, double* part, hipStream_t st) {
-  hipLaunchKernelGGL((trk::k_gramb_ln<Tin, SM>), dim3((unsigned)nparts), dim3(kNT), 0, st, X, L,
-                     I, R, Z, s, chunk, part);
-}
-
-template <typename Tin>
-int gramb_t(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Z, int64_t s, int sw,
-            int64_t nparts, int64_t chunk, double* part, hipStream_t st) {
-  const int si = (int)s;
-  switch (sw) {
-    case 4: gramb_w<Tin, 4>(X, L, I, R, Z, si, nparts, chunk, part, st); break;
-    case 8: gramb_w<Tin, 8>(X, L, I, R, Z, si, nparts, chunk, part, st); break;
-    case 12: gramb_w<Tin, 12>(X, L, I, R, Z, si, nparts, chunk, part, st); break;
-    case 16: gramb_w<Tin, 16>(X, L, I, R, Z, si, nparts, chunk, part, st); break;
-    case 20: gramb_w<Tin, 20>(X, L, I, R, Z, si, nparts, chunk, part, st); break;
-    case 24: gramb_w<Tin, 24>(X, L, I, R, Z, si, nparts, chunk, part, st); break;
-    case 32: gramb_w<Tin, 32>(X, L, I, R, Z, si, nparts, chunk, part, st); break;
-    case 40: gramb_w<Tin, 40>(X, L, I, R, Z, si, nparts, chunk, part, st); break;
-    case 48: gramb_w<Tin, 48>(X, L, I, R, Z, si, nparts, chunk, part, st); break;
-    case 64: gramb_w<Tin, 64>(X, L, I, R, Z, si, nparts, chunk, part, st); break;
-    default: return TR_ENOTSUP;
-  }
+template <typename Tin, int NKT>
+int pw_step(const Tin* X, int64_t L, int64_t I, int64_t R, const double* colw, const double* Yt,
+            int sw, int s, double* W, double* part, int64_t* nparts, hipStream_t st) {
+  const int64_t J = L * R;
+  hipLaunchKernelGGL((trk::k_pw_w<Tin, NKT>), dim3((unsigned)cdiv(J, 16)),
+                     dim3(trk::kPwWaves * trk::kWave), 0, st, X, L, I, R, colw, Yt, sw, W);
+  TR_TRY(check_launch());
+  const int64_t jper = cdiv(J, pw_splits(I, J));
+  const int64_t ny = cdiv(J, jper);
+  hipLaunchKernelGGL((trk::k_pw_y<Tin, NKT, kPwMT>), dim3((unsigned)pw_itiles(I), (unsigned)ny),
+                     dim3(trk::kPwWaves * trk::kWave), 0, st, X, L, I, R, W, s, jper, part);
+  *nparts = ny;
   return check_launch();
 }
 
-template <typename Tin, int SM, int RPT>
-void tile_w(const Tin* X, int64_t I, int64_t J, const double* colw, const double* Yt, int s,
-            int tj, int64_t per, int64_t nblk, double* part, hipStream_t st) {
-  const size_t lds = tile_lds(I, s, tj, sizeof(Tin) == 8);
-  if (lds > 65536)
-    (void)hipFuncSetAttribute((const void*)&trk::k_gram_tile_l1<Tin, SM, RPT>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((trk::k_gram_tile_l1<Tin, SM, RPT>), dim3((unsigned)nblk), dim3(kNT), lds,
-                     st, X, I, J, colw, Yt, s, tj, per, part);
-}
-
-template <typename Tin, int SM>
-void tile_sm(const Tin* X, int64_t I, int64_t J, const double* colw, const double* Yt, int s,
-             int tj, int64_t per, int64_t nblk, double* part, hipStream_t st) {
-  switch (tile_rpt(I)) {
-    case 1: tile_w<Tin, SM, 1>(X, I, J, colw, Yt, s, tj, per, nblk, part, st); break;
-    case 2: if constexpr (SM <= 32) tile_w<Tin, SM, 2>(X, I, J, colw, Yt, s, tj, per, nblk, part, st); break;
-    case 3: if constexpr (SM <= 20) tile_w<Tin, SM, 3>(X, I, J, colw, Yt, s, tj, per, nblk, part, st); break;
-    default: if constexpr (SM <= 16) tile_w<Tin, SM, 4>(X, I, J, colw, Yt, s, tj, per, nblk, part, st); break;
-  }
-}
-
 template <typename Tin>
-int tile_t(const Tin* X, int64_t I, int64_t J, const double* colw, const double* Yt, int64_t s,
-           int sw, int tj, int64_t per, int64_t nblk, double* part, hipStream_t st) {
+int pw_step_t(const Tin* X, int64_t L, int64_t I, int64_t R, const double* colw,
+              const double* Yt, int sw, int64_t s, double* W, double* part, int64_t* nparts,
+              hipStream_t st) {
   const int si = (int)s;
-  switch (sw) {
-    case 4: tile_sm<Tin, 4>(X, I, J, colw, Yt, si, tj, per, nblk, part, st); break;
-    case 8: tile_sm<Tin, 8>(X, I, J, colw, Yt, si, tj, per, nblk, part, st); break;
-    case 12: tile_sm<Tin, 12>(X, I, J, colw, Yt, si, tj, per, nblk, part, st); break;
-    case 16: tile_sm<Tin, 16>(X, I, J, colw, Yt, si, tj, per, nblk, part, st); break;
-    case 20: tile_sm<Tin, 20>(X, I, J, colw, Yt, si, tj, per, nblk, part, st); break;
-    case 24: tile_sm<Tin, 24>(X, I, J, colw, Yt, si, tj, per, nblk, part, st); break;
-    case 32: tile_sm<Tin, 32>(X, I, J, colw, Yt, si, tj, per, nblk, part, st); break;
-    case 40: tile_sm<Tin, 40>(X, I, J, colw, Yt, si, tj, per, nblk, part, st); break;
-    case 48: tile_sm<Tin, 48>(X, I, J, colw, Yt, si, tj, per, nblk, part, st); break;
-    case 64: tile_sm<Tin, 64>(X, I, J, colw, Yt, si, tj, per, nblk, part, st); break;
+  switch (pw_nkt(s)) {
+    case 1: return pw_step<Tin, 1>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st);
+    case 2: return pw_step<Tin, 2>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st);
+    case 3: return pw_step<Tin, 3>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st);
+    case 4: return pw_step<Tin, 4>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st);
     default: return TR_ENOTSUP;
   }
-  return check_launch();
 }
 
 size_t power_ws_bytes(int64_t L, int64_t I, int64_t R, int64_t s, bool f64) {
+  (void)f64;
   const int64_t J = L * R;
   const int sw = pad_width(s);
-  return align_up(8 * (size_t)(J * sw)) + align_up(8 * (size_t)(power_parts(L, I, J, s, f64) * I * s)) +
+  return align_up(8 * (size_t)(J * pw_width(s))) + align_up(8 * (size_t)(power_parts(I, J) * I * s)) +
          align_up(8 * (size_t)(I * sw));
 }
 
@@ -531,26 +467,11 @@ size_t power_ws_bytes(int64_t L, int64_t I, int64_t R, int64_t s, bool f64) {
 // Yt = G^T (row stride sw, zero-padded).  Z, part: scratch.
 int run_power(bool f64, const void* X, int64_t L, int64_t I, int64_t R, const double* colw,
               int q, int64_t s, int sw, double* Y, double* Yt, double* Z, double* part,
-              double* split, uint32_t* status, hipStream_t st) {
-  const int64_t J = L * R;
-  const bool tiled = L == 1 && tile_ok(I, s, f64);
+              uint32_t* status, hipStream_t st) {
   for (int step = 0; step < q; ++step) {
-    int64_t nused;
-    if (tiled) {
-      const int tj = tile_cols(I, s, f64);
-      const int64_t ntiles = cdiv(J, tj);
-      const int64_t per = cdiv(ntiles, tile_blocks(J, tj));
-      nused = cdiv(ntiles, per);
-      if (f64) TR_TRY(tile_t((const double*)X, I, J, colw, Yt, s, sw, tj, per, nused, part, st));
-      else TR_TRY(tile_t((const float*)X, I, J, colw, Yt, s, sw, tj, per, nused, part, st));
-    } else {
-      const int64_t nparts = gram_parts(J);
-      const int64_t chunk = cdiv(J, nparts);
-      nused = cdiv(J, chunk);
-      TR_TRY(launch_ttm(f64, X, L, I, R, Yt, sw, sw, colw, Z, split, st));
-      if (f64) TR_TRY(gramb_t((const double*)X, L, I, R, Z, s, sw, nused, chunk, part, st));
-      else TR_TRY(gramb_t((const float*)X, L, I, R, Z, s, sw, nused, chunk, part, st));
-    }
+    int64_t nused = 0;
+    if (f64) TR_TRY(pw_step_t((const double*)X, L, I, R, colw, Yt, sw, s, Z, part, &nused, st));
+    else TR_TRY(pw_step_t((const float*)X, L, I, R, colw, Yt, sw, s, Z, part, &nused, st));
     hipLaunchKernelGGL(trk::k_reduce_parts, dim3((unsigned)cdiv(I * s, kNT)), dim3(kNT), 0, st,
                        part, nused, I, (int)s, sw, Y, Yt, status);
     TR_TRY(check_launch());
@@ -702,8 +623,7 @@ int range_finder(const Plan& P, int n, const void* X, void* ws, void* Qout,
   // C_n = (M M^T)^q G_n, starting from Yt = G_n^T.
   {
     TimeScope ts(tm, TR_KC_POWER, n, st);
-    TR_TRY(run_power(src_f64, src, L, M.I, R, colw, P.q, M.s, M.sw, Y, Yt, Z, part,
-                     at<double>(ws, P.oSplit), status, st));
+    TR_TRY(run_power(src_f64, src, L, M.I, R, colw, P.q, M.s, M.sw, Y, Yt, Z, part, status, st));
   }
   if (diag && diag->sketch && diag->sketch[n])
     TR_TRY(copy_d2d(diag->sketch[n], Y, 8 * (size_t)(M.I * M.s), st));
@@ -898,13 +818,13 @@ int tucker_rand_power(int dtype, const void* X, int64_t L, int64_t I, int64_t R,
   const int sw = pad_width(s);
   char* ws = (char*)workspace;
   double* Z = (double*)ws;
-  double* part = (double*)(ws + align_up(8 * (size_t)(J * sw)));
-  double* Yt = (double*)(ws + align_up(8 * (size_t)(J * sw)) +
-                         align_up(8 * (size_t)(power_parts(L, I, J, s, f64) * I * s)));
+  double* part = (double*)(ws + align_up(8 * (size_t)(J * pw_width(s))));
+  double* Yt = (double*)(ws + align_up(8 * (size_t)(J * pw_width(s))) +
+                         align_up(8 * (size_t)(power_parts(I, J) * I * s)));
   hipLaunchKernelGGL(trk::k_transpose, dim3((unsigned)cdiv(I * sw, kNT)), dim3(kNT), 0, st, G, I,
                      s, (int64_t)sw, Yt);
   TR_TRY(check_launch());
-  return run_power(f64, X, L, I, R, colweight, q, s, sw, C, Yt, Z, part, nullptr, nullptr, st);
+  return run_power(f64, X, L, I, R, colweight, q, s, sw, C, Yt, Z, part, nullptr, st);
 }
 
 size_t tucker_rand_factor_workspace_size(int64_t I, int64_t s, int64_t mu) {
