@@ -1,5 +1,6 @@
-// Power-scheme products C <- X_(n) D X_(n)^T C (Strategy A: two skinny
-// products per step) on the FP64 matrix cores.  v_mfma_f64_16x16x4f64 lane
+// Dense contractions on the FP64 matrix cores: the power-scheme products
+// C <- X_(n) D X_(n)^T C (Strategy A: two skinny products per step) and the
+// mode-1 shrink Y = X x_1 Q^T.  v_mfma_f64_16x16x4f64 lane
 // layout (lane l = 16 * g + h, h = l % 16, g = l / 16):
 //   A (16 x 4): lane l holds A[h][g];  B (4 x 16): lane l holds B[g][h];
 //   D (16 x 16): lane l, item v holds D[g + 4 v][h].
@@ -18,6 +19,8 @@
 namespace trk {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -200,6 +203,115 @@ k_pw_y(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
           if (i < I && k < s) out[i + I * k] = v[q];
         }
       }
+  }
+}
+
+
+// Mode-1 shrink on the matrix cores: Y(k, j) = sum_i Q(i, k) X(i, j) for the
+// L == 1 view (X is I x R, column-major, I a multiple of 4 and 16-byte
+// aligned), k < kout, written as Y[k + kout j] in float64.  Q^T is staged once
+// per block in LDS as rows of 16 NKT (zero beyond `width`) and zero rows up
+// to a whole number of batches, so rows beyond I contribute exactly 0 and no
+// product needs a mask.  Blocks loop over tiles of 16 columns, one tile per
+// wave at a time.  A 16-row step gives each lane group g rows 4g .. 4g + 3 of
+// its column as one 16-byte vector load (a group beyond the column reads the
+// last group again; a column beyond R reads column R - 1, and its outputs are
+// not stored).  Work items are (tile, B steps); the loads of the next item
+// are in flight while the current one is multiplied out, from two
+// alternating register buffers.
+template <typename Tin, int B>
+__device__ __forceinline__ void ttm1_load(const Tin* __restrict__ col, int64_t I, int64_t s0,
+                                          int g, Tin (&xr)[B][4]) {
+#pragma unroll
+  for (int u = 0; u < B; ++u) {
+    const int64_t i0 = 16 * (s0 + u) + 4 * g;
+    const int64_t ic = i0 + 4 <= I ? i0 : I - 4;
+    if constexpr (sizeof(Tin) == 4) {
+      const f32x4 v = *reinterpret_cast<const f32x4*>(col + ic);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) xr[u][t] = v[t];
+    } else {
+      const f64x2 v0 = *reinterpret_cast<const f64x2*>(col + ic);
+      const f64x2 v1 = *reinterpret_cast<const f64x2*>(col + ic + 2);
+      xr[u][0] = v0[0];
+      xr[u][1] = v0[1];
+      xr[u][2] = v1[0];
+      xr[u][3] = v1[1];
+    }
+  }
+}
+
+template <typename Tin, int NKT, int B>
+__global__ void __launch_bounds__(kPwWaves * kWave)
+k_ttm1_mfma(const Tin* __restrict__ X, int64_t I, int64_t R, const double* __restrict__ Qt,
+            int width, int kout, double* __restrict__ Y) {
+  constexpr int SP = 16 * NKT;
+  extern __shared__ double qs[];  // qs[i * SP + k] = Q(i, k), zero rows i >= I
+  const int64_t nsteps = (I + 15) / 16;
+  const int64_t nitem = (nsteps + B - 1) / B;  // items per tile
+  const int64_t ipad = nitem * B * 16;
+  for (int64_t e = threadIdx.x; e < ipad * SP; e += kPwWaves * kWave) {
+    const int64_t i = e / SP;
+    const int k = (int)(e - i * SP);
+    qs[e] = (i < I && k < width) ? Qt[(i < I ? i : 0) * width + (k < width ? k : 0)] : 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int h = lane & 15, g = lane >> 4;
+  const int64_t ntile = (R + 15) / 16;
+  const int64_t stride = (int64_t)gridDim.x * kPwWaves;
+  int64_t tile = (int64_t)blockIdx.x * kPwWaves + wid, s0 = 0;
+  if (tile >= ntile) return;
+  auto colp = [&](int64_t tl) {
+    const int64_t j = tl * 16 + h;
+    return X + (j < R ? j : R - 1) * I;
+  };
+  Tin xa[B][4], xb[B][4];
+  ttm1_load<Tin, B>(colp(tile), I, s0, g, xa);
+  f64x4 acc[NKT];
+#pragma unroll
+  for (int kt = 0; kt < NKT; ++kt) acc[kt] = f64x4{0.0, 0.0, 0.0, 0.0};
+  // one work item: prefetch the next into `nxt`, multiply out `cur`
+  auto item = [&](Tin (&cur)[B][4], Tin (&nxt)[B][4]) __attribute__((always_inline)) -> bool {
+    int64_t ntl = tile, ns = s0 + B;
+    if (ns >= nsteps) {
+      ns = 0;
+      ntl += stride;
+    }
+    const bool more = ntl < ntile;
+    // unconditional (the last item reloads its own rows): a conditional
+    // prefetch would make every wait below count as if it had not been issued
+    ttm1_load<Tin, B>(colp(more ? ntl : tile), I, more ? ns : s0, g, nxt);
+    __builtin_amdgcn_sched_barrier(0);
+    const double* qb = qs + (16 * s0 + 4 * g) * SP + h;
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const double b = (double)cur[u][t];
+#pragma unroll
+        for (int kt = 0; kt < NKT; ++kt)
+          acc[kt] = mfma_f64(qb[(16 * u + t) * SP + 16 * kt], b, acc[kt]);
+      }
+    if (s0 + B >= nsteps) {  // tile complete
+      const int64_t j = tile * 16 + h;
+      if (j < R) {
+#pragma unroll
+        for (int kt = 0; kt < NKT; ++kt)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int k = 16 * kt + g + 4 * q;
+            if (k < kout) Y[k + (int64_t)kout * j] = acc[kt][q];
+          }
+      }
+#pragma unroll
+      for (int kt = 0; kt < NKT; ++kt) acc[kt] = f64x4{0.0, 0.0, 0.0, 0.0};
+    }
+    tile = ntl;
+    s0 = ns;
+    return more;
+  };
+  while (item(xa, xb) && item(xb, xa)) {
   }
 }
 

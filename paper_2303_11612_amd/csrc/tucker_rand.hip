@@ -364,6 +364,60 @@ int launch_gather(bool f64, const void* X, int64_t L, int64_t I, const int64_t* 
   return check_launch();
 }
 
+// Mode-1 shrink on the matrix cores (mu <= 32, I a multiple of 4, 16-byte
+// aligned source, padded Q^T within LDS); false otherwise (the caller then
+// uses the vector kernels).  The batch B of 16-row steps is the one of
+// 4, 5, 6, 8 that pads the row count least.
+inline int ttm1_batch(int64_t I) {
+  const int64_t ns = cdiv(I, 16);
+  int best = 8;
+  int64_t bestpad = cdiv(ns, 8) * 8;
+  for (int b : {6, 5, 4}) {
+    const int64_t pad = cdiv(ns, b) * b;
+    if (pad < bestpad) {
+      best = b;
+      bestpad = pad;
+    }
+  }
+  return best;
+}
+
+template <typename Tin, int NKT, int B>
+void ttm1_mfma_k(const Tin* X, int64_t I, int64_t R, const double* Qt, int width, int kout,
+                 double* Y, hipStream_t st) {
+  const size_t lds = 8 * (size_t)(cdiv(cdiv(I, 16), B) * B * 16) * 16 * NKT;
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)&trk::k_ttm1_mfma<Tin, NKT, B>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const int64_t ntile = cdiv(R, 16);
+  const int64_t nblk = std::max<int64_t>(1, std::min<int64_t>(512, cdiv(ntile, trk::kPwWaves)));
+  hipLaunchKernelGGL((trk::k_ttm1_mfma<Tin, NKT, B>), dim3((unsigned)nblk),
+                     dim3(trk::kPwWaves * trk::kWave), lds, st, X, I, R, Qt, width, kout, Y);
+}
+
+template <typename Tin, int NKT>
+void ttm1_mfma_b(const Tin* X, int64_t I, int64_t R, const double* Qt, int width, int kout,
+                 double* Y, hipStream_t st) {
+  switch (ttm1_batch(I)) {
+    case 4: ttm1_mfma_k<Tin, NKT, 4>(X, I, R, Qt, width, kout, Y, st); break;
+    case 5: ttm1_mfma_k<Tin, NKT, 5>(X, I, R, Qt, width, kout, Y, st); break;
+    case 6: ttm1_mfma_k<Tin, NKT, 6>(X, I, R, Qt, width, kout, Y, st); break;
+    default: ttm1_mfma_k<Tin, NKT, 8>(X, I, R, Qt, width, kout, Y, st); break;
+  }
+}
+
+template <typename Tin>
+bool ttm1_mfma(const Tin* X, int64_t I, int64_t R, const double* Qt, int width, int kout,
+               double* Y, hipStream_t st) {
+  if (I % 4 != 0 || (reinterpret_cast<uintptr_t>(X) % 16) != 0 || kout > 32) return false;
+  const int nkt = (int)cdiv(kout, 16);
+  const int b = ttm1_batch(I);
+  if (8 * (size_t)(cdiv(cdiv(I, 16), b) * b * 16) * 16 * nkt > 131072) return false;
+  if (nkt == 1) ttm1_mfma_b<Tin, 1>(X, I, R, Qt, width, kout, Y, st);
+  else ttm1_mfma_b<Tin, 2>(X, I, R, Qt, width, kout, Y, st);
+  return true;
+}
+
 template <typename Tin, int MU>
 void ttm_w(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Qt, int kout,
            const double* colscale, double* Y, double* split, hipStream_t st) {
@@ -379,6 +433,7 @@ void ttm_w(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Qt, int 
                        split, nsu, L, R, MU, kout, colscale, Y);
     return;
   }
+  if (L == 1 && !colscale && ttm1_mfma(X, I, R, Qt, MU, kout, Y, st)) return;
   if (L == 1)
     hipLaunchKernelGGL((trk::k_ttm_l1<Tin, MU>), grid, dim3(kNT), 0, st, X, I, R, Qt, kout,
                        colscale, Y);

@@ -223,8 +223,10 @@ def test_factor_of_rank_deficient_sketch(I, s, mu, rank, factor_variant):
 @pytest.mark.parametrize("in_dt", [np.float32, np.float64])
 @pytest.mark.parametrize("out_dt", [torch.float32, torch.float64])
 @pytest.mark.parametrize("mu", [3, 10, 20, 40])
-def test_ttm_matches_mode_product(in_dt, out_dt, mu):
-    shape = (61, 45, 300)
+@pytest.mark.parametrize("shape", [(61, 45, 300), (64, 30, 77), (400, 21, 19), (36, 5, 7)])
+def test_ttm_matches_mode_product(in_dt, out_dt, mu, shape):
+    # leading extents that are (not) multiples of 4 take the vector-load (or
+    # scalar) form of the mode-1 product; 400 rows span 12.5 row steps
     A = _rand_tensor(shape, in_dt, 4)
     X = tr.to_device(A)
     rng = np.random.default_rng(mu)
