@@ -47,6 +47,22 @@ def _parse():
     return ap.parse_args()
 
 
+def _measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when there is none or the kernel's source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)["kernels"][kernel]
+        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+                return None
+        return float(rec["traffic_bytes"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def _blas_threads():
     try:
         from threadpoolctl import threadpool_info
@@ -138,7 +154,7 @@ def main():
         # column norms: read the tensor, write J_1 float64 norms
         "colnorms": (dims[0] * J1 * elem + 8 * J1, "k_colnorms_l1<float>"),
         # shrink A x_1 Q_1^T: read the tensor, write mu_1 * J_1 float64 entries
-        "ttm": (dims[0] * J1 * elem + 8 * ranks[0] * J1, "k_ttm_l1<float>"),
+        "ttm": (dims[0] * J1 * elem + 8 * ranks[0] * J1, "k_ttm1_mfma<float, 1, 5>"),
     }
     kern = {}
     for cls, (nbytes, kname) in sweeps.items():
@@ -154,8 +170,12 @@ def main():
                       "bound": "latency (one workgroup: QR, QR of R^T, Jacobi, Q formation)"}
     dom = max(sweeps, key=lambda c: kern[c]["mode1_avg_ms"])
     ach = kern[dom]["achieved_GBs"]
+    traffic = _measured_traffic(kern[dom]["kernel"])
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else round(traffic),
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "algorithmic_bytes": kern[dom]["algorithmic_bytes"],
                 "kernel": kern[dom]["kernel"]}
 
     # relative error of the GPU result (orthogonal projection identity, Eq. (8))

@@ -54,15 +54,14 @@ constexpr uint64_t kTagSample = 1;
 // ---------------------------------------------------------------------------
 
 // Lane permutations through DPP (no LDS round trip).  A double moves as two
-// 32-bit halves with the same control word.  Lanes outside ROW_MASK keep
-// their own value (the "old" operand is the source itself, so no register
-// has to be cleared first).
-template <int CTRL, int ROW_MASK = 0xf, bool BOUND_CTRL = false>
+// 32-bit halves with the same control word.  Every pattern used here reads a
+// valid lane for every lane in ROW_MASK; lanes outside ROW_MASK get an
+// unspecified value, which callers select away.
+template <int CTRL, int ROW_MASK = 0xf>
 __device__ __forceinline__ double dpp_f64(double v) {
   const long long b = __double_as_longlong(v);
-  const int l = (int)(b & 0xffffffff), h = (int)(b >> 32);
-  const int lo = __builtin_amdgcn_update_dpp(l, l, CTRL, ROW_MASK, 0xf, BOUND_CTRL);
-  const int hi = __builtin_amdgcn_update_dpp(h, h, CTRL, ROW_MASK, 0xf, BOUND_CTRL);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffff), CTRL, ROW_MASK, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, ROW_MASK, 0xf, true);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 

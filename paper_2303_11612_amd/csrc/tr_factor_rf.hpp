@@ -24,7 +24,7 @@ struct RfShape {
   static constexpr int SEGLEN = NT / SEG;  // partial rows summed by one reducer lane
   static constexpr int PS = SM + 2;        // partial row stride (16-byte aligned rows)
   static constexpr int JW = kWave / SEG;   // values covered by one wave of reducers
-  static constexpr int LDX = SM + 1;       // column stride of X and U
+  static constexpr int LDX = SM + 2;       // column stride of X and U (16-byte aligned)
   // Segment g starts JW doubles after the end of segment g-1: the reducers of
   // one wave (JW values x SEG segments) then spread over all 32 banks, and
   // segments never overlap.
@@ -138,7 +138,7 @@ k_factor_rf(const double* __restrict__ C, int I, int s, int mu, double* __restri
             double* __restrict__ Qt, int ldqt, double* __restrict__ sig_out,
             void* __restrict__ Qcast, int cast_f32, uint32_t* __restrict__ status) {
   using S = RfShape<SM>;
-  constexpr int NT = S::NT, LDX = S::LDX;
+  constexpr int NT = S::NT, NW = NT / kWave, LDX = S::LDX;
   static_assert(MU <= SM && MU % 8 == 0, "column bound");
   extern __shared__ double smem[];
   double* P = smem;
@@ -269,67 +269,88 @@ k_factor_rf(const double* __restrict__ C, int I, int s, int mu, double* __restri
   }
   __syncthreads();
 
-  // ---- 3. one-sided Jacobi on the columns of X: pair g on DPP row g / 4 of
-  //         wave g % 4, 16 lanes per pair, rows l16 + 16 u ----
+  // ---- 3. one-sided Jacobi on the columns of X.  SM == 16: wave 0 alone
+  //         (no barrier between steps: one wave's LDS accesses complete in
+  //         order), pair g on lanes 8g .. 8g + 7.  SM == 32: all four waves,
+  //         pair g on DPP row g / 4 of wave g % 4.  Each lane holds RU
+  //         consecutive rows of the pair's two columns.  Column norms are
+  //         recomputed at the start of each sweep and then updated with each
+  //         rotation (a' = a - t c, b' = b + t c). ----
   {
-    constexpr int RU = SM / 16;
+    constexpr bool kOneWave = SM == 16;
+    constexpr int LP = kOneWave ? 8 : 16;  // lanes per pair
+    constexpr int RU = SM / LP;            // rows per lane
     const int se = s + (s & 1), np = se / 2, sm1 = se - 1;
-    const int l16 = lane & 15;
-    const int g = (lane >> 4) * 4 + wid;
-    const bool gact = g < np;
-    const int gg = gact ? g : 0;
+    const int lq = lane % LP;
+    const int slot = kOneWave ? lane / LP : (lane / LP) * NW + wid;
+    const bool gact = slot < np;
+    const int gg = gact ? slot : 0;
     const double tol = 2.0 * s * 2.220446049250313e-16;
-    for (int sweep = 0; sweep < 40 && se > 1; ++sweep) {
-      int rot = 0;
-      // circle method: position 0 fixed, positions 1..se-1 advance each step
-      int pp = gg == 0 ? -1 : gg - 1;  // -1: the fixed position
-      int qq = se - 2 - gg;
-      for (int step = 0; step < sm1; ++step) {
-        const int p0 = pp < 0 ? 0 : pp + 1, q0 = qq + 1;
-        const int p = min(p0, q0), q = max(p0, q0);
-        double xv[RU], yv[RU];
+    double* jn = sig;  // column norms^2 during the sweeps
+    if (!kOneWave || wid == 0) {
+      for (int sweep = 0; sweep < 40 && se > 1; ++sweep) {
+        if (tid < se) {
+          double t = 0.0;
 #pragma unroll
-        for (int u = 0; u < RU; ++u) {
-          xv[u] = X[p * LDX + l16 + 16 * u];
-          yv[u] = X[q * LDX + l16 + 16 * u];
+          for (int i = 0; i < SM; ++i) t = fma(X[tid * LDX + i], X[tid * LDX + i], t);
+          jn[tid] = t;
         }
-        double aa = 0.0, bb = 0.0, cc = 0.0;
-#pragma unroll
-        for (int u = 0; u < RU; ++u) {
-          aa = fma(xv[u], xv[u], aa);
-          bb = fma(yv[u], yv[u], bb);
-          cc = fma(xv[u], yv[u], cc);
-        }
-        aa = seg_reduce<16, RfSum>(aa);
-        bb = seg_reduce<16, RfSum>(bb);
-        cc = seg_reduce<16, RfSum>(cc);
-        // threshold on |x.y| / (|x| |y|); an estimate of the norms suffices
-        if (gact && cc != 0.0 &&
-            fabs(cc) * __builtin_amdgcn_rsq(aa) * __builtin_amdgcn_rsq(bb) > tol) {
-          // tan(theta) = sign(d) e / (|d| + hypot(d, e)) with d = |y|^2 - |x|^2,
-          // e = 2 x.y; d and e are first scaled by a common power of two into
-          // [1/2, 1) so that every operand below is of moderate size
-          double d = bb - aa, e = 2.0 * cc;
-          const int ex = max(__builtin_amdgcn_frexp_exp(d), __builtin_amdgcn_frexp_exp(e));
-          d = ldexp(d, -ex);
-          e = ldexp(e, -ex);
-          const double t = copysign(1.0, d) * e * rcp_nr(fabs(d) + sqrt_nr(fma(d, d, e * e)));
-          const double cs = rsqrt_nr(fma(t, t, 1.0));
-          const double sn = cs * t;
+        if (!kOneWave) __syncthreads();
+        int rot = 0;
+        // circle method: position 0 fixed, positions 1..se-1 advance each step
+        int pp = gg == 0 ? -1 : gg - 1;  // -1: the fixed position
+        int qq = se - 2 - gg;
+        for (int step = 0; step < sm1; ++step) {
+          const int p0 = pp < 0 ? 0 : pp + 1, q0 = qq + 1;
+          const int p = min(p0, q0), q = max(p0, q0);
+          double* xp = X + p * LDX + lq * RU;
+          double* xq = X + q * LDX + lq * RU;
+          double xv[RU], yv[RU];
 #pragma unroll
           for (int u = 0; u < RU; ++u) {
-            X[p * LDX + l16 + 16 * u] = cs * xv[u] - sn * yv[u];
-            X[q * LDX + l16 + 16 * u] = sn * xv[u] + cs * yv[u];
+            xv[u] = xp[u];
+            yv[u] = xq[u];
           }
-          rot = 1;
+          const double aa = jn[p], bb = jn[q];
+          double cc = 0.0;
+#pragma unroll
+          for (int u = 0; u < RU; ++u) cc = fma(xv[u], yv[u], cc);
+          cc = seg_reduce<LP, RfSum>(cc);
+          // Rotate when |x.y| / (|x| |y|) > tol (an estimate of the norms
+          // suffices).  tan(theta) = sign(d) e / (|d| + hypot(d, e)) with
+          // d = |y|^2 - |x|^2, e = 2 x.y, after scaling d and e by a common
+          // power of two into [1/2, 1) so that every operand below is of
+          // moderate size; cos = 1 / sqrt(1 + t^2), sin = t cos.  Late sweeps
+          // rotate few pairs, and a wave with none skips the arithmetic.
+          const double rel = fabs(cc) * __builtin_amdgcn_rsq(aa) * __builtin_amdgcn_rsq(bb);
+          if (gact && cc != 0.0 && rel > tol) {
+            const double dd = bb - aa;
+            const int exe = __builtin_amdgcn_frexp_exp(cc) + 1;
+            const int ex = dd == 0.0 ? exe : max(__builtin_amdgcn_frexp_exp(dd), exe);
+            const double d = ldexp(dd, -ex), e = ldexp(2.0 * cc, -ex);
+            const double t = copysign(1.0, d) * e * rcp_nr(fabs(d) + sqrt_nr(fma(d, d, e * e)));
+            const double cs = rsqrt_nr(fma(t, t, 1.0));
+            const double sn = cs * t;
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+              xp[u] = cs * xv[u] - sn * yv[u];
+              xq[u] = sn * xv[u] + cs * yv[u];
+            }
+            if (lq == 0) {
+              jn[p] = fma(-t, cc, aa);
+              jn[q] = fma(t, cc, bb);
+            }
+            rot = 1;
+          }
+          if (!kOneWave) __syncthreads();
+          if (pp >= 0) pp = pp + 1 == sm1 ? 0 : pp + 1;
+          qq = qq + 1 == sm1 ? 0 : qq + 1;
         }
-        __syncthreads();
-        if (pp >= 0) pp = pp + 1 == sm1 ? 0 : pp + 1;
-        qq = qq + 1 == sm1 ? 0 : qq + 1;
+        if (kOneWave ? !__any(rot) : !__syncthreads_or(rot)) break;
       }
-      if (!__syncthreads_or(rot)) break;
     }
   }
+  __syncthreads();
 
   // ---- 4. singular values, descending (ties: lower column first) ----
   if (tid < s) {

@@ -182,3 +182,15 @@ def test_config2_full_size_sthosvd_amm():
     """The benchmark workload at full size: 400^3 float32, Alg. 5."""
     w = synth.config(2)
     _compare(w.A, "sthosvd", w.ranks, w.oversample, w.power, w.prob, w.samples, w.seed)
+
+
+def test_config3_full_size_thosvd_power2():
+    """100^4 float32, tendiag core (k+1)^-2, exact products, q = 2 (Alg. 1)."""
+    w = synth.config(3)
+    _compare(w.A, w.algo, w.ranks, w.oversample, w.power, w.prob, w.samples, w.seed)
+
+
+def test_config4_full_size_thosvd_uniform():
+    """512 x 512 x 256 float32 Gaussian bumps, uniform sampling, T_n = 8000 (Alg. 4)."""
+    w = synth.config(4)
+    _compare(w.A, w.algo, w.ranks, w.oversample, w.power, w.prob, w.samples, w.seed)
