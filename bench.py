@@ -41,6 +41,16 @@ def _parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU time budget of the oracle baseline")
+    ap.add_argument("--workload", choices=("all", "decomp", "serving"), default="all",
+                    help="decomp: the 400^3 decomposition line only; serving: the "
+                         "request stream only; all: both in one line")
+    ap.add_argument("--requests", type=int, default=512)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--budget-gb", type=float, default=16.0)
+    ap.add_argument("--load", type=float, default=0.7,
+                    help="arrival rate as a fraction of the one-at-a-time throughput")
+    ap.add_argument("--source", choices=("device", "host"), default="device")
+    ap.add_argument("--oracle-requests", type=int, default=8)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device-to-device copy of 256 MiB (HBM "
                          "counter calibration under rocprofv3 --pmc)")
@@ -96,6 +106,27 @@ def main():
         print(json.dumps({"copy_probe_bytes": n, "copies": 5}))
         return
 
+    if args.workload == "serving":
+        srv = bench_serving(args)
+        cap = srv["saturated_throughput_rps"]["batched"]
+        out = {"metric": METRIC, "value": cap,
+               "unit": "requests/s", "n_gpus": 1, "steps": srv["requests"], "warmup": 0,
+               "ms_per_step": round(1e3 / cap, 4),
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+               "dtype": "f64", "data": "synthetic",
+               "config": {"workload": srv.pop("workload"), "parallelism": "single GPU"},
+               "serving": srv}
+        print(json.dumps(out), flush=True)
+        return
+    out = bench_decomp(args)
+    if args.workload == "all":
+        out["serving"] = bench_serving(args)
+    print(json.dumps(out), flush=True)
+
+
+def bench_decomp(args):
+    import numpy as np
+    import torch
     import synth
     import paper_2303_11612_amd as tr
 
@@ -225,7 +256,98 @@ def main():
             "max_factor_rel_err": max(float(np.linalg.norm(Qg[n] - Qo[n]) /
                                             np.linalg.norm(Qo[n])) for n in range(N)),
             "core_rel_err": float(np.linalg.norm(cg - co) / np.linalg.norm(co))}
-    print(json.dumps(out), flush=True)
+    return out
+
+
+def bench_serving(args):
+    """The request stream: modes U{32..384}, ranks U{4..24}, T_n = 4 mu_n,
+    nearly-optimal sampling, q = 1, K = 10, Poisson arrivals at `load` times
+    the one-at-a-time throughput; one slot (one request at a time) against
+    `slots` concurrent slots under an HBM budget, on the same arrivals."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2303_11612_amd as tr
+    from paper_2303_11612_amd import serving as sv
+
+    n = args.requests
+    t_gen = time.perf_counter()
+    reqs = []
+    for rid in range(n):
+        X, ranks, samples = synth.serving_request_device(rid)
+        if args.source == "host":
+            h = torch.empty(X.numel(), dtype=torch.float32, pin_memory=True)
+            h.copy_(X.permute(2, 1, 0).reshape(-1))
+            X = h.as_strided(tuple(X.shape), X.stride())
+        reqs.append(sv.Request(rid, X, ranks, samples, seed=rid))
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    budget = int(args.budget_gb * (1 << 30))
+
+    def serve(slots, arrivals):
+        for r, a in zip(reqs, arrivals):
+            r.arrival = float(a)
+        server = sv.Server(sv.GpuBackend(slots), slots=slots, hbm_budget=budget)
+        res = server.run(reqs)
+        return res, server.peak_used
+
+    # warm-up: kernels loaded and allocator pools filled for every slot
+    warm = reqs[:2 * args.slots]
+    for r in warm:
+        r.arrival = 0.0
+    sv.Server(sv.GpuBackend(args.slots), slots=args.slots, hbm_budget=budget).run(warm)
+    torch.cuda.synchronize()
+
+    zero = np.zeros(n)
+    sat1, _ = serve(1, zero)
+    cap1 = sv.summarize(sat1)["throughput_rps"]
+    satS, _ = serve(args.slots, zero)
+    capS = sv.summarize(satS)["throughput_rps"]
+    rate = args.load * cap1
+    arr = sv.poisson_arrivals(n, rate, seed=args.seed + 7)
+    one, _ = serve(1, arr)
+    mix, peak = serve(args.slots, arr)
+
+    # results alone (one slot, no overlap) against results in the mix: bitwise
+    same = all(torch.equal(a.core, b.core) and
+               all(torch.equal(x, y) for x, y in zip(a.factors, b.factors))
+               for a, b in zip(sat1, mix))
+    # relative Tucker error of each request: ||A||^2 - ||core||^2 (Eq. (8) with
+    # orthonormal factors), from the mix's outputs
+    re = []
+    for r, m in zip(reqs, mix):
+        nA2 = float(torch.sum(r.X.double() ** 2))
+        re.append(math.sqrt(max(0.0, 1.0 - float(torch.sum(m.core.double() ** 2)) / nA2)))
+    out = {
+        "workload": f"serving stream, {n} requests, modes U{{32..384}}^3 float32, ranks "
+                    f"U{{4..24}}, rand ST-HOSVD + nearly-optimal sampling T_n = 4 mu_n, "
+                    f"q 1, K 10, Poisson arrivals at {args.load} x one-at-a-time throughput",
+        "requests": n, "slots": args.slots, "source": args.source,
+        "hbm_budget_bytes": budget, "peak_admitted_bytes": int(peak),
+        "mean_tensor_MB": round(sum(r.X.numel() * 4 for r in reqs) / n / 1e6, 2),
+        "arrival_rate_rps": round(rate, 2),
+        "saturated_throughput_rps": {"one_at_a_time": cap1, "batched": capS},
+        "one_at_a_time": sv.summarize(one),
+        "batched": sv.summarize(mix),
+        "all_status_ok": all(m.status == 0 for m in mix),
+        "mix_equals_alone_bitwise": bool(same),
+        "rel_error": {"mean": float(np.mean(re)), "max": float(np.max(re))},
+        "generation_s": round(t_gen, 2),
+    }
+    if args.oracle_requests > 0:
+        import oracle
+        k = min(args.oracle_requests, n)
+        diffs, t_or = [], 0.0
+        for i in range(k):
+            A = reqs[i].X.double().cpu().numpy()
+            t1 = time.perf_counter()
+            Qo, co, _ = oracle.rand_sthosvd(A, reqs[i].ranks, 10, 1, "nearly_optimal",
+                                            reqs[i].samples, reqs[i].seed)
+            t_or += time.perf_counter() - t1
+            diffs.append(abs(oracle.relative_error(A, co, Qo) - re[i]))
+        out["oracle_subset"] = {"requests": k, "max_abs_re_diff": float(max(diffs)),
+                                "oracle_s_per_request": round(t_or / k, 3)}
+    return out
 
 
 if __name__ == "__main__":

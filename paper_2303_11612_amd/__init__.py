@@ -180,6 +180,7 @@ def _decompose(fn_name, A, ranks, oversample, power, prob, samples, seed, precis
             status = torch.zeros(1, dtype=torch.int32, device=A.device)
             info["status"] = status
             dstruct.status = status.data_ptr()
+        if diag and diag != "status":
             # sketches and singular values for every mode
             s = [min(ranks[n] + oversample, dims[n]) for n in range(N)]
             cur = list(dims)

@@ -35,7 +35,7 @@ import numpy as np
 __all__ = [
     "orth", "tucker_signal", "tendiag", "add_noise", "Workload",
     "low_rank_plus_noise", "gaussian_bumps", "config", "CONFIGS",
-    "serving_request",
+    "serving_request", "serving_shape", "serving_request_device",
 ]
 
 
@@ -188,13 +188,8 @@ def config(k: int, seed: int = 0) -> Workload:
 CONFIGS = (1, 2, 3, 4)
 
 
-def serving_request(req_id: int, base_seed: int = 1000, dtype=np.float32):
-    """One request of the serving stream: modes U{32..384}, ranks U{4..24}.
-
-    Ranks are redrawn until mu_n <= I_n and mu_n <= prod_{m != n} mu_m (a
-    feasible multilinear rank).  Gaussian core, orthonormal factors, noise 1e-3.
-    Returns (A, ranks, samples) with samples T_n = 4*mu_n.
-    """
+def serving_shape(req_id: int, base_seed: int = 1000):
+    """(dims, ranks) of a serving request without generating its tensor."""
     rng = np.random.default_rng(base_seed + req_id)
     dims = tuple(int(x) for x in rng.integers(32, 385, size=3))
     while True:
@@ -204,5 +199,50 @@ def serving_request(req_id: int, base_seed: int = 1000, dtype=np.float32):
                  for n in range(3))
         if ok:
             break
+    return dims, ranks
+
+
+def serving_request(req_id: int, base_seed: int = 1000, dtype=np.float32):
+    """One request of the serving stream: modes U{32..384}, ranks U{4..24}.
+
+    Ranks are redrawn until mu_n <= I_n and mu_n <= prod_{m != n} mu_m (a
+    feasible multilinear rank).  Gaussian core, orthonormal factors, noise 1e-3.
+    Returns (A, ranks, samples) with samples T_n = 4*mu_n.
+    """
+    dims, ranks = serving_shape(req_id, base_seed)
     A = low_rank_plus_noise(dims, ranks, 1e-3, base_seed + req_id, dtype)
     return A, ranks, tuple(4 * r for r in ranks)
+
+
+def serving_request_device(req_id: int, base_seed: int = 1000, device="cuda"):
+    """A serving request generated in device memory (for long request streams).
+
+    Same shape, ranks, core and factors as ``serving_request`` (numpy draws);
+    the signal is assembled in float64 on the device and the noise is drawn
+    with torch's generator on the device seeded with base_seed + req_id, so the
+    tensor is a different sample of the same distribution.  Returns
+    (X, ranks, samples) with X a column-major float32 device tensor.
+    """
+    import torch
+    dims, ranks = serving_shape(req_id, base_seed)
+    rng = np.random.default_rng(base_seed + req_id)
+    C = rng.standard_normal(tuple(ranks)[::-1]).T
+    U = [orth(rng.standard_normal((dims[n], ranks[n]))) for n in range(3)]
+    f64 = dict(dtype=torch.float64, device=device)
+    # B[i,j,k] = sum_abc C[a,b,c] U1[i,a] U2[j,b] U3[k,c], built as the
+    # C-ordered array of reversed shape (k, j, i) so that its transpose is
+    # the Fortran-ordered tensor.
+    Ct = torch.as_tensor(np.ascontiguousarray(C.T), **f64)          # (c, b, a)
+    U1, U2, U3 = (torch.as_tensor(u, **f64) for u in U)
+    T = torch.matmul(Ct.reshape(-1, ranks[0]), U1.t().contiguous())  # (c*b, i)
+    T = T.reshape(ranks[2], ranks[1], dims[0]).permute(0, 2, 1).reshape(-1, ranks[1])
+    T = torch.matmul(T, U2.t().contiguous())                         # (c*i, j)
+    T = T.reshape(ranks[2], dims[0], dims[1]).permute(1, 2, 0).reshape(-1, ranks[2])
+    T = torch.matmul(T, U3.t().contiguous())                         # (i*j, k)
+    B = T.reshape(dims[0], dims[1], dims[2]).permute(2, 1, 0).contiguous()  # (k, j, i)
+    g = torch.Generator(device=device)
+    g.manual_seed(base_seed + req_id)
+    E = torch.randn(B.shape, generator=g, **f64)
+    scale = 1e-3 * float(torch.linalg.vector_norm(B)) / math.sqrt(B.numel())
+    X = (B + scale * E).to(torch.float32)
+    return X.permute(2, 1, 0), ranks, tuple(4 * r for r in ranks)
