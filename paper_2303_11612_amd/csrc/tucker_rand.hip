@@ -17,6 +17,7 @@
 #include "tr_kernels.hpp"
 #include "tr_factor_rf.hpp"
 #include "tr_power.hpp"
+#include "tr_lowp.hpp"
 #include "tucker_rand.h"
 
 namespace {
@@ -118,6 +119,23 @@ inline bool factor_in_lds(int64_t I, int64_t s, int64_t mu) {
 }
 inline bool factor_supported(int64_t I, int64_t s) { return s >= 1 && s <= 64 && I <= (1 << 24); }
 
+// Low-precision power steps (k_pw_lp): rows padded to Ip = 128 MI (MI in
+// {1, 2, 4}, so I <= 512), sketch columns to 16 NKT (NKT <= 3, so s <= 48).
+inline int lp_mi(int64_t I) { return I <= 128 ? 1 : (I <= 256 ? 2 : 4); }
+inline int64_t lp_ip(int64_t I) { return 128 * lp_mi(I); }
+inline int lp_nkt(int64_t s) { return (int)cdiv(s, 16); }
+inline bool lp_supported(int64_t I, int64_t s) { return I <= 512 && s >= 1 && s <= 48; }
+inline size_t lp_lds_bytes(int mi, int nkt) {
+  return 4 * (size_t)(4 * 32 * mi * 36 + 2 * 4 * 16 * nkt * 36);
+}
+// Blocks of one power step over J columns: at most the resident blocks of
+// the chip, at least two column blocks of 32 each.
+inline int64_t lp_blocks(int64_t I, int64_t s, int64_t J) {
+  const int64_t per_cu = lp_lds_bytes(lp_mi(I), lp_nkt(s)) <= 80 * 1024 ? 2 : 1;
+  return std::max<int64_t>(1, std::min<int64_t>(256 * per_cu, cdiv(cdiv(J, 32), 2)));
+}
+inline size_t lp_esz(int prec) { return prec == TR_PREC_FP8E4M3 ? 1 : 2; }
+
 // ---------------------------------------------------------------------------
 // Plan: per-mode shapes and the workspace layout.
 // ---------------------------------------------------------------------------
@@ -141,6 +159,9 @@ struct Plan {
   // workspace offsets (bytes)
   size_t oG, oY, oYt, oZ, oPart, oNorms, oW, oCdf, oBsum, oIdx, oScale, oScale2, oCp,
       oMax, oSig, oX0, oX1, oCore, oSplit, total;
+  // low-precision power steps
+  int prec = TR_PREC_NATIVE;
+  size_t oYq = 0, oTau = 0, oPartLp = 0, oCq = 0, oOmega = 0, oXmax = 0;
   size_t oQ[TR_MAX_ORDER], oQt[TR_MAX_ORDER];
 };
 
@@ -155,10 +176,11 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
     return TR_EINVAL;
   if (p->prob != TR_PROB_NONE && !p->samples) return TR_EINVAL;
   if (p->flags != 0) return TR_EINVAL;
-  if (p->precision != TR_PREC_NATIVE) {
-    if (p->precision == TR_PREC_BF16 || p->precision == TR_PREC_FP8E4M3) return TR_ENOTSUP;
+  if (p->precision != TR_PREC_NATIVE && p->precision != TR_PREC_BF16 &&
+      p->precision != TR_PREC_FP8E4M3)
     return TR_EINVAL;
-  }
+  const bool lp = p->precision != TR_PREC_NATIVE;
+  P->prec = p->precision;
   const int N = p->order;
   P->N = N;
   P->sthosvd = sthosvd;
@@ -176,7 +198,7 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
   if (total_el > 9.0e15) return TR_EINVAL;
 
   size_t maxIs = 0, maxZ = 0, maxPart = 0, maxJs = 0, maxT = 0, maxCp = 0, maxInter = 0,
-         maxSplit = 0;
+         maxSplit = 0, maxYq = 0, maxPartLp = 0, maxCq = 0;
   int64_t maxS = 0;
   for (int n = 0; n < N; ++n) {
     ModePlan& M = P->m[n];
@@ -200,6 +222,15 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
       }
     }
     if (!factor_supported(M.I, M.s)) return TR_ENOTSUP;
+    if (lp) {
+      if (!lp_supported(M.I, M.s)) return TR_ENOTSUP;
+      const int64_t jl = M.sampled ? M.T : M.J;
+      if (!M.sampled && M.J >= ((int64_t)1 << 32)) return TR_ENOTSUP;
+      const int64_t Ip = lp_ip(M.I), SP = 16 * lp_nkt(M.s);
+      maxYq = std::max(maxYq, (size_t)(SP * Ip));
+      maxPartLp = std::max(maxPartLp, (size_t)(lp_blocks(M.I, M.s, jl) * SP * Ip));
+      if (M.sampled) maxCq = std::max(maxCq, (size_t)(Ip * M.T));
+    }
     M.sw = pad_width(M.s);
     M.muw = pad_width(M.mu);
     if (M.sw == 0 || M.muw == 0) return TR_ENOTSUP;
@@ -248,8 +279,9 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
   P->oG = take(8 * maxIs);
   P->oY = take(8 * maxIs);
   P->oYt = take(8 * maxIs);
-  P->oZ = take(8 * maxZ);
-  P->oPart = take(8 * maxPart);
+  // the float64 power steps' W and partial sketches (unused in low precision)
+  P->oZ = take(lp ? 8 : 8 * maxZ);
+  P->oPart = take(lp ? 8 : 8 * maxPart);
   P->oNorms = take(8 * maxJs);
   P->oW = take(8 * maxJs);
   P->oCdf = take(8 * maxJs);
@@ -257,7 +289,7 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
   P->oIdx = take(8 * maxT);
   P->oScale = take(8 * maxT);
   P->oScale2 = take(8 * maxT);
-  P->oCp = take(8 * maxCp);
+  P->oCp = take(lp ? 8 : 8 * maxCp);
   P->oMax = take(8);
   P->oSig = take(8 * (size_t)maxS);
   for (int n = 0; n < N; ++n) {
@@ -268,6 +300,14 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
   P->oX1 = take(8 * maxInter);
   P->oCore = take(8 * core_el);
   P->oSplit = take(8 * maxSplit);
+  if (lp) {
+    P->oYq = take(2 * maxYq);
+    P->oTau = take(4 * 64);
+    P->oPartLp = take(4 * maxPartLp);
+    P->oCq = take(lp_esz(P->prec) * maxCq);
+    P->oOmega = take(4 * maxT);
+    P->oXmax = take(4);
+  }
   P->total = off;
   return TR_OK;
 }
@@ -534,6 +574,155 @@ int run_power(bool f64, const void* X, int64_t L, int64_t I, int64_t R, const do
   return TR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Low-precision power steps.
+// ---------------------------------------------------------------------------
+template <typename Tin, typename OP, int MI, int NKT>
+int pw_lp_k(const void* X, int64_t L, int64_t I, int64_t R, int64_t ldi, const void* Cq,
+            const float* tau, const float* omega, const unsigned* xmax, float* part,
+            int64_t nblk, hipStream_t st) {
+  const size_t lds = lp_lds_bytes(MI, NKT);
+  auto* fn = &trk::k_pw_lp<Tin, OP, MI, NKT>;
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+  hipLaunchKernelGGL(fn, dim3((unsigned)nblk), dim3(trk::kPwWaves * trk::kWave), lds, st,
+                     (const Tin*)X, L, I, R, ldi, (const typename OP::stor*)Cq, tau, omega,
+                     xmax, part);
+  return check_launch();
+}
+
+template <typename Tin, typename OP, int MI>
+int pw_lp_n(int nkt, const void* X, int64_t L, int64_t I, int64_t R, int64_t ldi,
+            const void* Cq, const float* tau, const float* omega, const unsigned* xmax,
+            float* part, int64_t nblk, hipStream_t st) {
+  switch (nkt) {
+    case 1: return pw_lp_k<Tin, OP, MI, 1>(X, L, I, R, ldi, Cq, tau, omega, xmax, part, nblk, st);
+    case 2: return pw_lp_k<Tin, OP, MI, 2>(X, L, I, R, ldi, Cq, tau, omega, xmax, part, nblk, st);
+    case 3: return pw_lp_k<Tin, OP, MI, 3>(X, L, I, R, ldi, Cq, tau, omega, xmax, part, nblk, st);
+    default: return TR_ENOTSUP;
+  }
+}
+
+template <typename Tin, typename OP>
+int pw_lp_m(int64_t s, const void* X, int64_t L, int64_t I, int64_t R, int64_t ldi,
+            const void* Cq, const float* tau, const float* omega, const unsigned* xmax,
+            float* part, int64_t nblk, hipStream_t st) {
+  const int nkt = lp_nkt(s);
+  switch (lp_mi(I)) {
+    case 1: return pw_lp_n<Tin, OP, 1>(nkt, X, L, I, R, ldi, Cq, tau, omega, xmax, part, nblk, st);
+    case 2: return pw_lp_n<Tin, OP, 2>(nkt, X, L, I, R, ldi, Cq, tau, omega, xmax, part, nblk, st);
+    default: return pw_lp_n<Tin, OP, 4>(nkt, X, L, I, R, ldi, Cq, tau, omega, xmax, part, nblk, st);
+  }
+}
+
+// Source of a low-precision power step: a float32 / float64 tensor view, or
+// the gathered sample matrix already in operand form.
+enum LpSrc { kLpF32 = 0, kLpF64 = 1, kLpStored = 2 };
+
+template <typename OP>
+int pw_lp_src(int kind, int64_t s, const void* X, int64_t L, int64_t I, int64_t R, int64_t ldi,
+              const void* Cq, const float* tau, const float* omega, const unsigned* xmax,
+              float* part, int64_t nblk, hipStream_t st) {
+  switch (kind) {
+    case kLpF32:
+      return pw_lp_m<float, OP>(s, X, L, I, R, ldi, Cq, tau, omega, xmax, part, nblk, st);
+    case kLpF64:
+      return pw_lp_m<double, OP>(s, X, L, I, R, ldi, Cq, tau, omega, xmax, part, nblk, st);
+    default:
+      return pw_lp_m<typename OP::stor, OP>(s, X, L, I, R, ldi, Cq, tau, omega, xmax, part,
+                                             nblk, st);
+  }
+}
+
+int launch_quant_y(int prec, const double* C, int64_t I, int64_t s, void* Cq, float* tau,
+                   hipStream_t st) {
+  const int Ip = (int)lp_ip(I), SP = 16 * lp_nkt(s);
+  if (prec == TR_PREC_FP8E4M3)
+    hipLaunchKernelGGL(trk::k_quant_y<trk::OpFp8>, dim3(SP), dim3(kNT), 0, st, C, I, (int)s, Ip,
+                       (uint8_t*)Cq, tau);
+  else
+    hipLaunchKernelGGL(trk::k_quant_y<trk::OpBf16>, dim3(SP), dim3(kNT), 0, st, C, I, (int)s,
+                       Ip, (uint16_t*)Cq, tau);
+  return check_launch();
+}
+
+template <typename Tin>
+int gather_lp_t(int prec, const Tin* X, int64_t L, int64_t I, const int64_t* idx, int64_t T,
+                const double* scale2, void* Cq, float* omega, hipStream_t st) {
+  const int Ip = (int)lp_ip(I);
+  if (prec == TR_PREC_FP8E4M3)
+    hipLaunchKernelGGL((trk::k_gather_lp<Tin, trk::OpFp8>), dim3((unsigned)T), dim3(kNT), 0, st,
+                       X, L, I, idx, Ip, scale2, (uint8_t*)Cq, omega);
+  else
+    hipLaunchKernelGGL((trk::k_gather_lp<Tin, trk::OpBf16>), dim3((unsigned)T), dim3(kNT), 0,
+                       st, X, L, I, idx, Ip, scale2, (uint16_t*)Cq, omega);
+  return check_launch();
+}
+
+int launch_gather_lp(int prec, bool f64, const void* X, int64_t L, int64_t I, const int64_t* idx,
+                     int64_t T, const double* scale2, void* Cq, float* omega, hipStream_t st) {
+  return f64 ? gather_lp_t(prec, (const double*)X, L, I, idx, T, scale2, Cq, omega, st)
+             : gather_lp_t(prec, (const float*)X, L, I, idx, T, scale2, Cq, omega, st);
+}
+
+int launch_maxabs(bool f64, const void* X, int64_t n, unsigned* out, hipStream_t st) {
+  // the slot is 8-byte aligned and at least 8 bytes long (workspace layout)
+  TR_TRY(launch_fill(reinterpret_cast<unsigned long long*>(out), 1, 0ull, st));
+  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, cdiv(n, kNT * 8)));
+  if (f64)
+    hipLaunchKernelGGL(trk::k_maxabs<double>, dim3(nb), dim3(kNT), 0, st, (const double*)X, n,
+                       out);
+  else
+    hipLaunchKernelGGL(trk::k_maxabs<float>, dim3(nb), dim3(kNT), 0, st, (const float*)X, n, out);
+  return check_launch();
+}
+
+int launch_factor(const double* C, int64_t I, int64_t s, int64_t mu, double* Q, double* Qt,
+                  int ldqt, double* sig, void* Qcast, int cast_f32, uint32_t* status,
+                  double* gA, hipStream_t st);
+
+// The power scheme in low precision (k_quant_y, k_pw_lp, k_reduce_parts_lp
+// per step), C and G float64 I x s column-major.  M: a tensor view (kind
+// kLpF32 / kLpF64, ldi = I, omega unused) or the operand-form sample matrix
+// (kLpStored, L = 1, ldi = Ip, omega = its column weights).  q = 1:
+// C = M D M^T G.  q > 1: subspace iteration -- between steps the sketch is
+// replaced by an orthonormal basis of its range (its s left singular vectors,
+// float64), because rounding the raw iterate (AA^T)^i G to the operand format
+// would erase every direction below the format's precision relative to the
+// leading one; C = M D M^T Y_{q-1} has the range of (M D M^T)^q G.
+// G is overwritten for q > 1.
+int run_power_lp(const Plan& P, int kind, const void* M, int64_t L, int64_t I, int64_t R,
+                 int64_t ldi, const float* omega, const unsigned* xmax, int64_t s,
+                 double* G, double* C, void* ws, uint32_t* status, hipStream_t st) {
+  void* Cq = static_cast<char*>(ws) + P.oYq;
+  float* tau = reinterpret_cast<float*>(static_cast<char*>(ws) + P.oTau);
+  float* part = reinterpret_cast<float*>(static_cast<char*>(ws) + P.oPartLp);
+  const int64_t nblk = lp_blocks(I, s, L * R);
+  const int64_t Ip = lp_ip(I), SP = 16 * lp_nkt(s);
+  const double* src = G;
+  for (int step = 0; step < P.q; ++step) {
+    TR_TRY(launch_quant_y(P.prec, src, I, s, Cq, tau, st));
+    if (P.prec == TR_PREC_FP8E4M3)
+      TR_TRY(pw_lp_src<trk::OpFp8>(kind, s, M, L, I, R, ldi, Cq, tau, omega, xmax, part, nblk,
+                                   st));
+    else
+      TR_TRY(pw_lp_src<trk::OpBf16>(kind, s, M, L, I, R, ldi, Cq, tau, omega, xmax, part, nblk,
+                                    st));
+    hipLaunchKernelGGL(trk::k_reduce_parts_lp, dim3((unsigned)cdiv(I * s, 32)), dim3(kNT), 0, st,
+                       part, nblk, I, (int)s, (int)SP, (int)Ip, C, status);
+    TR_TRY(check_launch());
+    if (step + 1 < P.q) {
+      // C is dead after this call (it doubles as the factor's scratch)
+      TR_TRY(launch_factor(C, I, s, s, G, reinterpret_cast<double*>(static_cast<char*>(ws) + P.oYt),
+                           pad_width(s), reinterpret_cast<double*>(static_cast<char*>(ws) + P.oSig),
+                           nullptr, 0, status, C, st));
+      src = G;
+    }
+  }
+  return TR_OK;
+}
+
 template <int SM, bool G>
 int factor_k(const double* C, int I, int s, int mu, double* Q, double* Qt, int ldqt, double* sig,
              void* Qcast, int cast_f32, uint32_t* status, double* gA, hipStream_t st) {
@@ -628,7 +817,7 @@ int copy_d2d(void* dst, const void* src, size_t bytes, hipStream_t st) {
 // Range finder of mode n on tensor X (3-D view from the plan): fills Q64 / Qt
 // of the mode in the workspace and the caller's Q (cast to dtype).
 int range_finder(const Plan& P, int n, const void* X, void* ws, void* Qout,
-                 const tr_diag* diag, hipStream_t st) {
+                 const tr_diag* diag, bool need_xmax, hipStream_t st) {
   const ModePlan& M = P.m[n];
   tr_timer* tm = diag ? diag->timer : nullptr;
   uint32_t* status = diag ? diag->status : nullptr;
@@ -645,6 +834,7 @@ int range_finder(const Plan& P, int n, const void* X, void* ws, void* Qout,
   bool src_f64 = M.src_f64;
   int64_t L = M.L, R = M.R;
   const double* colw = nullptr;
+  const bool lp = P.prec != TR_PREC_NATIVE;
   if (M.sampled) {
     double* norms = at<double>(ws, P.oNorms);
     auto* maxb = at<unsigned long long>(ws, P.oMax);
@@ -664,7 +854,11 @@ int range_finder(const Plan& P, int n, const void* X, void* ws, void* Qout,
     }
     {
       TimeScope ts(tm, TR_KC_GATHER, n, st);
-      TR_TRY(launch_gather(M.src_f64, X, M.L, M.I, idx, M.T, at<void>(ws, P.oCp), st));
+      if (lp)
+        TR_TRY(launch_gather_lp(P.prec, M.src_f64, X, M.L, M.I, idx, M.T, scale2,
+                                at<void>(ws, P.oCq), at<float>(ws, P.oOmega), st));
+      else
+        TR_TRY(launch_gather(M.src_f64, X, M.L, M.I, idx, M.T, at<void>(ws, P.oCp), st));
     }
     if (diag && diag->indices && diag->indices[n])
       TR_TRY(copy_d2d(diag->indices[n], idx, 8 * (size_t)M.T, st));
@@ -676,7 +870,20 @@ int range_finder(const Plan& P, int n, const void* X, void* ws, void* Qout,
     colw = scale2;
   }
   // C_n = (M M^T)^q G_n, starting from Yt = G_n^T.
-  {
+  if (lp) {
+    unsigned* xmax = nullptr;
+    if (!M.sampled && P.prec == TR_PREC_FP8E4M3) {
+      xmax = at<unsigned>(ws, P.oXmax);
+      if (need_xmax) TR_TRY(launch_maxabs(M.src_f64, X, M.L * M.I * M.R, xmax, st));
+    }
+    TimeScope ts(tm, TR_KC_POWER, n, st);
+    if (M.sampled)
+      TR_TRY(run_power_lp(P, kLpStored, at<void>(ws, P.oCq), 1, M.I, M.T, lp_ip(M.I),
+                          at<float>(ws, P.oOmega), nullptr, M.s, G, Y, ws, status, st));
+    else
+      TR_TRY(run_power_lp(P, M.src_f64 ? kLpF64 : kLpF32, X, M.L, M.I, M.R, M.I, nullptr, xmax,
+                          M.s, G, Y, ws, status, st));
+  } else {
     TimeScope ts(tm, TR_KC_POWER, n, st);
     TR_TRY(run_power(src_f64, src, L, M.I, R, colw, P.q, M.s, M.sw, Y, Yt, Z, part, status, st));
   }
@@ -725,7 +932,8 @@ int run_thosvd(const tr_params* p, int dtype, const void* A, void* const* Q, voi
   Plan P;
   TR_TRY(make_plan(p, dtype, false, &P));
   TR_TRY(check_buffers(P, A, Q, core, ws, ws_bytes));
-  for (int n = 0; n < P.N; ++n) TR_TRY(range_finder(P, n, A, ws, Q[n], diag, st));
+  // every mode reads the same tensor: its max |entry| (FP8 scale) is taken once
+  for (int n = 0; n < P.N; ++n) TR_TRY(range_finder(P, n, A, ws, Q[n], diag, n == 0, st));
   int64_t shp[TR_MAX_ORDER];
   for (int k = 0; k < P.N; ++k) shp[k] = P.dims[k];
   const void* cur = A;
@@ -753,7 +961,7 @@ int run_sthosvd(const tr_params* p, int dtype, const void* A, void* const* Q, vo
   bool cur_f64 = dtype == TR_F64;
   tr_timer* tm = diag ? diag->timer : nullptr;
   for (int n = 0; n < P.N; ++n) {
-    TR_TRY(range_finder(P, n, cur, ws, Q[n], diag, st));
+    TR_TRY(range_finder(P, n, cur, ws, Q[n], diag, true, st));
     const ModePlan& M = P.m[n];
     void* out = nullptr;
     TR_TRY(shrink(P, n, n, cur, cur_f64, M.L, M.I, M.R, ws, core, tm, &out, st));

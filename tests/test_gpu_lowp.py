@@ -1,0 +1,165 @@
+"""Low-precision power products on the GPU (bfloat16 and FP8 e4m3 operands,
+float32 accumulation) against the emulation in oracle/lowp.py, and the
+relative Tucker error of the low-precision result against the FP64 oracle.
+
+Bars, per format (derivation: the device accumulates each 16 x 16 x 32
+product in float32 in an order of its own, so sums differ from the
+emulation's float64 ones by ~1e-7 relative; where such a difference moves a
+value across a rounding boundary of the operand format, one operand differs
+by one unit of the format, which moves the sketch by about the format's unit
+roundoff divided by sqrt(J) -- rare, and bounded by the Frobenius bars):
+* bfloat16: relative Frobenius difference of each mode's sketch <= 2e-3,
+  median relative difference per entry <= 1e-4;
+* e4m3: <= 2e-2 and <= 1e-3.
+With q > 1 the iterate is orthonormalised between steps (subspace
+iteration); its basis within nearly tied noise-level singular values is not
+determined, so those cases compare the leading mu-dimensional subspace
+(spectral norm of the projector difference) and the leading mu singular
+values against the Frobenius bar.
+The full-size configurations report the relative error RE of Eq. (8) of the
+low-precision result beside the FP64 oracle's RE and bound their ratio.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+import paper_2303_11612_amd as tr
+from oracle import lowp
+
+pytestmark = pytest.mark.gpu
+
+BARS = {"bf16": (2e-3, 1e-4), "fp8e4m3": (2e-2, 1e-3)}
+# bound on RE(low precision) / RE(FP64 oracle) on noisy low-rank tensors
+RE_RATIO = {"bf16": 1.5, "fp8e4m3": 30.0}
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _gpu(A, algo, ranks, K, q, prob, samples, seed, prec):
+    f = tr.tucker_rand_thosvd if algo == "thosvd" else tr.tucker_rand_sthosvd
+    Qs, core, info = f(tr.to_device(A), ranks, K, q, prob, samples, seed, precision=prec,
+                       diag=True)
+    torch.cuda.synchronize()
+    assert _np(info["status"])[0] == 0
+    return [_np(Q) for Q in Qs], _np(core), info
+
+
+def _check_sketch(Cg, Ce, prec, what):
+    fro, med = BARS[prec]
+    rel = np.linalg.norm(Cg - Ce) / np.linalg.norm(Ce)
+    e = np.abs(Cg - Ce) / np.maximum(np.abs(Ce), 1e-300)
+    assert rel <= fro, (what, rel)
+    assert np.median(e) <= med, (what, np.median(e))
+
+
+def _check_leading(Cg, Ce, mu, prec, what):
+    fro, _ = BARS[prec]
+    Qg, sg = oracle.leading_left_singular_vectors(Cg, mu)
+    Qe, se = oracle.leading_left_singular_vectors(Ce, mu)
+    assert np.linalg.norm(Qg @ Qg.T - Qe @ Qe.T, 2) <= fro, what
+    assert np.allclose(sg[:mu], se[:mu], rtol=fro), what
+
+
+CASES = [
+    # shape, ranks, K, q, prob, samples
+    ((61, 45, 33), (5, 4, 6), 10, 1, "none", None),
+    ((61, 45, 33), (5, 4, 6), 10, 2, "none", None),
+    ((12, 10, 9, 8), (3, 3, 2, 2), 5, 1, "none", None),
+    ((130, 40, 37), (6, 6, 6), 10, 1, "nearly_optimal", (300, 200, 200)),
+    ((300, 70, 20), (12, 8, 5), 10, 1, "uniform", (500, 400, 400)),
+    ((300, 70, 20), (12, 8, 5), 10, 2, "nearly_optimal", (500, 400, 400)),
+]
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8e4m3"])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_thosvd_sketches_match_emulation(prec, case):
+    shape, ranks, K, q, prob, samples = CASES[case]
+    A = synth.low_rank_plus_noise(shape, ranks, 1e-3, 40 + case, np.float32)
+    seed = 11 + case
+    Qg, cg, info = _gpu(A, "thosvd", ranks, K, q, prob, samples, seed, prec)
+    A64 = A.astype(np.float64)
+    for n in range(A.ndim):
+        I = shape[n]
+        s = min(ranks[n] + K, I)
+        An = oracle.unfold(A64, n)
+        xi = scale = None
+        if prob != "none" and samples[n] <= An.shape[1]:
+            norms = oracle.column_sq_norms(An) if prob == "nearly_optimal" else None
+            xi, scale, _, _ = oracle.randsample(norms, An.shape[1], samples[n], prob, seed, n)
+            assert np.array_equal(_np(info["indices"][n]), xi)
+        Ce = lowp.power_sketch_lp(A, n, s, q, prec, seed, xi, scale)
+        Cg = _np(info["sketch"][n])
+        if q == 1:
+            _check_sketch(Cg, Ce, prec, (case, n))
+        else:
+            # q > 1: the iterate's basis within the noise-level singular
+            # values (nearly tied) is arbitrary, so only the leading
+            # subspace and singular values are determined
+            _check_leading(Cg, Ce, ranks[n], prec, (case, n))
+        # the factor is the float64 SVD of the sketch: orthonormal columns
+        assert np.allclose(Qg[n].T @ Qg[n], np.eye(ranks[n]), atol=1e-5)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8e4m3"])
+def test_sthosvd_first_mode_matches_emulation(prec):
+    A = synth.low_rank_plus_noise((200, 30, 24), (8, 5, 4), 1e-3, 9, np.float64)
+    Qg, cg, info = _gpu(A, "sthosvd", (8, 5, 4), 10, 1, "none", None, 4, prec)
+    Ce = lowp.power_sketch_lp(A, 0, 18, 1, prec, 4)
+    _check_sketch(_np(info["sketch"][0]), Ce, prec, "mode 1")
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8e4m3"])
+def test_lowp_relative_error_close_to_fp64(prec):
+    A = synth.low_rank_plus_noise((120, 90, 60), (8, 8, 8), 1e-3, 21, np.float32)
+    A64 = A.astype(np.float64)
+    Qg, cg, _ = _gpu(A, "sthosvd", (8, 8, 8), 10, 1, "nearly_optimal", (400, 400, 400), 3,
+                     prec)
+    Qo, co, _ = oracle.rand_sthosvd(A64, (8, 8, 8), 10, 1, "nearly_optimal", (400, 400, 400), 3)
+    re_o = oracle.relative_error(A64, co, Qo)
+    re_g = oracle.relative_error(A64, cg.astype(np.float64), [Q.astype(np.float64) for Q in Qg])
+    print(f"120x90x60, noise 1e-3, {prec}: RE {re_g:.6e}, fp64 oracle RE {re_o:.6e}")
+    # rounding the data to the operand format adds an error of about its unit
+    # roundoff per entry (bfloat16 2^-9, e4m3 2^-4 relative), comparable here
+    # to the tensor's own noise of 1e-3
+    assert re_g <= re_o * RE_RATIO[prec], (re_g, re_o)
+
+
+def test_unsupported_shapes_rejected():
+    A = tr.to_device(np.zeros((600, 4, 4), np.float32))
+    with pytest.raises(RuntimeError, match="not supported"):
+        tr.tucker_rand_thosvd(A, (2, 2, 2), 10, 1, precision="bf16")
+
+
+def test_config3_full_size_bf16():
+    w = synth.config(3, 0)
+    A64 = w.A.astype(np.float64)
+    Qg, cg, _ = _gpu(w.A, "thosvd", w.ranks, w.oversample, w.power, "none", None, 0, "bf16")
+    Qo, co, _ = oracle.rand_thosvd(A64, w.ranks, w.oversample, w.power, "none", None, 0)
+    re_o = oracle.relative_error(A64, co, Qo)
+    re_g = oracle.relative_error(A64, cg.astype(np.float64), [Q.astype(np.float64) for Q in Qg])
+    print(f"config 3, bf16: RE {re_g:.6e}, fp64 oracle RE {re_o:.6e}")
+    assert re_g <= RE_RATIO["bf16"] * re_o
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8e4m3"])
+def test_config4_full_size(prec):
+    w = synth.config(4, 0)
+    A64 = w.A.astype(np.float64)
+    Qg, cg, info = _gpu(w.A, "thosvd", w.ranks, w.oversample, w.power, w.prob, w.samples, 0,
+                        prec)
+    # mode-1 sketch against the emulation (sampled columns: bit-exact indices)
+    An = oracle.unfold(A64, 0)
+    xi, scale, _, _ = oracle.randsample(None, An.shape[1], w.samples[0], "uniform", 0, 0)
+    assert np.array_equal(_np(info["indices"][0]), xi)
+    Ce = lowp.power_sketch_lp(w.A, 0, w.ranks[0] + w.oversample, 1, prec, 0, xi, scale)
+    _check_sketch(_np(info["sketch"][0]), Ce, prec, "config 4 mode 1")
+    Qo, co, _ = oracle.rand_thosvd(A64, w.ranks, w.oversample, w.power, w.prob, w.samples, 0)
+    re_o = oracle.relative_error(A64, co, Qo)
+    re_g = oracle.relative_error(A64, cg.astype(np.float64), [Q.astype(np.float64) for Q in Qg])
+    print(f"config 4, {prec}: RE {re_g:.6e}, fp64 oracle RE {re_o:.6e}")
+    assert re_g <= re_o * RE_RATIO[prec]
