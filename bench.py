@@ -41,9 +41,12 @@ def _parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU time budget of the oracle baseline")
-    ap.add_argument("--workload", choices=("all", "decomp", "serving"), default="all",
+    ap.add_argument("--workload", choices=("all", "decomp", "serving", "precision"),
+                    default="all",
                     help="decomp: the 400^3 decomposition line only; serving: the "
-                         "request stream only; all: both in one line")
+                         "request stream only; precision: the low-precision forms of "
+                         "the 100^4 and 512x512x256 configurations; all: everything "
+                         "in one line")
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--budget-gb", type=float, default=16.0)
@@ -118,9 +121,21 @@ def main():
                "serving": srv}
         print(json.dumps(out), flush=True)
         return
+    if args.workload == "precision":
+        prec = bench_precision(args)
+        c3 = prec["config3"]
+        out = {"metric": METRIC, "value": c3["bf16"]["decomp_per_s"], "unit": "decomp/s",
+               "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+               "ms_per_step": c3["bf16"]["ms"], "higher_is_better": True, "scaling": "weak",
+               "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+               "config": {"workload": c3["workload"], "parallelism": "single GPU"},
+               "precision": prec}
+        print(json.dumps(out), flush=True)
+        return
     out = bench_decomp(args)
     if args.workload == "all":
         out["serving"] = bench_serving(args)
+        out["precision"] = bench_precision(args)
     print(json.dumps(out), flush=True)
 
 
@@ -257,6 +272,92 @@ def bench_decomp(args):
                                             np.linalg.norm(Qo[n])) for n in range(N)),
             "core_rel_err": float(np.linalg.norm(cg - co) / np.linalg.norm(co))}
     return out
+
+
+def _re_fp64(X, Qs, core):
+    """||A - core x_1 Q_1 ... x_N Q_N||_F / ||A||_F in float64 on the device (Eq. (8))."""
+    import torch
+    A = X.double()
+    B = core.double()
+    for n, Q in enumerate(Qs):
+        B = torch.movedim(torch.tensordot(Q.double(), B, dims=([1], [n])), 0, n)
+    return float(torch.linalg.vector_norm(A - B) / torch.linalg.vector_norm(A))
+
+
+def bench_precision(args):
+    """Decomposition time and relative error of the float64 path and of the
+    low-precision power products on the 100^4 configuration (T-HOSVD, q = 2,
+    exact products: float64 vs bfloat16) and the 512 x 512 x 256 one
+    (T-HOSVD, q = 1, 8000 uniformly sampled columns: float64 vs bfloat16 vs
+    FP8 e4m3).  The relative errors come from a float64 reconstruction; the
+    FP64 oracle's error is added by the CPU baseline leg."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2303_11612_amd as tr
+
+    steps = max(2, min(args.steps, 10))
+    res = {}
+    for k, precs, name in ((3, ("native", "bf16"),
+                            "rand T-HOSVD (Alg. 1), 100^4 float32, ranks 20, K 10, q 2"),
+                           (4, ("native", "bf16", "fp8e4m3"),
+                            "rand T-HOSVD + sampled products (Alg. 4), 512x512x256 float32 "
+                            "bumps, ranks (30,30,15), K 10, q 1, T_n 8000 uniform")):
+        w = synth.config(k, args.seed)
+        X = tr.to_device(w.A)
+        entry = {"workload": name}
+        for prec in precs:
+            wsb = tr.tucker_rand_workspace_size(w.dims, w.ranks, w.oversample, w.power, w.prob,
+                                                w.samples, args.seed, torch.float32,
+                                                sthosvd=False, precision=prec)
+            ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+            Qs = [tr.colmajor_empty((w.dims[n], w.ranks[n]), torch.float32)
+                  for n in range(len(w.dims))]
+            core = tr.colmajor_empty(w.ranks, torch.float32)
+
+            def step(tm=None):
+                tr.tucker_rand_thosvd(X, w.ranks, w.oversample, w.power, w.prob, w.samples,
+                                      args.seed, precision=prec, workspace=ws, out=(Qs, core),
+                                      timer=tm)
+            for _ in range(2):
+                step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                step()
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / steps
+            timer = tr.Timer(capacity=64 * (steps + 1), classes=("power",))
+            timer.reset()
+            for _ in range(steps):
+                step(timer)
+            torch.cuda.synchronize()
+            ptot, pcnt, _, _ = timer.read("power")
+            entry[prec] = {"ms": round(ms, 4), "decomp_per_s": round(1e3 / ms, 2),
+                           "power_ms_per_decomp": round(ptot / steps, 4),
+                           "re": _re_fp64(X, Qs, core)}
+            if prec == "native":
+                entry[prec]["Q"] = [Q.double().cpu().numpy() for Q in Qs]
+            else:
+                Qn = entry["native"]["Q"]
+                # largest principal-angle sine between the low-precision and
+                # the float64 factors' subspaces, per mode
+                entry[prec]["subspace_sin_vs_native"] = [
+                    float(np.linalg.norm(Q.double().cpu().numpy() @ Q.double().cpu().numpy().T
+                                         - Qn[n] @ Qn[n].T, 2)) for n, Q in enumerate(Qs)]
+                entry[prec]["re_ratio_vs_native"] = entry[prec]["re"] / entry["native"]["re"]
+            del ws
+        entry["native"].pop("Q")
+        if not args.no_cpu_baseline:
+            import oracle
+            A64 = w.A.astype(np.float64)
+            Qo, co, _ = oracle.rand_thosvd(A64, w.ranks, w.oversample, w.power, w.prob,
+                                           w.samples, args.seed)
+            entry["re_oracle_fp64"] = oracle.relative_error(A64, co, Qo)
+        res[f"config{k}"] = entry
+        del X
+        torch.cuda.empty_cache()
+    return res
 
 
 def bench_serving(args):

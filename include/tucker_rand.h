@@ -63,8 +63,23 @@ typedef enum {
   TR_PROB_UNIFORM = 2          /* p_j = 1/J_n:             Alg. 4 / Alg. 5      */
 } tr_prob;
 
-/* Arithmetic of the large contractions.  TR_PREC_NATIVE accumulates every
- * product, norm and factor in float64 (float32 inputs are widened exactly). */
+/* Arithmetic of the power-scheme products C_n = (M D M^T)^q G_n, M = A_(n)
+ * (Alg. 1 / 2) or the sampled C'_n (Alg. 4 / 5).
+ *   TR_PREC_NATIVE: every product, norm and factor in float64 (float32
+ *     inputs are widened exactly).
+ *   TR_PREC_BF16 / TR_PREC_FP8E4M3: one fused pass over M per power step on
+ *     the matrix cores.  M is rounded to bfloat16, or to FP8 e4m3 (OCP
+ *     "e4m3fn", max 448) with one scale for a tensor and one per column for
+ *     C'_n; C is rounded per step (per-column scale for e4m3); M^T C is
+ *     formed in that format with float32 accumulation and D M^T C enters the
+ *     second product as a bfloat16 pair (about 16 bits).  Block partial sums
+ *     are added in float64.  For q > 1 the iterate is replaced between steps
+ *     by an orthonormal basis of its range (float64), which keeps the range
+ *     of (M D M^T)^q G_n.  Column norms, sampling probabilities, the QR / SVD
+ *     of the sketch and the shrink stay float64.  Supported for I_n <= 512,
+ *     s_n <= 48 and, for unsampled modes, J_n < 2^32 (else TR_ENOTSUP).
+ *     The rounding of M adds about the format's unit roundoff (2^-9 or 2^-4
+ *     relative) to each entry of the data the range finder sees. */
 typedef enum { TR_PREC_NATIVE = 0, TR_PREC_BF16 = 1, TR_PREC_FP8E4M3 = 2 } tr_prec;
 
 /* Device status bits (OR-ed into tr_diag.status). */
