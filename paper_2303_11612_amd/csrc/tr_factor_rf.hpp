@@ -275,7 +275,8 @@ k_factor_rf(const double* __restrict__ C, int I, int s, int mu, double* __restri
   //         pair g on DPP row g / 4 of wave g % 4.  Each lane holds RU
   //         consecutive rows of the pair's two columns.  Column norms are
   //         recomputed at the start of each sweep and then updated with each
-  //         rotation (a' = a - t c, b' = b + t c). ----
+  //         rotation (a' = a - t c, b' = b + t c).  The sweeps end after one
+  //         without a rotation larger than tol_big (see below). ----
   {
     constexpr bool kOneWave = SM == 16;
     constexpr int LP = kOneWave ? 8 : 16;  // lanes per pair
@@ -286,6 +287,10 @@ k_factor_rf(const double* __restrict__ C, int I, int s, int mu, double* __restri
     const bool gact = slot < np;
     const int gg = gact ? slot : 0;
     const double tol = 2.0 * s * 2.220446049250313e-16;
+    // Cyclic Jacobi converges quadratically: after a sweep whose rotations
+    // all had |x.y| / (|x| |y|) <= tol_big = sqrt(tol) / 10, every pair is
+    // below tol, so the sweep that would only confirm it is skipped.
+    const double tol_big = 0.1 * sqrt(tol);
     double* jn = sig;  // column norms^2 during the sweeps
     if (!kOneWave || wid == 0) {
       for (int sweep = 0; sweep < 40 && se > 1; ++sweep) {
@@ -340,7 +345,7 @@ k_factor_rf(const double* __restrict__ C, int I, int s, int mu, double* __restri
               jn[p] = fma(-t, cc, aa);
               jn[q] = fma(t, cc, bb);
             }
-            rot = 1;
+            rot |= rel > tol_big ? 1 : 0;
           }
           if (!kOneWave) __syncthreads();
           if (pp >= 0) pp = pp + 1 == sm1 ? 0 : pp + 1;
