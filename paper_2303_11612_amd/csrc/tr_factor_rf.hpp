@@ -132,11 +132,17 @@ __device__ __forceinline__ void householder(double alpha, double sum2, double* b
   }
 }
 
+// Workgroup b factors jobs.j[b] (several independent sketches per launch).
 template <int SM, int R, int MU>
 __global__ void __launch_bounds__(256)
-k_factor_rf(const double* __restrict__ C, int I, int s, int mu, double* __restrict__ Q,
-            double* __restrict__ Qt, int ldqt, double* __restrict__ sig_out,
-            void* __restrict__ Qcast, int cast_f32, uint32_t* __restrict__ status) {
+k_factor_rf(FactorJobs jobs, int cast_f32, uint32_t* __restrict__ status) {
+  const FactorJob& jb = jobs.j[blockIdx.x];
+  const double* __restrict__ C = jb.C;
+  const int I = jb.I, s = jb.s, mu = jb.mu, ldqt = jb.ldqt;
+  double* __restrict__ Q = jb.Q;
+  double* __restrict__ Qt = jb.Qt;
+  double* __restrict__ sig_out = jb.sig;
+  void* __restrict__ Qcast = jb.Qcast;
   using S = RfShape<SM>;
   constexpr int NT = S::NT, NW = NT / kWave, LDX = S::LDX;
   static_assert(MU <= SM && MU % 8 == 0, "column bound");

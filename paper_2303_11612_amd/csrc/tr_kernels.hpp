@@ -572,12 +572,37 @@ __device__ __forceinline__ void jacobi_pair(int g, int step, int se, int* pp, in
   *qq = p < q ? q : p;
 }
 
+// One factorization of a batch: the sketch C (I x s), its outputs Q (I x mu),
+// Qt (row stride ldqt), sigma and the optional cast copy of Q, and (global
+// variant) the I x s scratch gA; Q doubles as the I x mu scratch there.
+struct FactorJob {
+  const double* C;
+  double* Q;
+  double* Qt;
+  double* sig;
+  void* Qcast;
+  double* gA;
+  int I, s, mu, ldqt;
+};
+constexpr int kMaxFactorJobs = 8;
+// Independent factorizations launched together, one workgroup each (by value
+// in the kernel arguments; workgroup b takes j[b]).
+struct FactorJobs {
+  FactorJob j[kMaxFactorJobs];
+};
+
 template <int SM, bool kGlobal>
 __global__ void __launch_bounds__(kFactorNT)
-k_factor(const double* __restrict__ C, int I, int s, int mu, double* __restrict__ Q,
-         double* __restrict__ Qt, int ldqt, double* __restrict__ sig_out,
-         void* __restrict__ Qcast, int cast_f32, uint32_t* __restrict__ status,
-         double* __restrict__ gA, double* __restrict__ gZ) {
+k_factor(FactorJobs jobs, int cast_f32, uint32_t* __restrict__ status) {
+  const FactorJob& jb = jobs.j[blockIdx.x];
+  const double* __restrict__ C = jb.C;
+  const int I = jb.I, s = jb.s, mu = jb.mu, ldqt = jb.ldqt;
+  double* __restrict__ Q = jb.Q;
+  double* __restrict__ Qt = jb.Qt;
+  double* __restrict__ sig_out = jb.sig;
+  void* __restrict__ Qcast = jb.Qcast;
+  double* __restrict__ gA = jb.gA;
+  double* __restrict__ gZ = jb.Q;
   using F = FactorShape<SM>;
   constexpr int NT = F::NT, NW = F::NW, LDR = F::LDR, H = SM / 2, HW = (H + NW - 1) / NW;
   constexpr int CH = SM < 16 ? SM : 16;  // columns per register chunk

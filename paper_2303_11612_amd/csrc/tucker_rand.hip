@@ -163,6 +163,9 @@ struct Plan {
   int prec = TR_PREC_NATIVE;
   size_t oYq = 0, oTau = 0, oPartLp = 0, oCq = 0, oOmega = 0, oXmax = 0;
   size_t oQ[TR_MAX_ORDER], oQt[TR_MAX_ORDER];
+  // T-HOSVD: every mode's sketch and singular values are kept until the
+  // factorizations of all modes run in one launch
+  size_t oYn[TR_MAX_ORDER] = {}, oSign[TR_MAX_ORDER] = {};
 };
 
 // Validates and fills the plan; returns TR_OK or an error code.
@@ -296,6 +299,11 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
     P->oQ[n] = take(8 * (size_t)(P->m[n].I * P->m[n].mu));
     P->oQt[n] = take(8 * (size_t)(P->m[n].I * P->m[n].muw));
   }
+  if (!sthosvd)
+    for (int n = 0; n < N; ++n) {
+      P->oYn[n] = take(8 * (size_t)(P->m[n].I * P->m[n].s));
+      P->oSign[n] = take(8 * (size_t)P->m[n].s);
+    }
   P->oX0 = take(8 * maxInter);
   P->oX1 = take(8 * maxInter);
   P->oCore = take(8 * core_el);
@@ -723,19 +731,6 @@ int run_power_lp(const Plan& P, int kind, const void* M, int64_t L, int64_t I, i
   return TR_OK;
 }
 
-template <int SM, bool G>
-int factor_k(const double* C, int I, int s, int mu, double* Q, double* Qt, int ldqt, double* sig,
-             void* Qcast, int cast_f32, uint32_t* status, double* gA, hipStream_t st) {
-  const size_t lds = trk::FactorShape<SM>::lds_bytes(I, s, mu, G);
-  if (lds > 65536 &&
-      hipFuncSetAttribute((const void*)&trk::k_factor<SM, G>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-    return TR_EDEVICE;
-  hipLaunchKernelGGL((trk::k_factor<SM, G>), dim3(1), dim3(trk::kFactorNT), lds, st, C, I, s,
-                     mu, Q, Qt, ldqt, sig, Qcast, cast_f32, status, gA, Q);
-  return check_launch();
-}
-
 // TUCKER_RAND_FACTOR=lds selects the LDS-resident factor kernel for every
 // shape (both variants are then testable on the same inputs).
 inline bool force_lds_factor() {
@@ -743,60 +738,114 @@ inline bool force_lds_factor() {
   return v != nullptr && std::strcmp(v, "lds") == 0;
 }
 
+inline bool factor_rf_covers(int64_t I, int64_t s, int64_t mu) {
+  return I <= 512 && s <= 32 && (I <= 256 || s <= 16 || mu <= 16);
+}
+
+// Kernel instance a factorization runs in: the register-resident kernel
+// (s <= 32, I <= 512, mu <= 16 when I > 256 with s > 16), else the LDS-
+// resident one, else the one with its working matrices in global scratch.
+static_assert(trk::kMaxFactorJobs >= TR_MAX_ORDER, "one factorization job per mode");
+
+enum FactorVariant {
+  kRf16x1, kRf16x2, kRf32x1, kRf32x2, kLds16, kLds32, kLds64, kGlb16, kGlb32, kGlb64
+};
+
+int factor_variant(int64_t I, int64_t s, int64_t mu, bool has_scratch, int* var) {
+  if (!factor_supported(I, s) || mu < 1 || mu > s) return TR_ENOTSUP;
+  if (factor_rf_covers(I, s, mu) && !force_lds_factor()) {
+    const bool r1 = I <= 256;
+    if (s <= 16) *var = r1 ? kRf16x1 : kRf16x2;
+    else *var = r1 ? kRf32x1 : kRf32x2;
+    return TR_OK;
+  }
+  const int sm = factor_sm(s);
+  const int k = sm == 16 ? 0 : (sm == 32 ? 1 : 2);
+  if (factor_in_lds(I, s, mu)) {
+    *var = kLds16 + k;
+    return TR_OK;
+  }
+  if (!has_scratch) return TR_ENOMEM;
+  *var = kGlb16 + k;
+  return TR_OK;
+}
+
 template <int SM, int R, int MU>
-int factor_rf(const double* C, int I, int s, int mu, double* Q, double* Qt, int ldqt, double* sig,
-              void* Qcast, int cast_f32, uint32_t* status, hipStream_t st) {
+int factor_rf_jobs(const trk::FactorJobs& jobs, int n, int cast_f32, uint32_t* status,
+                   hipStream_t st) {
   const size_t lds = trk::RfShape<SM>::lds_bytes();
   if (lds > 65536 &&
       hipFuncSetAttribute((const void*)&trk::k_factor_rf<SM, R, MU>,
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return TR_EDEVICE;
-  hipLaunchKernelGGL((trk::k_factor_rf<SM, R, MU>), dim3(1), dim3(trk::RfShape<SM>::NT), lds, st,
-                     C, I, s, mu, Q, Qt, ldqt, sig, Qcast, cast_f32, status);
+  hipLaunchKernelGGL((trk::k_factor_rf<SM, R, MU>), dim3((unsigned)n), dim3(trk::RfShape<SM>::NT),
+                     lds, st, jobs, cast_f32, status);
   return check_launch();
 }
 
-// Register-resident variant: s <= 32, I <= 512, and mu <= 16 when I > 256
-// with s > 16.  Returns TR_ENOTSUP for shapes it does not cover.
-int launch_factor_rf(const double* C, int I, int s, int mu, double* Q, double* Qt, int ldqt,
-                     double* sig, void* Qcast, int cast_f32, uint32_t* status, hipStream_t st) {
-  if (I > 512 || s > 32) return TR_ENOTSUP;
-  const bool r1 = I <= 256;
-  if (s <= 16)
-    return r1 ? factor_rf<16, 1, 16>(C, I, s, mu, Q, Qt, ldqt, sig, Qcast, cast_f32, status, st)
-              : factor_rf<16, 2, 16>(C, I, s, mu, Q, Qt, ldqt, sig, Qcast, cast_f32, status, st);
-  if (r1) return factor_rf<32, 1, 32>(C, I, s, mu, Q, Qt, ldqt, sig, Qcast, cast_f32, status, st);
-  if (mu <= 16)
-    return factor_rf<32, 2, 16>(C, I, s, mu, Q, Qt, ldqt, sig, Qcast, cast_f32, status, st);
-  return TR_ENOTSUP;
+template <int SM, bool G>
+int factor_k_jobs(const trk::FactorJobs& jobs, int n, int cast_f32, uint32_t* status,
+                  hipStream_t st) {
+  size_t lds = 0;
+  for (int b = 0; b < n; ++b)
+    lds = std::max(lds, trk::FactorShape<SM>::lds_bytes(jobs.j[b].I, jobs.j[b].s, jobs.j[b].mu, G));
+  if (lds > 65536 &&
+      hipFuncSetAttribute((const void*)&trk::k_factor<SM, G>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return TR_EDEVICE;
+  hipLaunchKernelGGL((trk::k_factor<SM, G>), dim3((unsigned)n), dim3(trk::kFactorNT), lds, st,
+                     jobs, cast_f32, status);
+  return check_launch();
 }
 
-inline bool factor_rf_covers(int64_t I, int64_t s, int64_t mu) {
-  return I <= 512 && s <= 32 && (I <= 256 || s <= 16 || mu <= 16);
+int launch_factor_group(int var, const trk::FactorJobs& jobs, int n, int cast_f32,
+                        uint32_t* status, hipStream_t st) {
+  switch (var) {
+    case kRf16x1: return factor_rf_jobs<16, 1, 16>(jobs, n, cast_f32, status, st);
+    case kRf16x2: return factor_rf_jobs<16, 2, 16>(jobs, n, cast_f32, status, st);
+    case kRf32x1: return factor_rf_jobs<32, 1, 32>(jobs, n, cast_f32, status, st);
+    case kRf32x2: return factor_rf_jobs<32, 2, 16>(jobs, n, cast_f32, status, st);
+    case kLds16: return factor_k_jobs<16, false>(jobs, n, cast_f32, status, st);
+    case kLds32: return factor_k_jobs<32, false>(jobs, n, cast_f32, status, st);
+    case kLds64: return factor_k_jobs<64, false>(jobs, n, cast_f32, status, st);
+    case kGlb16: return factor_k_jobs<16, true>(jobs, n, cast_f32, status, st);
+    case kGlb32: return factor_k_jobs<32, true>(jobs, n, cast_f32, status, st);
+    default: return factor_k_jobs<64, true>(jobs, n, cast_f32, status, st);
+  }
 }
 
-// Q (I x mu, float64), Qt (row stride ldqt, zero padding), sigma, optional
-// cast copy of Q in the caller's dtype.  gA: I x s float64 scratch, needed
-// only when the working matrices do not fit in LDS (may equal C).
+// Independent factorizations (n <= kMaxFactorJobs): one launch per kernel
+// instance, one workgroup per job, so jobs of the same instance run side by
+// side.  Each job: Q (I x mu, float64), Qt (row stride ldqt, zero padding),
+// sigma, optional cast copy of Q in the caller's dtype; gA: I x s float64
+// scratch, needed only when the working matrices do not fit in LDS (may
+// equal C).
+int launch_factor_jobs(const trk::FactorJob* job, int n, int cast_f32, uint32_t* status,
+                       hipStream_t st) {
+  if (n < 1 || n > trk::kMaxFactorJobs) return TR_EINVAL;
+  int var[trk::kMaxFactorJobs];
+  for (int b = 0; b < n; ++b)
+    TR_TRY(factor_variant(job[b].I, job[b].s, job[b].mu, job[b].gA != nullptr, &var[b]));
+  bool done[trk::kMaxFactorJobs] = {};
+  for (int b = 0; b < n; ++b) {
+    if (done[b]) continue;
+    trk::FactorJobs group{};
+    int m = 0;
+    for (int c = b; c < n; ++c)
+      if (!done[c] && var[c] == var[b]) {
+        group.j[m++] = job[c];
+        done[c] = true;
+      }
+    TR_TRY(launch_factor_group(var[b], group, m, cast_f32, status, st));
+  }
+  return TR_OK;
+}
+
 int launch_factor(const double* C, int64_t I, int64_t s, int64_t mu, double* Q, double* Qt,
                   int ldqt, double* sig, void* Qcast, int cast_f32, uint32_t* status,
                   double* gA, hipStream_t st) {
-  if (!factor_supported(I, s) || mu < 1 || mu > s) return TR_ENOTSUP;
-  if (factor_rf_covers(I, s, mu) && !force_lds_factor())
-    return launch_factor_rf(C, (int)I, (int)s, (int)mu, Q, Qt, ldqt, sig, Qcast, cast_f32, status,
-                            st);
-  const bool lds = factor_in_lds(I, s, mu);
-  if (!lds && !gA) return TR_ENOMEM;
-  const int sm = factor_sm(s);
-  const int Ii = (int)I, si = (int)s, mi = (int)mu;
-  if (lds) {
-    if (sm == 16) return factor_k<16, false>(C, Ii, si, mi, Q, Qt, ldqt, sig, Qcast, cast_f32, status, nullptr, st);
-    if (sm == 32) return factor_k<32, false>(C, Ii, si, mi, Q, Qt, ldqt, sig, Qcast, cast_f32, status, nullptr, st);
-    return factor_k<64, false>(C, Ii, si, mi, Q, Qt, ldqt, sig, Qcast, cast_f32, status, nullptr, st);
-  }
-  if (sm == 16) return factor_k<16, true>(C, Ii, si, mi, Q, Qt, ldqt, sig, Qcast, cast_f32, status, gA, st);
-  if (sm == 32) return factor_k<32, true>(C, Ii, si, mi, Q, Qt, ldqt, sig, Qcast, cast_f32, status, gA, st);
-  return factor_k<64, true>(C, Ii, si, mi, Q, Qt, ldqt, sig, Qcast, cast_f32, status, gA, st);
+  trk::FactorJob jb{C, Q, Qt, sig, Qcast, gA, (int)I, (int)s, (int)mu, ldqt};
+  return launch_factor_jobs(&jb, 1, cast_f32, status, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -816,13 +865,14 @@ int copy_d2d(void* dst, const void* src, size_t bytes, hipStream_t st) {
 
 // Range finder of mode n on tensor X (3-D view from the plan): fills Q64 / Qt
 // of the mode in the workspace and the caller's Q (cast to dtype).
-int range_finder(const Plan& P, int n, const void* X, void* ws, void* Qout,
-                 const tr_diag* diag, bool need_xmax, hipStream_t st) {
+// Sketch of mode n of tensor X (3-D view from the plan): C_n = (M M^T)^q G_n
+// into Y (I x s, float64).
+int range_sketch(const Plan& P, int n, const void* X, void* ws, const tr_diag* diag,
+                 bool need_xmax, double* Y, hipStream_t st) {
   const ModePlan& M = P.m[n];
   tr_timer* tm = diag ? diag->timer : nullptr;
   uint32_t* status = diag ? diag->status : nullptr;
   double* G = at<double>(ws, P.oG);
-  double* Y = at<double>(ws, P.oY);
   double* Yt = at<double>(ws, P.oYt);
   double* Z = at<double>(ws, P.oZ);
   double* part = at<double>(ws, P.oPart);
@@ -889,14 +939,32 @@ int range_finder(const Plan& P, int n, const void* X, void* ws, void* Qout,
   }
   if (diag && diag->sketch && diag->sketch[n])
     TR_TRY(copy_d2d(diag->sketch[n], Y, 8 * (size_t)(M.I * M.s), st));
-  double* sig = (diag && diag->sigma && diag->sigma[n]) ? diag->sigma[n] : at<double>(ws, P.oSig);
-  {
-    TimeScope ts(tm, TR_KC_FACTOR, n, st);
-    // the sketch Y is dead after this call: it doubles as the factor's scratch
-    TR_TRY(launch_factor(Y, M.I, M.s, M.mu, at<double>(ws, P.oQ[n]), at<double>(ws, P.oQt[n]),
-                         M.muw, sig, Qout, P.dtype == TR_F32, status, Y, st));
-  }
   return TR_OK;
+}
+
+// The factorization of mode n's sketch Y: Q64 / Qt of the mode in the
+// workspace and the caller's Q (cast to dtype).  Y is dead afterwards (it
+// doubles as the factor's scratch).
+trk::FactorJob factor_job(const Plan& P, int n, double* Y, double* sig, void* ws, void* Qout) {
+  const ModePlan& M = P.m[n];
+  return trk::FactorJob{Y, at<double>(ws, P.oQ[n]), at<double>(ws, P.oQt[n]), sig, Qout, Y,
+                        (int)M.I, (int)M.s, (int)M.mu, M.muw};
+}
+
+double* mode_sigma(const Plan& P, int n, const tr_diag* diag, void* ws, size_t off) {
+  return (diag && diag->sigma && diag->sigma[n]) ? diag->sigma[n] : at<double>(ws, off);
+}
+
+// Range finder of mode n (ST-HOSVD: sketch, then factor).
+int range_finder(const Plan& P, int n, const void* X, void* ws, void* Qout,
+                 const tr_diag* diag, bool need_xmax, hipStream_t st) {
+  double* Y = at<double>(ws, P.oY);
+  TR_TRY(range_sketch(P, n, X, ws, diag, need_xmax, Y, st));
+  tr_timer* tm = diag ? diag->timer : nullptr;
+  uint32_t* status = diag ? diag->status : nullptr;
+  TimeScope ts(tm, TR_KC_FACTOR, n, st);
+  const trk::FactorJob jb = factor_job(P, n, Y, mode_sigma(P, n, diag, ws, P.oSig), ws, Qout);
+  return launch_factor_jobs(&jb, 1, P.dtype == TR_F32, status, st);
 }
 
 int check_buffers(const Plan& P, const void* A, void* const* Q, const void* core, void* ws,
@@ -932,8 +1000,19 @@ int run_thosvd(const tr_params* p, int dtype, const void* A, void* const* Q, voi
   Plan P;
   TR_TRY(make_plan(p, dtype, false, &P));
   TR_TRY(check_buffers(P, A, Q, core, ws, ws_bytes));
-  // every mode reads the same tensor: its max |entry| (FP8 scale) is taken once
-  for (int n = 0; n < P.N; ++n) TR_TRY(range_finder(P, n, A, ws, Q[n], diag, n == 0, st));
+  // the modes are independent: all sketches first (every mode reads the same
+  // tensor, so its max |entry| -- the FP8 scale -- is taken once), then all
+  // factorizations in one launch per kernel instance
+  trk::FactorJob jobs[TR_MAX_ORDER];
+  for (int n = 0; n < P.N; ++n) {
+    double* Yn = at<double>(ws, P.oYn[n]);
+    TR_TRY(range_sketch(P, n, A, ws, diag, n == 0, Yn, st));
+    jobs[n] = factor_job(P, n, Yn, mode_sigma(P, n, diag, ws, P.oSign[n]), ws, Q[n]);
+  }
+  {
+    TimeScope ts(diag ? diag->timer : nullptr, TR_KC_FACTOR, 0, st);
+    TR_TRY(launch_factor_jobs(jobs, P.N, P.dtype == TR_F32, diag ? diag->status : nullptr, st));
+  }
   int64_t shp[TR_MAX_ORDER];
   for (int k = 0; k < P.N; ++k) shp[k] = P.dims[k];
   const void* cur = A;

@@ -71,9 +71,17 @@ def test_unsupported_requests():
     with pytest.raises(_abi.TuckerRandError) as e:
         _ws((200, 200, 200), (60, 10, 10), 10, 1)        # s = 70 > 64
     assert e.value.code == _abi.TR_ENOTSUP
+    # low-precision power products: I_n <= 512 and s_n <= 48
     with pytest.raises(_abi.TuckerRandError) as e:
-        _ws((20, 20, 20), (4, 4, 4), 4, 1, precision="bf16")
+        _ws((600, 20, 20), (4, 4, 4), 4, 1, precision="bf16")
     assert e.value.code == _abi.TR_ENOTSUP
+    with pytest.raises(_abi.TuckerRandError) as e:
+        _ws((100, 100, 100), (40, 4, 4), 10, 1, precision="fp8e4m3")   # s = 50
+    assert e.value.code == _abi.TR_ENOTSUP
+    assert _ws((20, 20, 20), (4, 4, 4), 4, 1, precision="bf16") > 0
+    with pytest.raises(_abi.TuckerRandError) as e:
+        _ws((20, 20, 20), (4, 4, 4), 4, 1, precision=7)
+    assert e.value.code == _abi.TR_EINVAL
 
 
 def test_null_pointers_rejected_before_launch():
