@@ -7,7 +7,7 @@
 // constant (the column loops are instantiated per step), so nothing is
 // indexed dynamically.  Workgroup sums go through one LDS tile of per-thread
 // partials read back by 256/SM lanes per value and finished with DPP.
-// Supports s <= 32, I <= 512 (mu <= MU).
+// Supports s <= SM (16, 32 or 48), I <= 256 R (mu <= MU).
 #pragma once
 
 #include <type_traits>
@@ -20,7 +20,8 @@ namespace trk {
 template <int SM>
 struct RfShape {
   static constexpr int NT = 256;
-  static constexpr int SEG = NT / SM;      // reducer lanes per value
+  // reducer lanes per value (a power of two, SEG * SM <= NT)
+  static constexpr int SEG = SM <= 16 ? 16 : (SM <= 32 ? 8 : 4);
   static constexpr int SEGLEN = NT / SEG;  // partial rows summed by one reducer lane
   static constexpr int PS = SM + 2;        // partial row stride (16-byte aligned rows)
   static constexpr int JW = kWave / SEG;   // values covered by one wave of reducers
@@ -285,7 +286,8 @@ k_factor_rf(FactorJobs jobs, int cast_f32, uint32_t* __restrict__ status) {
   //         without a rotation larger than tol_big (see below). ----
   {
     constexpr bool kOneWave = SM == 16;
-    constexpr int LP = kOneWave ? 8 : 16;  // lanes per pair
+    // lanes per pair; four waves give 64 / LP * 4 pair slots >= SM / 2
+    constexpr int LP = (kOneWave || SM > 32) ? 8 : 16;
     constexpr int RU = SM / LP;            // rows per lane
     const int se = s + (s & 1), np = se / 2, sm1 = se - 1;
     const int lq = lane % LP;

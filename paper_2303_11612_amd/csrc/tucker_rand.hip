@@ -738,25 +738,32 @@ inline bool force_lds_factor() {
   return v != nullptr && std::strcmp(v, "lds") == 0;
 }
 
-inline bool factor_rf_covers(int64_t I, int64_t s, int64_t mu) {
-  return I <= 512 && s <= 32 && (I <= 256 || s <= 16 || mu <= 16);
-}
-
-// Kernel instance a factorization runs in: the register-resident kernel
-// (s <= 32, I <= 512, mu <= 16 when I > 256 with s > 16), else the LDS-
-// resident one, else the one with its working matrices in global scratch.
 static_assert(trk::kMaxFactorJobs >= TR_MAX_ORDER, "one factorization job per mode");
 
+// Kernel instance a factorization runs in: the register-resident kernel
+// (<SM, R, MU>: s <= SM, I <= 256 R, mu <= MU), else the LDS-resident one,
+// else the one with its working matrices in global scratch.
 enum FactorVariant {
-  kRf16x1, kRf16x2, kRf32x1, kRf32x2, kLds16, kLds32, kLds64, kGlb16, kGlb32, kGlb64
+  kRf16x1, kRf16x2, kRf32x1, kRf32x2, kRf48x1, kRf48x2,
+  kLds16, kLds32, kLds64, kGlb16, kGlb32, kGlb64
 };
+
+// The smallest register-resident instance covering (I, s, mu), or -1.
+inline int factor_rf_variant(int64_t I, int64_t s, int64_t mu) {
+  if (I > 512 || s > 48) return -1;
+  const bool r1 = I <= 256;
+  if (s <= 16) return r1 ? kRf16x1 : kRf16x2;
+  if (s <= 32 && r1) return kRf32x1;
+  if (s <= 32 && mu <= 16) return kRf32x2;
+  if (r1) return kRf48x1;
+  return mu <= 32 ? kRf48x2 : -1;
+}
 
 int factor_variant(int64_t I, int64_t s, int64_t mu, bool has_scratch, int* var) {
   if (!factor_supported(I, s) || mu < 1 || mu > s) return TR_ENOTSUP;
-  if (factor_rf_covers(I, s, mu) && !force_lds_factor()) {
-    const bool r1 = I <= 256;
-    if (s <= 16) *var = r1 ? kRf16x1 : kRf16x2;
-    else *var = r1 ? kRf32x1 : kRf32x2;
+  const int rf = factor_rf_variant(I, s, mu);
+  if (rf >= 0 && !force_lds_factor()) {
+    *var = rf;
     return TR_OK;
   }
   const int sm = factor_sm(s);
@@ -805,6 +812,8 @@ int launch_factor_group(int var, const trk::FactorJobs& jobs, int n, int cast_f3
     case kRf16x2: return factor_rf_jobs<16, 2, 16>(jobs, n, cast_f32, status, st);
     case kRf32x1: return factor_rf_jobs<32, 1, 32>(jobs, n, cast_f32, status, st);
     case kRf32x2: return factor_rf_jobs<32, 2, 16>(jobs, n, cast_f32, status, st);
+    case kRf48x1: return factor_rf_jobs<48, 1, 48>(jobs, n, cast_f32, status, st);
+    case kRf48x2: return factor_rf_jobs<48, 2, 32>(jobs, n, cast_f32, status, st);
     case kLds16: return factor_k_jobs<16, false>(jobs, n, cast_f32, status, st);
     case kLds32: return factor_k_jobs<32, false>(jobs, n, cast_f32, status, st);
     case kLds64: return factor_k_jobs<64, false>(jobs, n, cast_f32, status, st);
