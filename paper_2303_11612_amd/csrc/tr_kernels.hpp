@@ -34,7 +34,7 @@ struct RowsPerChunk {
 // Philox block of four outputs; Box-Muller on words (0,1) and (2,3).  Writes
 // G (I x s column-major) and Gt (row-major copy, row i = G(i, :)).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kNT)
+static __global__ void __launch_bounds__(kNT)
 k_gaussian(double* __restrict__ G, double* __restrict__ Gt, int64_t I, int64_t s,
            int64_t ldgt, uint64_t mode, uint64_t seed) {
   const int64_t total = I * s;
@@ -168,14 +168,14 @@ k_colnorms_ln(const T* __restrict__ X, int64_t L, int64_t I, int64_t R,
 
 // Atomic maximum of the IEEE bit patterns of v[0..n) (used when the norms are
 // supplied by the caller rather than produced by the column-norm kernel).
-__global__ void __launch_bounds__(kNT)
+static __global__ void __launch_bounds__(kNT)
 k_max_bits(const double* __restrict__ v, int64_t n, unsigned long long* __restrict__ out) {
   __shared__ unsigned long long scr[kNT / kWave];
   const int64_t j = (int64_t)blockIdx.x * kNT + threadIdx.x;
   block_max_bits(j < n ? v[j] : 0.0, out, scr);
 }
 
-__global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v) {
+static __global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < n) p[e] = v;
 }
@@ -222,7 +222,7 @@ __device__ __forceinline__ unsigned long long block_exscan_u64(
   return before + inc - v;
 }
 
-__global__ void __launch_bounds__(kNT)
+static __global__ void __launch_bounds__(kNT)
 k_weights(const double* __restrict__ norms, int64_t J,
           const unsigned long long* __restrict__ max_bits, int kexp, int uniform,
           unsigned long long* __restrict__ w, unsigned long long* __restrict__ bsum,
@@ -264,7 +264,7 @@ k_weights(const double* __restrict__ norms, int64_t J,
 }
 
 // In-place exclusive scan of the block sums (one workgroup of 1024 threads).
-__global__ void __launch_bounds__(1024)
+static __global__ void __launch_bounds__(1024)
 k_scan_bsum(unsigned long long* __restrict__ bsum, int64_t nb) {
   __shared__ unsigned long long scr[1024 / kWave];
   const int t = threadIdx.x;
@@ -282,7 +282,7 @@ k_scan_bsum(unsigned long long* __restrict__ bsum, int64_t nb) {
 }
 
 // Inclusive prefix sums cdf_j = w_0 + ... + w_j.
-__global__ void __launch_bounds__(kNT)
+static __global__ void __launch_bounds__(kNT)
 k_cdf(const unsigned long long* __restrict__ w, const unsigned long long* __restrict__ boff,
       int64_t J, unsigned long long* __restrict__ cdf) {
   __shared__ unsigned long long scr[kNT / kWave];
@@ -307,7 +307,7 @@ k_cdf(const unsigned long long* __restrict__ w, const unsigned long long* __rest
 // One thread per draw t: x = floor((h 2^64 + l) W / 2^128) exactly, then the
 // first j with cdf_j > x, and the rescale sqrt((W / w_j) / T).  Also stores
 // scale^2 (the column weight of C' C'^T).
-__global__ void __launch_bounds__(kNT)
+static __global__ void __launch_bounds__(kNT)
 k_draw(const unsigned long long* __restrict__ cdf, int64_t J, int64_t T, uint64_t seed,
        uint64_t mode, int uniform, int64_t* __restrict__ idx, double* __restrict__ scale,
        double* __restrict__ scale2) {
@@ -479,7 +479,7 @@ k_ttm_split(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
 }
 
 // Y(l, k, r) = colscale_j * sum_y part[y][j*MU + k] for k < kout, row stride kout.
-__global__ void __launch_bounds__(kNT)
+static __global__ void __launch_bounds__(kNT)
 k_sum_splits(const double* __restrict__ part, int64_t nsplit, int64_t L, int64_t R, int MU,
              int kout, const double* __restrict__ colscale, double* __restrict__ Y) {
   const int64_t J = L * R;
@@ -503,7 +503,7 @@ k_sum_splits(const double* __restrict__ part, int64_t nsplit, int64_t L, int64_t
 
 // Y(e) = sum_b part_b(e) in increasing b; also the row-major copy Yt (stride
 // ldyt >= s; its padding columns are left untouched, i.e. zero).
-__global__ void __launch_bounds__(kNT)
+static __global__ void __launch_bounds__(kNT)
 k_reduce_parts(const double* __restrict__ part, int64_t nparts, int64_t I, int s, int ldyt,
                double* __restrict__ Y, double* __restrict__ Yt, uint32_t* __restrict__ status) {
   const int64_t n = I * s;
@@ -525,7 +525,7 @@ k_reduce_parts(const double* __restrict__ part, int64_t nparts, int64_t I, int s
   if (!isfinite(acc) && status) atomicOr(status, kDevNonFinite);
 }
 
-__global__ void k_fill_f64(double* __restrict__ p, int64_t n, double v) {
+static __global__ void k_fill_f64(double* __restrict__ p, int64_t n, double v) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < n) p[e] = v;
 }
@@ -966,7 +966,7 @@ k_factor(FactorJobs jobs, int cast_f32, uint32_t* __restrict__ status) {
 
 // Row-major copy Qt (row stride ldqt >= mu, padding zero) of a column-major
 // I x mu matrix Q.
-__global__ void k_transpose(const double* __restrict__ Q, int64_t I, int64_t mu, int64_t ldqt,
+static __global__ void k_transpose(const double* __restrict__ Q, int64_t I, int64_t mu, int64_t ldqt,
                             double* __restrict__ Qt) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= I * ldqt) return;

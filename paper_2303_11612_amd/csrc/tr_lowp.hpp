@@ -436,7 +436,7 @@ k_pw_lp(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R, int64_t ldi,
 // i < I, k < s; C column-major I x s.  Block: 32 entries x 8 groups of
 // blocks b (group q takes b = q, q + 8, ...); the 8 group sums are added in
 // order.
-__global__ void __launch_bounds__(kNT)
+static __global__ void __launch_bounds__(kNT)
 k_reduce_parts_lp(const float* __restrict__ part, int64_t nparts, int64_t I, int s, int SP,
                   int Ip, double* __restrict__ C, uint32_t* __restrict__ status) {
   __shared__ double red[8][33];

@@ -18,15 +18,16 @@
 #include "tr_factor_rf.hpp"
 #include "tr_power.hpp"
 #include "tr_lowp.hpp"
+#include "tr_host.hpp"
 #include "tucker_rand.h"
 
 namespace {
 
+using namespace trh;
 using trk::kNT;
 
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // ---------------------------------------------------------------------------
 // Kernel timer: a pool of event pairs recorded around selected launches.
@@ -119,21 +120,6 @@ inline bool factor_in_lds(int64_t I, int64_t s, int64_t mu) {
 }
 inline bool factor_supported(int64_t I, int64_t s) { return s >= 1 && s <= 64 && I <= (1 << 24); }
 
-// Low-precision power steps (k_pw_lp): rows padded to Ip = 128 MI (MI in
-// {1, 2, 4}, so I <= 512), sketch columns to 16 NKT (NKT <= 3, so s <= 48).
-inline int lp_mi(int64_t I) { return I <= 128 ? 1 : (I <= 256 ? 2 : 4); }
-inline int64_t lp_ip(int64_t I) { return 128 * lp_mi(I); }
-inline int lp_nkt(int64_t s) { return (int)cdiv(s, 16); }
-inline bool lp_supported(int64_t I, int64_t s) { return I <= 512 && s >= 1 && s <= 48; }
-inline size_t lp_lds_bytes(int mi, int nkt) {
-  return 4 * (size_t)(4 * 32 * mi * 36 + 2 * 4 * 16 * nkt * 36);
-}
-// Blocks of one power step over J columns: at most the resident blocks of
-// the chip, at least two column blocks of 32 each.
-inline int64_t lp_blocks(int64_t I, int64_t s, int64_t J) {
-  const int64_t per_cu = lp_lds_bytes(lp_mi(I), lp_nkt(s)) <= 80 * 1024 ? 2 : 1;
-  return std::max<int64_t>(1, std::min<int64_t>(256 * per_cu, cdiv(cdiv(J, 32), 2)));
-}
 inline size_t lp_esz(int prec) { return prec == TR_PREC_FP8E4M3 ? 1 : 2; }
 
 // ---------------------------------------------------------------------------
@@ -319,14 +305,6 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
   P->total = off;
   return TR_OK;
 }
-
-inline int check_launch() { return hipGetLastError() == hipSuccess ? TR_OK : TR_EDEVICE; }
-
-#define TR_TRY(expr)              \
-  do {                            \
-    const int _rc = (expr);       \
-    if (_rc != TR_OK) return _rc; \
-  } while (0)
 
 // ---------------------------------------------------------------------------
 // Launchers (all asynchronous on `st`).
@@ -585,64 +563,6 @@ int run_power(bool f64, const void* X, int64_t L, int64_t I, int64_t R, const do
 // ---------------------------------------------------------------------------
 // Low-precision power steps.
 // ---------------------------------------------------------------------------
-template <typename Tin, typename OP, int MI, int NKT>
-int pw_lp_k(const void* X, int64_t L, int64_t I, int64_t R, int64_t ldi, const void* Cq,
-            const float* tau, const float* omega, const unsigned* xmax, float* part,
-            int64_t nblk, hipStream_t st) {
-  const size_t lds = lp_lds_bytes(MI, NKT);
-  auto* fn = &trk::k_pw_lp<Tin, OP, MI, NKT>;
-  if (lds > 65536)
-    (void)hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
-  hipLaunchKernelGGL(fn, dim3((unsigned)nblk), dim3(trk::kPwWaves * trk::kWave), lds, st,
-                     (const Tin*)X, L, I, R, ldi, (const typename OP::stor*)Cq, tau, omega,
-                     xmax, part);
-  return check_launch();
-}
-
-template <typename Tin, typename OP, int MI>
-int pw_lp_n(int nkt, const void* X, int64_t L, int64_t I, int64_t R, int64_t ldi,
-            const void* Cq, const float* tau, const float* omega, const unsigned* xmax,
-            float* part, int64_t nblk, hipStream_t st) {
-  switch (nkt) {
-    case 1: return pw_lp_k<Tin, OP, MI, 1>(X, L, I, R, ldi, Cq, tau, omega, xmax, part, nblk, st);
-    case 2: return pw_lp_k<Tin, OP, MI, 2>(X, L, I, R, ldi, Cq, tau, omega, xmax, part, nblk, st);
-    case 3: return pw_lp_k<Tin, OP, MI, 3>(X, L, I, R, ldi, Cq, tau, omega, xmax, part, nblk, st);
-    default: return TR_ENOTSUP;
-  }
-}
-
-template <typename Tin, typename OP>
-int pw_lp_m(int64_t s, const void* X, int64_t L, int64_t I, int64_t R, int64_t ldi,
-            const void* Cq, const float* tau, const float* omega, const unsigned* xmax,
-            float* part, int64_t nblk, hipStream_t st) {
-  const int nkt = lp_nkt(s);
-  switch (lp_mi(I)) {
-    case 1: return pw_lp_n<Tin, OP, 1>(nkt, X, L, I, R, ldi, Cq, tau, omega, xmax, part, nblk, st);
-    case 2: return pw_lp_n<Tin, OP, 2>(nkt, X, L, I, R, ldi, Cq, tau, omega, xmax, part, nblk, st);
-    default: return pw_lp_n<Tin, OP, 4>(nkt, X, L, I, R, ldi, Cq, tau, omega, xmax, part, nblk, st);
-  }
-}
-
-// Source of a low-precision power step: a float32 / float64 tensor view, or
-// the gathered sample matrix already in operand form.
-enum LpSrc { kLpF32 = 0, kLpF64 = 1, kLpStored = 2 };
-
-template <typename OP>
-int pw_lp_src(int kind, int64_t s, const void* X, int64_t L, int64_t I, int64_t R, int64_t ldi,
-              const void* Cq, const float* tau, const float* omega, const unsigned* xmax,
-              float* part, int64_t nblk, hipStream_t st) {
-  switch (kind) {
-    case kLpF32:
-      return pw_lp_m<float, OP>(s, X, L, I, R, ldi, Cq, tau, omega, xmax, part, nblk, st);
-    case kLpF64:
-      return pw_lp_m<double, OP>(s, X, L, I, R, ldi, Cq, tau, omega, xmax, part, nblk, st);
-    default:
-      return pw_lp_m<typename OP::stor, OP>(s, X, L, I, R, ldi, Cq, tau, omega, xmax, part,
-                                             nblk, st);
-  }
-}
-
 int launch_quant_y(int prec, const double* C, int64_t I, int64_t s, void* Cq, float* tau,
                    hipStream_t st) {
   const int Ip = (int)lp_ip(I), SP = 16 * lp_nkt(s);
@@ -711,12 +631,7 @@ int run_power_lp(const Plan& P, int kind, const void* M, int64_t L, int64_t I, i
   const double* src = G;
   for (int step = 0; step < P.q; ++step) {
     TR_TRY(launch_quant_y(P.prec, src, I, s, Cq, tau, st));
-    if (P.prec == TR_PREC_FP8E4M3)
-      TR_TRY(pw_lp_src<trk::OpFp8>(kind, s, M, L, I, R, ldi, Cq, tau, omega, xmax, part, nblk,
-                                   st));
-    else
-      TR_TRY(pw_lp_src<trk::OpBf16>(kind, s, M, L, I, R, ldi, Cq, tau, omega, xmax, part, nblk,
-                                    st));
+    TR_TRY(launch_pw_lp(P.prec, kind, s, M, L, I, R, ldi, Cq, tau, omega, xmax, part, nblk, st));
     hipLaunchKernelGGL(trk::k_reduce_parts_lp, dim3((unsigned)cdiv(I * s, 32)), dim3(kNT), 0, st,
                        part, nblk, I, (int)s, (int)SP, (int)Ip, C, status);
     TR_TRY(check_launch());
@@ -739,14 +654,6 @@ inline bool force_lds_factor() {
 }
 
 static_assert(trk::kMaxFactorJobs >= TR_MAX_ORDER, "one factorization job per mode");
-
-// Kernel instance a factorization runs in: the register-resident kernel
-// (<SM, R, MU>: s <= SM, I <= 256 R, mu <= MU), else the LDS-resident one,
-// else the one with its working matrices in global scratch.
-enum FactorVariant {
-  kRf16x1, kRf16x2, kRf32x1, kRf32x2, kRf48x1, kRf48x2,
-  kLds16, kLds32, kLds64, kGlb16, kGlb32, kGlb64
-};
 
 // The smallest register-resident instance covering (I, s, mu), or -1.
 inline int factor_rf_variant(int64_t I, int64_t s, int64_t mu) {
@@ -775,52 +682,6 @@ int factor_variant(int64_t I, int64_t s, int64_t mu, bool has_scratch, int* var)
   if (!has_scratch) return TR_ENOMEM;
   *var = kGlb16 + k;
   return TR_OK;
-}
-
-template <int SM, int R, int MU>
-int factor_rf_jobs(const trk::FactorJobs& jobs, int n, int cast_f32, uint32_t* status,
-                   hipStream_t st) {
-  const size_t lds = trk::RfShape<SM>::lds_bytes();
-  if (lds > 65536 &&
-      hipFuncSetAttribute((const void*)&trk::k_factor_rf<SM, R, MU>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-    return TR_EDEVICE;
-  hipLaunchKernelGGL((trk::k_factor_rf<SM, R, MU>), dim3((unsigned)n), dim3(trk::RfShape<SM>::NT),
-                     lds, st, jobs, cast_f32, status);
-  return check_launch();
-}
-
-template <int SM, bool G>
-int factor_k_jobs(const trk::FactorJobs& jobs, int n, int cast_f32, uint32_t* status,
-                  hipStream_t st) {
-  size_t lds = 0;
-  for (int b = 0; b < n; ++b)
-    lds = std::max(lds, trk::FactorShape<SM>::lds_bytes(jobs.j[b].I, jobs.j[b].s, jobs.j[b].mu, G));
-  if (lds > 65536 &&
-      hipFuncSetAttribute((const void*)&trk::k_factor<SM, G>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-    return TR_EDEVICE;
-  hipLaunchKernelGGL((trk::k_factor<SM, G>), dim3((unsigned)n), dim3(trk::kFactorNT), lds, st,
-                     jobs, cast_f32, status);
-  return check_launch();
-}
-
-int launch_factor_group(int var, const trk::FactorJobs& jobs, int n, int cast_f32,
-                        uint32_t* status, hipStream_t st) {
-  switch (var) {
-    case kRf16x1: return factor_rf_jobs<16, 1, 16>(jobs, n, cast_f32, status, st);
-    case kRf16x2: return factor_rf_jobs<16, 2, 16>(jobs, n, cast_f32, status, st);
-    case kRf32x1: return factor_rf_jobs<32, 1, 32>(jobs, n, cast_f32, status, st);
-    case kRf32x2: return factor_rf_jobs<32, 2, 16>(jobs, n, cast_f32, status, st);
-    case kRf48x1: return factor_rf_jobs<48, 1, 48>(jobs, n, cast_f32, status, st);
-    case kRf48x2: return factor_rf_jobs<48, 2, 32>(jobs, n, cast_f32, status, st);
-    case kLds16: return factor_k_jobs<16, false>(jobs, n, cast_f32, status, st);
-    case kLds32: return factor_k_jobs<32, false>(jobs, n, cast_f32, status, st);
-    case kLds64: return factor_k_jobs<64, false>(jobs, n, cast_f32, status, st);
-    case kGlb16: return factor_k_jobs<16, true>(jobs, n, cast_f32, status, st);
-    case kGlb32: return factor_k_jobs<32, true>(jobs, n, cast_f32, status, st);
-    default: return factor_k_jobs<64, true>(jobs, n, cast_f32, status, st);
-  }
 }
 
 // Independent factorizations (n <= kMaxFactorJobs): one launch per kernel
