@@ -152,6 +152,9 @@ struct Plan {
   // T-HOSVD: every mode's sketch and singular values are kept until the
   // factorizations of all modes run in one launch
   size_t oYn[TR_MAX_ORDER] = {}, oSign[TR_MAX_ORDER] = {};
+  // T-HOSVD, low precision, q > 1: every mode's current orthonormal iterate,
+  // so that the modes advance one power step at a time together
+  size_t oGn[TR_MAX_ORDER] = {};
 };
 
 // Validates and fills the plan; returns TR_OK or an error code.
@@ -289,6 +292,7 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
     for (int n = 0; n < N; ++n) {
       P->oYn[n] = take(8 * (size_t)(P->m[n].I * P->m[n].s));
       P->oSign[n] = take(8 * (size_t)P->m[n].s);
+      if (lp && P->q > 1) P->oGn[n] = take(8 * (size_t)(P->m[n].I * P->m[n].sw));
     }
   P->oX0 = take(8 * maxInter);
   P->oX1 = take(8 * maxInter);
@@ -620,21 +624,28 @@ int launch_factor(const double* C, int64_t I, int64_t s, int64_t mu, double* Q, 
 // would erase every direction below the format's precision relative to the
 // leading one; C = M D M^T Y_{q-1} has the range of (M D M^T)^q G.
 // G is overwritten for q > 1.
-int run_power_lp(const Plan& P, int kind, const void* M, int64_t L, int64_t I, int64_t R,
-                 int64_t ldi, const float* omega, const unsigned* xmax, int64_t s,
-                 double* G, double* C, void* ws, uint32_t* status, hipStream_t st) {
+// One low-precision power step C = M D M^T Y (Y and C float64 I x s).
+int power_lp_step(const Plan& P, int kind, const void* M, int64_t L, int64_t I, int64_t R,
+                  int64_t ldi, const float* omega, const unsigned* xmax, int64_t s,
+                  const double* Y, double* C, void* ws, uint32_t* status, hipStream_t st) {
   void* Cq = static_cast<char*>(ws) + P.oYq;
   float* tau = reinterpret_cast<float*>(static_cast<char*>(ws) + P.oTau);
   float* part = reinterpret_cast<float*>(static_cast<char*>(ws) + P.oPartLp);
   const int64_t nblk = lp_blocks(I, s, L * R);
   const int64_t Ip = lp_ip(I), SP = 16 * lp_nkt(s);
+  TR_TRY(launch_quant_y(P.prec, Y, I, s, Cq, tau, st));
+  TR_TRY(launch_pw_lp(P.prec, kind, s, M, L, I, R, ldi, Cq, tau, omega, xmax, part, nblk, st));
+  hipLaunchKernelGGL(trk::k_reduce_parts_lp, dim3((unsigned)cdiv(I * s, 32)), dim3(kNT), 0, st,
+                     part, nblk, I, (int)s, (int)SP, (int)Ip, C, status);
+  return check_launch();
+}
+
+int run_power_lp(const Plan& P, int kind, const void* M, int64_t L, int64_t I, int64_t R,
+                 int64_t ldi, const float* omega, const unsigned* xmax, int64_t s,
+                 double* G, double* C, void* ws, uint32_t* status, hipStream_t st) {
   const double* src = G;
   for (int step = 0; step < P.q; ++step) {
-    TR_TRY(launch_quant_y(P.prec, src, I, s, Cq, tau, st));
-    TR_TRY(launch_pw_lp(P.prec, kind, s, M, L, I, R, ldi, Cq, tau, omega, xmax, part, nblk, st));
-    hipLaunchKernelGGL(trk::k_reduce_parts_lp, dim3((unsigned)cdiv(I * s, 32)), dim3(kNT), 0, st,
-                       part, nblk, I, (int)s, (int)SP, (int)Ip, C, status);
-    TR_TRY(check_launch());
+    TR_TRY(power_lp_step(P, kind, M, L, I, R, ldi, omega, xmax, s, src, C, ws, status, st));
     if (step + 1 < P.q) {
       // C is dead after this call (it doubles as the factor's scratch)
       TR_TRY(launch_factor(C, I, s, s, G, reinterpret_cast<double*>(static_cast<char*>(ws) + P.oYt),
@@ -874,11 +885,70 @@ int run_thosvd(const tr_params* p, int dtype, const void* A, void* const* Q, voi
   // tensor, so its max |entry| -- the FP8 scale -- is taken once), then all
   // factorizations in one launch per kernel instance
   trk::FactorJob jobs[TR_MAX_ORDER];
+  tr_timer* tm0 = diag ? diag->timer : nullptr;
+  uint32_t* status = diag ? diag->status : nullptr;
+  // low precision with q > 1: the unsampled modes advance one power step at
+  // a time together, so that each round of orthonormalisation between steps
+  // is one launch for all of them
+  bool together[TR_MAX_ORDER] = {};
+  int ntog = 0;
   for (int n = 0; n < P.N; ++n) {
-    double* Yn = at<double>(ws, P.oYn[n]);
-    TR_TRY(range_sketch(P, n, A, ws, diag, n == 0, Yn, st));
-    jobs[n] = factor_job(P, n, Yn, mode_sigma(P, n, diag, ws, P.oSign[n]), ws, Q[n]);
+    together[n] = P.prec != TR_PREC_NATIVE && P.q > 1 && !P.m[n].sampled;
+    ntog += together[n] ? 1 : 0;
   }
+  bool xmax_ready = false;
+  for (int n = 0; n < P.N; ++n) {
+    if (together[n]) continue;
+    TR_TRY(range_sketch(P, n, A, ws, diag, !xmax_ready, at<double>(ws, P.oYn[n]), st));
+    // an unsampled mode in FP8 has taken the tensor's max |entry| (every mode
+    // reads the same tensor)
+    if (!P.m[n].sampled) xmax_ready = true;
+  }
+  if (ntog > 0) {
+    unsigned* xmax = nullptr;
+    if (P.prec == TR_PREC_FP8E4M3) {
+      xmax = at<unsigned>(ws, P.oXmax);
+      const ModePlan& M0 = P.m[0];
+      if (!xmax_ready) TR_TRY(launch_maxabs(M0.src_f64, A, M0.L * M0.I * M0.R, xmax, st));
+    }
+    for (int n = 0; n < P.N; ++n)
+      if (together[n]) {
+        const ModePlan& M = P.m[n];
+        TimeScope ts(tm0, TR_KC_GAUSSIAN, n, st);
+        TR_TRY(launch_gaussian(at<double>(ws, P.oGn[n]), at<double>(ws, P.oYt), M.I, M.s, M.sw, n,
+                               P.seed, st));
+      }
+    for (int step = 0; step < P.q; ++step) {
+      trk::FactorJob orth[TR_MAX_ORDER];
+      int k = 0;
+      for (int n = 0; n < P.N; ++n) {
+        if (!together[n]) continue;
+        const ModePlan& M = P.m[n];
+        double* Gn = at<double>(ws, P.oGn[n]);
+        double* Yn = at<double>(ws, P.oYn[n]);
+        {
+          TimeScope ts(tm0, TR_KC_POWER, n, st);
+          TR_TRY(power_lp_step(P, M.src_f64 ? kLpF64 : kLpF32, A, M.L, M.I, M.R, M.I, nullptr,
+                               xmax, M.s, Gn, Yn, ws, status, st));
+        }
+        // next iterate: an orthonormal basis of range(Y_n) (its s left
+        // singular vectors, float64); Y_n is the factor's scratch
+        orth[k++] = trk::FactorJob{Yn, Gn, nullptr, at<double>(ws, P.oSign[n]), nullptr, Yn,
+                                   (int)M.I, (int)M.s, (int)M.s, 0};
+      }
+      if (step + 1 < P.q) {
+        TimeScope ts(tm0, TR_KC_POWER, 0, st);
+        TR_TRY(launch_factor_jobs(orth, k, 0, status, st));
+      }
+    }
+    for (int n = 0; n < P.N; ++n)
+      if (together[n] && diag && diag->sketch && diag->sketch[n])
+        TR_TRY(copy_d2d(diag->sketch[n], at<double>(ws, P.oYn[n]),
+                        8 * (size_t)(P.m[n].I * P.m[n].s), st));
+  }
+  for (int n = 0; n < P.N; ++n)
+    jobs[n] = factor_job(P, n, at<double>(ws, P.oYn[n]), mode_sigma(P, n, diag, ws, P.oSign[n]),
+                         ws, Q[n]);
   {
     TimeScope ts(diag ? diag->timer : nullptr, TR_KC_FACTOR, 0, st);
     TR_TRY(launch_factor_jobs(jobs, P.N, P.dtype == TR_F32, diag ? diag->status : nullptr, st));

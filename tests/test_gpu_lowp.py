@@ -106,6 +106,30 @@ def test_thosvd_sketches_match_emulation(prec, case):
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp8e4m3"])
+@pytest.mark.parametrize("q", [1, 2])
+def test_thosvd_mixed_sampled_and_exact_modes(prec, q):
+    # mode 1 is sampled (T = 40 <= J = 48); modes 2 and 3 have T > J and are
+    # computed exactly, from the tensor's FP8 scale taken after mode 1
+    A = synth.low_rank_plus_noise((30, 8, 6), (3, 3, 3), 1e-3, 8, np.float32)
+    ranks, K, samples, seed = (3, 3, 3), 4, (40, 400, 400), 5
+    Qg, cg, info = _gpu(A, "thosvd", ranks, K, q, "nearly_optimal", samples, seed, prec)
+    A64 = A.astype(np.float64)
+    for n in range(3):
+        An = oracle.unfold(A64, n)
+        s = min(ranks[n] + K, A.shape[n])
+        xi = scale = None
+        if samples[n] <= An.shape[1]:
+            xi, scale, _, _ = oracle.randsample(oracle.column_sq_norms(An), An.shape[1],
+                                                samples[n], "nearly_optimal", seed, n)
+        Ce = lowp.power_sketch_lp(A, n, s, q, prec, seed, xi, scale)
+        Cg = _np(info["sketch"][n])
+        if q == 1:
+            _check_sketch(Cg, Ce, prec, n)
+        else:
+            _check_leading(Cg, Ce, ranks[n], prec, n)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8e4m3"])
 def test_sthosvd_first_mode_matches_emulation(prec):
     A = synth.low_rank_plus_noise((200, 30, 24), (8, 5, 4), 1e-3, 9, np.float64)
     Qg, cg, info = _gpu(A, "sthosvd", (8, 5, 4), 10, 1, "none", None, 4, prec)
