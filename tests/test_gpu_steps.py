@@ -50,7 +50,8 @@ def test_gaussian_matches_oracle(I, s, mode, seed):
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
-@pytest.mark.parametrize("shape", [(300, 70, 3), (37, 23, 11), (5, 600, 2), (1000, 1, 1)])
+@pytest.mark.parametrize("shape", [(300, 70, 3), (37, 23, 11), (5, 600, 2), (1000, 1, 1),
+                                   (4, 50, 3), (8, 33, 5), (400, 20, 20)])
 def test_colnorms_bit_exact(dtype, shape):
     A = _rand_tensor(shape, dtype, 3)
     X = tr.to_device(A)
