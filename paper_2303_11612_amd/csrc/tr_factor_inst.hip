@@ -5,6 +5,7 @@
 
 #include "tr_factor_rf.hpp"
 #include "tr_host.hpp"
+#include "tr_factor.hpp"
 #include "tr_kernels.hpp"
 
 #ifndef TR_FACTOR_INST

@@ -13,7 +13,7 @@
 #include <type_traits>
 
 #include "tr_device.hpp"
-#include "tr_kernels.hpp"
+#include "tr_factor.hpp"
 
 namespace trk {
 

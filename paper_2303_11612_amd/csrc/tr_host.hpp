@@ -9,7 +9,7 @@
 #include <algorithm>
 #include <cstdint>
 
-#include "tr_kernels.hpp"
+#include "tr_factor.hpp"
 #include "tucker_rand.h"
 
 namespace trh {

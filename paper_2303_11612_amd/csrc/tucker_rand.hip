@@ -14,6 +14,7 @@
 #include <new>
 #include <vector>
 
+#include "tr_factor.hpp"
 #include "tr_kernels.hpp"
 #include "tr_factor_rf.hpp"
 #include "tr_power.hpp"
