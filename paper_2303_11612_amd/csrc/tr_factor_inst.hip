@@ -129,5 +129,19 @@ int launch_factor_kGlb64(const trk::FactorJobs& jobs, int n, int cast_f32, uint3
   return factor_k_jobs<64, true>(jobs, n, cast_f32, status, st);
 }
 #endif
+#if TR_FACTOR_INST == 12
+static_assert(kRf24x1 == 12, "instance numbering");
+int launch_factor_kRf24x1(const trk::FactorJobs& jobs, int n, int cast_f32, uint32_t* status,
+                      hipStream_t st) {
+  return factor_rf_jobs<24, 1, 24>(jobs, n, cast_f32, status, st);
+}
+#endif
+#if TR_FACTOR_INST == 13
+static_assert(kRf24x2 == 13, "instance numbering");
+int launch_factor_kRf24x2(const trk::FactorJobs& jobs, int n, int cast_f32, uint32_t* status,
+                      hipStream_t st) {
+  return factor_rf_jobs<24, 2, 16>(jobs, n, cast_f32, status, st);
+}
+#endif
 
 }  // namespace trh

@@ -7,7 +7,9 @@
 // constant (the column loops are instantiated per step), so nothing is
 // indexed dynamically.  Workgroup sums go through one LDS tile of per-thread
 // partials read back by 256/SM lanes per value and finished with DPP.
-// Supports s <= SM (16, 32 or 48), I <= 256 R (mu <= MU).
+// Supports s <= SM (16, 24, 32 or 48), I <= 256 R (mu <= MU).  The code is
+// straight-line per step, so a smaller SM also means fewer instructions to
+// fetch: a call after a large sweep fetches them from beyond the L2.
 #pragma once
 
 #include <type_traits>
@@ -101,16 +103,23 @@ __device__ __forceinline__ void rf_reduce(const double (&p)[N], int jend, double
   const bool mine = rj >= J0 && rj < jend;
   double acc = Op::kId;
   if (mine) {
+    // every load of a batch is issued before the first add (one LDS round
+    // trip per batch), then the batch is summed as a binary tree
     const double* src = P + rg * S::SEGLEN * S::PS + S::poff(rg) + rj;
-    double a0 = src[0], a1 = src[S::PS], a2 = src[2 * S::PS], a3 = src[3 * S::PS];
+    constexpr int BT = S::SEGLEN < 32 ? S::SEGLEN : 32;
 #pragma unroll
-    for (int t = 4; t < S::SEGLEN; t += 4) {
-      a0 = Op::f(a0, src[t * S::PS]);
-      a1 = Op::f(a1, src[(t + 1) * S::PS]);
-      a2 = Op::f(a2, src[(t + 2) * S::PS]);
-      a3 = Op::f(a3, src[(t + 3) * S::PS]);
+    for (int b0 = 0; b0 < S::SEGLEN; b0 += BT) {
+      double t[BT];
+#pragma unroll
+      for (int i = 0; i < BT; ++i) t[i] = src[(b0 + i) * S::PS];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int w = BT / 2; w >= 1; w /= 2) {
+#pragma unroll
+        for (int i = 0; i < w; ++i) t[i] = Op::f(t[i], t[i + w]);
+      }
+      acc = b0 == 0 ? t[0] : Op::f(acc, t[0]);
     }
-    acc = Op::f(Op::f(a0, a1), Op::f(a2, a3));
   }
   acc = seg_reduce<S::SEG, Op>(acc);
   if (mine && rg == 0) vec[rj] = acc;
@@ -279,7 +288,9 @@ k_factor_rf(FactorJobs jobs, int cast_f32, uint32_t* __restrict__ status) {
   // ---- 3. one-sided Jacobi on the columns of X.  SM == 16: wave 0 alone
   //         (no barrier between steps: one wave's LDS accesses complete in
   //         order), pair g on lanes 8g .. 8g + 7.  SM == 32: all four waves,
-  //         pair g on DPP row g / 4 of wave g % 4.  Each lane holds RU
+  //         pair g on DPP row g / 4 of wave g % 4.  SM == 24 and 48: all four
+  //         waves, 8 lanes per pair, pair g on lanes 8 (g / 4) .. + 7 of wave
+  //         g % 4.  Each lane holds RU
   //         consecutive rows of the pair's two columns.  Column norms are
   //         recomputed at the start of each sweep and then updated with each
   //         rotation (a' = a - t c, b' = b + t c).  The sweeps end after one
@@ -287,8 +298,10 @@ k_factor_rf(FactorJobs jobs, int cast_f32, uint32_t* __restrict__ status) {
   {
     constexpr bool kOneWave = SM == 16;
     // lanes per pair; four waves give 64 / LP * 4 pair slots >= SM / 2
-    constexpr int LP = (kOneWave || SM > 32) ? 8 : 16;
+    constexpr int LP = SM == 32 ? 16 : 8;
     constexpr int RU = SM / LP;            // rows per lane
+    static_assert(RU * LP == SM && (kOneWave ? kWave / LP : NW * (kWave / LP)) >= SM / 2,
+                  "Jacobi pair layout");
     const int se = s + (s & 1), np = se / 2, sm1 = se - 1;
     const int lq = lane % LP;
     const int slot = kOneWave ? lane / LP : (lane / LP) * NW + wid;

@@ -672,6 +672,8 @@ inline int factor_rf_variant(int64_t I, int64_t s, int64_t mu) {
   if (I > 512 || s > 48) return -1;
   const bool r1 = I <= 256;
   if (s <= 16) return r1 ? kRf16x1 : kRf16x2;
+  if (s <= 24 && r1) return kRf24x1;
+  if (s <= 24 && mu <= 16) return kRf24x2;
   if (s <= 32 && r1) return kRf32x1;
   if (s <= 32 && mu <= 16) return kRf32x2;
   if (r1) return kRf48x1;

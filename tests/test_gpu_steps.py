@@ -157,7 +157,7 @@ def _graded(I, s, seed, decay=0.6):
 
 @pytest.fixture(params=["reg", "lds"])
 def factor_variant(request, monkeypatch):
-    """Both factor kernels: the register-resident one (default for s <= 32,
+    """Both factor kernels: the register-resident one (default for s <= 48,
     I <= 512) and the LDS-resident one (every shape when forced)."""
     monkeypatch.setenv("TUCKER_RAND_FACTOR", request.param)
     return request.param
@@ -167,7 +167,8 @@ def factor_variant(request, monkeypatch):
                                     (513, 16, 9), (1000, 24, 12), (2000, 12, 4), (7, 7, 7),
                                     (1, 1, 1), (33, 1, 1), (96, 64, 40), (256, 16, 16),
                                     (300, 16, 8), (256, 32, 32), (512, 32, 16), (400, 30, 20),
-                                    (257, 17, 16), (2, 2, 1), (40, 31, 3)])
+                                    (257, 17, 16), (2, 2, 1), (40, 31, 3), (256, 24, 24),
+                                    (130, 21, 17), (400, 24, 16), (512, 17, 3)])
 def test_factor_matches_svd(I, s, mu, factor_variant):
     C = _graded(I, s, I + s)
     Q, sig = tr.tucker_rand_factor(tr.to_device(C), mu)
