@@ -32,13 +32,16 @@ struct RowsPerChunk {
 // ---------------------------------------------------------------------------
 // K1  Gaussian test matrix (Alg. 1 step 2 / Alg. 4 step 5).  One thread per
 // Philox block of four outputs; Box-Muller on words (0,1) and (2,3).  Writes
-// G (I x s column-major) and Gt (row-major copy, row i = G(i, :)).
+// G (I x s column-major) and Gt (row-major copy, row i = G(i, :)).  `zero`,
+// if given, is one word cleared on the way (the running maximum of the column
+// norms that the next kernel on the stream accumulates), which saves a launch.
 // ---------------------------------------------------------------------------
 static __global__ void __launch_bounds__(kNT)
 k_gaussian(double* __restrict__ G, double* __restrict__ Gt, int64_t I, int64_t s,
-           int64_t ldgt, uint64_t mode, uint64_t seed) {
+           int64_t ldgt, uint64_t mode, uint64_t seed, unsigned long long* __restrict__ zero) {
   const int64_t total = I * s;
   const int64_t b = (int64_t)blockIdx.x * kNT + threadIdx.x;
+  if (zero && b == 0) *zero = 0ull;
   if (4 * b >= total) return;
   const U64x4 r = philox4x64_10((uint64_t)b, mode, kTagGauss, 0, seed, 0);
 #pragma unroll
@@ -281,10 +284,13 @@ k_scan_bsum(unsigned long long* __restrict__ bsum, int64_t nb) {
   }
 }
 
-// Inclusive prefix sums cdf_j = w_0 + ... + w_j.
+// Inclusive prefix sums cdf_j = w_0 + ... + w_j.  boff holds each block's
+// offset (the scanned block sums), or with `raw` the block sums themselves:
+// block b then adds up those of blocks 0 .. b-1 itself (exact integer sums;
+// used for a few blocks, where it saves the scan launch).
 static __global__ void __launch_bounds__(kNT)
 k_cdf(const unsigned long long* __restrict__ w, const unsigned long long* __restrict__ boff,
-      int64_t J, unsigned long long* __restrict__ cdf) {
+      int raw, int64_t J, unsigned long long* __restrict__ cdf) {
   __shared__ unsigned long long scr[kNT / kWave];
   constexpr int E = kScanChunk / kNT;
   const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * E;
@@ -295,8 +301,16 @@ k_cdf(const unsigned long long* __restrict__ w, const unsigned long long* __rest
     v[m] = (base + m < J) ? w[base + m] : 0ull;
     local += v[m];
   }
+  unsigned long long off;
+  if (raw) {
+    unsigned long long part = 0;
+    for (int64_t k = threadIdx.x; k < (int64_t)blockIdx.x; k += kNT) part += boff[k];
+    off = block_sum_u64(part, scr);
+  } else {
+    off = boff[blockIdx.x];
+  }
   unsigned long long total;
-  unsigned long long run = boff[blockIdx.x] + block_exscan_u64(local, scr, &total);
+  unsigned long long run = off + block_exscan_u64(local, scr, &total);
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     run += v[m];

@@ -320,13 +320,14 @@ int launch_fill_f64(double* p, int64_t n, double v, hipStream_t st) {
   return check_launch();
 }
 
-// G (I x s) and its row-major copy Gt with zero padding to stride ldgt.
+// G (I x s) and its row-major copy Gt with zero padding to stride ldgt;
+// `zero` (optional) is a word set to 0 by the same launch.
 int launch_gaussian(double* G, double* Gt, int64_t I, int64_t s, int64_t ldgt, int mode,
-                    uint64_t seed, hipStream_t st) {
+                    uint64_t seed, hipStream_t st, unsigned long long* zero = nullptr) {
   if (Gt && ldgt > s) TR_TRY(launch_fill_f64(Gt, I * ldgt, 0.0, st));
   const int64_t blocks4 = cdiv(I * s, 4);
   hipLaunchKernelGGL(trk::k_gaussian, dim3((unsigned)cdiv(blocks4, kNT)), dim3(kNT), 0, st,
-                     G, Gt, I, s, ldgt, (uint64_t)mode, seed);
+                     G, Gt, I, s, ldgt, (uint64_t)mode, seed, zero);
   return check_launch();
 }
 
@@ -373,9 +374,14 @@ int launch_sample(const double* norms, const unsigned long long* maxb, int64_t J
     hipLaunchKernelGGL(trk::k_weights, dim3((unsigned)nb), dim3(kNT), 0, st, norms, J, maxb,
                        kexp, 0, w, bsum, status);
     TR_TRY(check_launch());
-    hipLaunchKernelGGL(trk::k_scan_bsum, dim3(1), dim3(1024), 0, st, bsum, nb);
-    TR_TRY(check_launch());
-    hipLaunchKernelGGL(trk::k_cdf, dim3((unsigned)nb), dim3(kNT), 0, st, w, bsum, J, cdf);
+    // up to 1024 blocks, each block of k_cdf sums the block totals before it
+    // (at most 2^20 loads in all); beyond that one workgroup scans them first
+    const int raw = nb <= 1024 ? 1 : 0;
+    if (!raw) {
+      hipLaunchKernelGGL(trk::k_scan_bsum, dim3(1), dim3(1024), 0, st, bsum, nb);
+      TR_TRY(check_launch());
+    }
+    hipLaunchKernelGGL(trk::k_cdf, dim3((unsigned)nb), dim3(kNT), 0, st, w, bsum, raw, J, cdf);
     TR_TRY(check_launch());
   }
   hipLaunchKernelGGL(trk::k_draw, dim3((unsigned)cdiv(T, kNT)), dim3(kNT), 0, st, cdf, J, T,
@@ -760,9 +766,13 @@ int range_sketch(const Plan& P, int n, const void* X, void* ws, const tr_diag* d
   double* Yt = at<double>(ws, P.oYt);
   double* Z = at<double>(ws, P.oZ);
   double* part = at<double>(ws, P.oPart);
+  // the running maximum of the column norms starts at 0; the Gaussian
+  // launch, just before them on the stream, clears it
+  const bool norms_needed = M.sampled && P.prob == TR_PROB_NEARLY_OPTIMAL;
   {
     TimeScope ts(tm, TR_KC_GAUSSIAN, n, st);
-    TR_TRY(launch_gaussian(G, Yt, M.I, M.s, M.sw, n, P.seed, st));
+    TR_TRY(launch_gaussian(G, Yt, M.I, M.s, M.sw, n, P.seed, st,
+                           norms_needed ? at<unsigned long long>(ws, P.oMax) : nullptr));
   }
   const void* src = X;
   bool src_f64 = M.src_f64;
@@ -775,8 +785,7 @@ int range_sketch(const Plan& P, int n, const void* X, void* ws, const tr_diag* d
     int64_t* idx = at<int64_t>(ws, P.oIdx);
     double* scale = at<double>(ws, P.oScale);
     double* scale2 = at<double>(ws, P.oScale2);
-    if (P.prob == TR_PROB_NEARLY_OPTIMAL) {
-      TR_TRY(launch_fill(maxb, 1, 0ull, st));
+    if (norms_needed) {
       TimeScope ts(tm, TR_KC_COLNORMS, n, st);
       TR_TRY(launch_colnorms(M.src_f64, X, M.L, M.I, M.R, norms, maxb, st));
     }

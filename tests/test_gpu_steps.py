@@ -73,6 +73,10 @@ def _norm_vectors():
     yield "zeros", 5000, n
     yield "tiny", 3, np.array([1.0, 2.0, 0.5])
     yield "one", 1, np.array([4.0])
+    # more than 1024 scan blocks of 1024 columns: the block offsets are
+    # scanned by their own launch instead of inside the prefix-sum kernel
+    J = 1200000
+    yield "many_blocks", J, rng.random(J) ** 4
 
 
 @pytest.mark.parametrize("case", list(_norm_vectors()), ids=lambda c: c[0])
