@@ -94,15 +94,15 @@ __device__ __forceinline__ void block_max_bits(double v, unsigned long long* out
   }
 }
 
-// Stages rows [i0, i0 + TI) of the kNT consecutive columns starting at `base`
-// (an L == 1 view: column c is contiguous, length I) into tile[ii][c].  All
-// TI loads of a thread are issued before any is consumed (out-of-range
-// elements read a clamped in-range address and are not stored).
+// Loads rows [i0, i0 + TI) of the kNT consecutive columns starting at `base`
+// (an L == 1 view: column c is contiguous, length I) into registers, and
+// stores them to tile[ii][c].  All TI loads of a thread are issued before any
+// is consumed (out-of-range elements read a clamped in-range address and are
+// not stored).
 template <typename T, int TI>
-__device__ __forceinline__ void stage_fiber_chunk(const T* __restrict__ base, int64_t I,
-                                                  int64_t i0, int ncol, T (*tile)[kNT + 1]) {
-  T v[TI];
-  bool ok[TI];
+__device__ __forceinline__ void load_fiber_chunk(const T* __restrict__ base, int64_t I,
+                                                 int64_t i0, int ncol, T (&v)[TI],
+                                                 bool (&ok)[TI]) {
 #pragma unroll
   for (int m = 0; m < TI; ++m) {
     const int e = threadIdx.x + kNT * m;
@@ -110,11 +110,23 @@ __device__ __forceinline__ void stage_fiber_chunk(const T* __restrict__ base, in
     ok[m] = cc < ncol && i0 + ii < I;
     v[m] = base[ok[m] ? (int64_t)cc * I + i0 + ii : 0];
   }
+}
+template <typename T, int TI>
+__device__ __forceinline__ void store_fiber_chunk(const T (&v)[TI], const bool (&ok)[TI],
+                                                  T (*tile)[kNT + 1]) {
 #pragma unroll
   for (int m = 0; m < TI; ++m) {
     const int e = threadIdx.x + kNT * m;
     if (ok[m]) tile[e % TI][e / TI] = v[m];
   }
+}
+template <typename T, int TI>
+__device__ __forceinline__ void stage_fiber_chunk(const T* __restrict__ base, int64_t I,
+                                                  int64_t i0, int ncol, T (*tile)[kNT + 1]) {
+  T v[TI];
+  bool ok[TI];
+  load_fiber_chunk<T, TI>(base, I, i0, ncol, v, ok);
+  store_fiber_chunk<T, TI>(v, ok, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -132,9 +144,14 @@ k_colnorms_l1(const T* __restrict__ X, int64_t I, int64_t J,
   const int ncol = (int)min((int64_t)kNT, J - j0);
   const T* base = X + j0 * I;
   double acc = 0.0;
+  // the next chunk's loads are in flight while this one is summed from LDS
+  T v[TI];
+  bool ok[TI];
+  load_fiber_chunk<T, TI>(base, I, 0, ncol, v, ok);
   for (int64_t i0 = 0; i0 < I; i0 += TI) {
-    stage_fiber_chunk<T, TI>(base, I, i0, ncol, tile);
+    store_fiber_chunk<T, TI>(v, ok, tile);
     __syncthreads();
+    if (i0 + TI < I) load_fiber_chunk<T, TI>(base, I, i0 + TI, ncol, v, ok);
     const int ti = (int)min((int64_t)TI, I - i0);
     if (c < ncol)
       for (int ii = 0; ii < ti; ++ii) acc = sq_add(acc, (double)tile[ii][c]);

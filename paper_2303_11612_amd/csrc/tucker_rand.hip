@@ -427,7 +427,10 @@ void ttm1_mfma_k(const Tin* X, int64_t I, int64_t R, const double* Qt, int width
     (void)hipFuncSetAttribute((const void*)&trk::k_ttm1_mfma<Tin, NKT, B>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   const int64_t ntile = cdiv(R, 16);
-  const int64_t nblk = std::max<int64_t>(1, std::min<int64_t>(512, cdiv(ntile, trk::kPwWaves)));
+  // persistent blocks: as many as fit three to a compute unit (by the Q^T
+  // tile in LDS), capped by the tiles there are
+  const int64_t per_cu = lds <= 53248 ? 3 : (lds <= 81920 ? 2 : 1);
+  const int64_t nblk = std::max<int64_t>(1, std::min<int64_t>(256 * per_cu, cdiv(ntile, trk::kPwWaves)));
   hipLaunchKernelGGL((trk::k_ttm1_mfma<Tin, NKT, B>), dim3((unsigned)nblk),
                      dim3(trk::kPwWaves * trk::kWave), lds, st, X, I, R, Qt, width, kout, Y);
 }
