@@ -186,6 +186,49 @@ k_colnorms_ln(const T* __restrict__ X, int64_t L, int64_t I, int64_t R,
   if (max_bits) block_max_bits(acc, max_bits, scr);
 }
 
+// Column norms of a tensor the library produced itself (ST-HOSVD's shrunk
+// tensors, whose last bits differ from any other computation's anyway), for
+// views with too few columns to fill the device one thread per column: S
+// threads per column each sum a contiguous segment of ceil(I/S) rows in row
+// order, and the segment sums are added in segment order (deterministic).
+template <typename T, int S>
+__global__ void __launch_bounds__(kNT)
+k_colnorms_seg(const T* __restrict__ X, int64_t L, int64_t I, int64_t R,
+               double* __restrict__ norms, unsigned long long* __restrict__ max_bits) {
+  constexpr int CPB = kNT / S;  // columns per workgroup
+  __shared__ double part[S][CPB + 1];
+  __shared__ unsigned long long scr[kNT / kWave];
+  const int cl = threadIdx.x % CPB, sg = threadIdx.x / CPB;
+  const int64_t J = L * R;
+  const int64_t j = (int64_t)blockIdx.x * CPB + cl;
+  const int64_t seg = (I + S - 1) / S;
+  const int64_t i0 = sg * seg, i1 = min(I, i0 + seg);
+  double acc = 0.0;
+  if (j < J) {
+    const int64_t r = j / L, l = j - r * L;
+    const T* p = X + l + L * I * r;
+    constexpr int B = 16;
+    for (int64_t a = i0; a < i1; a += B) {
+      T v[B];
+#pragma unroll
+      for (int b = 0; b < B; ++b) v[b] = p[L * min(a + b, i1 - 1)];
+#pragma unroll
+      for (int b = 0; b < B; ++b)
+        if (a + b < i1) acc = sq_add(acc, (double)v[b]);
+    }
+  }
+  part[sg][cl] = acc;
+  __syncthreads();
+  double tot = 0.0;
+  if (sg == 0 && j < J) {
+    tot = part[0][cl];
+#pragma unroll
+    for (int g = 1; g < S; ++g) tot += part[g][cl];
+    norms[j] = tot;
+  }
+  if (max_bits) block_max_bits(tot, max_bits, scr);
+}
+
 // Atomic maximum of the IEEE bit patterns of v[0..n) (used when the norms are
 // supplied by the caller rather than produced by the column-norm kernel).
 static __global__ void __launch_bounds__(kNT)

@@ -132,6 +132,7 @@ struct ModePlan {
   int sw, muw;          // padded widths of the sketch rows and of Q^T rows
   bool sampled;
   bool src_f64;         // the tensor of this mode is float64
+  bool intermediate;    // ... and the library's own shrunk tensor (ST-HOSVD, n > 0)
 };
 
 struct Plan {
@@ -205,6 +206,7 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
     if (M.mu < 1 || M.mu > M.I || M.mu > M.J) return TR_EINVAL;
     M.s = std::min<int64_t>(M.mu + p->oversample, M.I);
     M.src_f64 = (dtype == TR_F64) || (sthosvd && n > 0);
+    M.intermediate = sthosvd && n > 0;
     M.T = 0;
     M.sampled = false;
     if (p->prob != TR_PROB_NONE) {
@@ -331,12 +333,19 @@ int launch_gaussian(double* G, double* Gt, int64_t I, int64_t s, int64_t ldgt, i
   return check_launch();
 }
 
+// Norms of the caller's tensor sum each column's rows in order (one thread
+// per column), which makes them bit-exact; `seg_ok` (the library's own shrunk
+// tensor) lets a view with few columns split each column over 8 threads.
 template <typename T>
 int launch_colnorms_t(const T* X, int64_t L, int64_t I, int64_t R, double* norms,
-                      unsigned long long* maxb, hipStream_t st) {
+                      unsigned long long* maxb, hipStream_t st, bool seg_ok) {
   const int64_t J = L * R;
   const dim3 grid((unsigned)cdiv(J, kNT));
-  if (L == 1)
+  constexpr int kSeg = 8;
+  if (seg_ok && J < 64 * (int64_t)kNT && I >= 4 * kSeg)
+    hipLaunchKernelGGL((trk::k_colnorms_seg<T, kSeg>), dim3((unsigned)cdiv(J, kNT / kSeg)),
+                       dim3(kNT), 0, st, X, L, I, R, norms, maxb);
+  else if (L == 1)
     hipLaunchKernelGGL(trk::k_colnorms_l1<T>, grid, dim3(kNT), 0, st, X, I, J, norms, maxb);
   else
     hipLaunchKernelGGL(trk::k_colnorms_ln<T>, grid, dim3(kNT), 0, st, X, L, I, R, norms, maxb);
@@ -344,9 +353,9 @@ int launch_colnorms_t(const T* X, int64_t L, int64_t I, int64_t R, double* norms
 }
 
 int launch_colnorms(bool f64, const void* X, int64_t L, int64_t I, int64_t R, double* norms,
-                    unsigned long long* maxb, hipStream_t st) {
-  return f64 ? launch_colnorms_t((const double*)X, L, I, R, norms, maxb, st)
-             : launch_colnorms_t((const float*)X, L, I, R, norms, maxb, st);
+                    unsigned long long* maxb, hipStream_t st, bool seg_ok = false) {
+  return f64 ? launch_colnorms_t((const double*)X, L, I, R, norms, maxb, st, seg_ok)
+             : launch_colnorms_t((const float*)X, L, I, R, norms, maxb, st, seg_ok);
 }
 
 int launch_fill(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t st) {
@@ -790,7 +799,7 @@ int range_sketch(const Plan& P, int n, const void* X, void* ws, const tr_diag* d
     double* scale2 = at<double>(ws, P.oScale2);
     if (norms_needed) {
       TimeScope ts(tm, TR_KC_COLNORMS, n, st);
-      TR_TRY(launch_colnorms(M.src_f64, X, M.L, M.I, M.R, norms, maxb, st));
+      TR_TRY(launch_colnorms(M.src_f64, X, M.L, M.I, M.R, norms, maxb, st, M.intermediate));
     }
     {
       TimeScope ts(tm, TR_KC_SAMPLE, n, st);
