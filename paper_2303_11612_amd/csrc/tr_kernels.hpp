@@ -129,10 +129,55 @@ __device__ __forceinline__ void stage_fiber_chunk(const T* __restrict__ base, in
   store_fiber_chunk<T, TI>(v, ok, tile);
 }
 
+// The same chunk with 16-byte loads (VW consecutive rows of one column per
+// load); needs I a multiple of VW and a 16-byte aligned base.
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+  static constexpr int W = 4;
+};
+template <>
+struct Vec16<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+  static constexpr int W = 2;
+};
+template <typename T, int TI>
+struct FiberChunkV {
+  static constexpr int VW = Vec16<T>::W, NV = TI / VW;  // vectors per column chunk
+  typename Vec16<T>::type v[NV];                           // NV = loads per thread
+  bool ok[NV];
+  __device__ __forceinline__ void load(const T* __restrict__ base, int64_t I, int64_t i0,
+                                       int ncol) {
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+      const int e = threadIdx.x + kNT * m;
+      const int cc = e / NV, q = e % NV;
+      ok[m] = cc < ncol && i0 + VW * q < I;
+      v[m] = *reinterpret_cast<const typename Vec16<T>::type*>(
+          base + (ok[m] ? (int64_t)cc * I + i0 + VW * q : 0));
+    }
+  }
+  __device__ __forceinline__ void store(T (*tile)[kNT + 1]) const {
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+      const int e = threadIdx.x + kNT * m;
+      const int cc = e / NV, q = e % NV;
+      if (ok[m]) {
+#pragma unroll
+        for (int t = 0; t < VW; ++t) tile[VW * q + t][cc] = v[m][t];
+      }
+    }
+  }
+};
+
 // ---------------------------------------------------------------------------
 // K3  Column norms n_j = ||A_(n)(:, j)||^2, rows summed in increasing order.
+// VEC: the chunks are loaded 16 bytes at a time (I a multiple of 16/sizeof(T),
+// X 16-byte aligned).
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool VEC>
 __global__ void __launch_bounds__(kNT)
 k_colnorms_l1(const T* __restrict__ X, int64_t I, int64_t J,
               double* __restrict__ norms, unsigned long long* __restrict__ max_bits) {
@@ -145,13 +190,19 @@ k_colnorms_l1(const T* __restrict__ X, int64_t I, int64_t J,
   const T* base = X + j0 * I;
   double acc = 0.0;
   // the next chunk's loads are in flight while this one is summed from LDS
-  T v[TI];
-  bool ok[TI];
-  load_fiber_chunk<T, TI>(base, I, 0, ncol, v, ok);
+  T v[VEC ? 1 : TI];
+  bool ok[VEC ? 1 : TI];
+  FiberChunkV<T, TI> cv;
+  if constexpr (VEC) cv.load(base, I, 0, ncol);
+  else load_fiber_chunk<T, TI>(base, I, 0, ncol, v, ok);
   for (int64_t i0 = 0; i0 < I; i0 += TI) {
-    store_fiber_chunk<T, TI>(v, ok, tile);
+    if constexpr (VEC) cv.store(tile);
+    else store_fiber_chunk<T, TI>(v, ok, tile);
     __syncthreads();
-    if (i0 + TI < I) load_fiber_chunk<T, TI>(base, I, i0 + TI, ncol, v, ok);
+    if (i0 + TI < I) {
+      if constexpr (VEC) cv.load(base, I, i0 + TI, ncol);
+      else load_fiber_chunk<T, TI>(base, I, i0 + TI, ncol, v, ok);
+    }
     const int ti = (int)min((int64_t)TI, I - i0);
     if (c < ncol)
       for (int ii = 0; ii < ti; ++ii) acc = sq_add(acc, (double)tile[ii][c]);

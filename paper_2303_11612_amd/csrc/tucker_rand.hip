@@ -345,8 +345,13 @@ int launch_colnorms_t(const T* X, int64_t L, int64_t I, int64_t R, double* norms
   if (seg_ok && J < 64 * (int64_t)kNT && I >= 4 * kSeg)
     hipLaunchKernelGGL((trk::k_colnorms_seg<T, kSeg>), dim3((unsigned)cdiv(J, kNT / kSeg)),
                        dim3(kNT), 0, st, X, L, I, R, norms, maxb);
+  else if (L == 1 && (I * (int64_t)sizeof(T)) % 16 == 0 &&
+           reinterpret_cast<uintptr_t>(X) % 16 == 0)
+    hipLaunchKernelGGL((trk::k_colnorms_l1<T, true>), grid, dim3(kNT), 0, st, X, I, J, norms,
+                       maxb);
   else if (L == 1)
-    hipLaunchKernelGGL(trk::k_colnorms_l1<T>, grid, dim3(kNT), 0, st, X, I, J, norms, maxb);
+    hipLaunchKernelGGL((trk::k_colnorms_l1<T, false>), grid, dim3(kNT), 0, st, X, I, J, norms,
+                       maxb);
   else
     hipLaunchKernelGGL(trk::k_colnorms_ln<T>, grid, dim3(kNT), 0, st, X, L, I, R, norms, maxb);
   return check_launch();
