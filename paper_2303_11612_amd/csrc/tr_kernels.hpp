@@ -333,6 +333,62 @@ k_ttm_ln(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
   }
 }
 
+// Y = X x_n Q^T for a view with few columns (one launch): S threads per
+// column each take a contiguous segment of ceil(I/S) rows (MU accumulators,
+// rows in increasing order), and the segment sums are added in segment order
+// in LDS; colscale (optional) multiplies column j's outputs.  Qt is row-major
+// with row stride MU.
+template <typename Tin, int MU, int S>
+__global__ void __launch_bounds__(kNT)
+k_ttm_seg(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
+          const double* __restrict__ Qt, int kout, const double* __restrict__ colscale,
+          double* __restrict__ Y) {
+  constexpr int CPB = kNT / S;  // columns per workgroup
+  __shared__ double part[S][CPB][MU];
+  const int cl = threadIdx.x % CPB, sg = threadIdx.x / CPB;
+  const int64_t J = L * R;
+  const int64_t j = (int64_t)blockIdx.x * CPB + cl;
+  const bool act = j < J;
+  const int64_t jj = act ? j : 0;
+  const int64_t r = jj / L, l = jj - r * L;
+  const Tin* p = X + l + L * I * r;
+  const int64_t seg = (I + S - 1) / S;
+  const int64_t ia = sg * seg, ib = min(I, ia + seg);
+  double acc[MU];
+#pragma unroll
+  for (int k = 0; k < MU; ++k) acc[k] = 0.0;
+  constexpr int B = 8;
+  for (int64_t i0 = ia; i0 < ib; i0 += B) {
+    Tin v[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) v[b] = p[L * min(i0 + b, ib - 1)];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      if (i0 + b < ib) {
+        const double x = act ? (double)v[b] : 0.0;
+        const double* q = Qt + (i0 + b) * MU;
+#pragma unroll
+        for (int k = 0; k < MU; ++k) acc[k] = fma(q[k], x, acc[k]);
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < MU; ++k) part[sg][cl][k] = acc[k];
+  __syncthreads();
+  for (int e = threadIdx.x; e < CPB * kout; e += kNT) {
+    const int c = e / kout, k = e - c * kout;
+    const int64_t jc = (int64_t)blockIdx.x * CPB + c;
+    if (jc < J) {
+      double t = part[0][c][k];
+#pragma unroll
+      for (int g = 1; g < S; ++g) t += part[g][c][k];
+      if (colscale) t *= colscale[jc];
+      const int64_t rc = jc / L, lc = jc - rc * L;
+      Y[lc + L * (k + (int64_t)kout * rc)] = t;
+    }
+  }
+}
+
 // Mode product for views with few columns: block (x, y) covers kNT columns
 // and the rows [y*ich, (y+1)*ich); partial sums over its rows go to
 // part[y][j*MU + k] and are added in increasing y by k_sum_splits.

@@ -478,6 +478,13 @@ void ttm_w(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Qt, int 
   const int64_t J = L * R;
   const dim3 grid((unsigned)cdiv(J, kNT));
   const int64_t ns = split ? ttm_splits(J, I) : 1;
+  if (ns > 1 && MU <= 24) {
+    // segments combined inside the workgroup: one launch, no partials
+    constexpr int S = 16;
+    hipLaunchKernelGGL((trk::k_ttm_seg<Tin, MU, S>), dim3((unsigned)cdiv(J, kNT / S)),
+                       dim3(kNT), 0, st, X, L, I, R, Qt, kout, colscale, Y);
+    return;
+  }
   if (ns > 1) {
     const int64_t ich = cdiv(I, ns);
     const int64_t nsu = cdiv(I, ich);
