@@ -48,7 +48,7 @@ def _parse():
                          "the 100^4 and 512x512x256 configurations; all: everything "
                          "in one line")
     ap.add_argument("--requests", type=int, default=512)
-    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--budget-gb", type=float, default=16.0)
     ap.add_argument("--load", type=float, default=0.7,
                     help="arrival rate as a fraction of the one-at-a-time throughput")

@@ -143,7 +143,7 @@ class GpuBackend:
 class Server:
     """Admission by free slot and HBM footprint, in arrival order."""
 
-    def __init__(self, backend, slots: int = 4, hbm_budget: int = 16 * GIB,
+    def __init__(self, backend, slots: int = 8, hbm_budget: int = 16 * GIB,
                  lookahead: int = 8):
         if slots < 1:
             raise ValueError("slots must be >= 1")
