@@ -33,18 +33,23 @@ constexpr int kPwBatch = 4;  // loop iterations whose loads are issued together
 // row stride 16 NKT; columns k >= s come out zero).  Y is read from its
 // row-major copy Yt (row stride sw >= s, zero padding).  Block: one tile of
 // 16 columns j; its four waves take interleaved quarters of the rows i and
-// their partial tiles are added in LDS (wave order 0..3).
-template <typename Tin, int NKT>
+// their partial tiles are added in LDS (wave order 0..3).  WPT (few rows):
+// each wave takes a tile of its own (64 columns per block) and all its rows,
+// in order, with no reduction across waves.
+template <typename Tin, int NKT, bool WPT = false>
 __global__ void __launch_bounds__(kPwWaves * kWave)
 k_pw_w(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
        const double* __restrict__ colw, const double* __restrict__ Yt, int sw,
        double* __restrict__ W) {
   constexpr int SP = 16 * NKT;
-  __shared__ f64x4 red[kPwWaves - 1][NKT][kWave];
+  constexpr int kSplit = WPT ? 1 : kPwWaves;  // waves sharing a tile's rows
+  __shared__ f64x4 red[WPT ? 1 : kPwWaves - 1][NKT][kWave];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int h = lane & 15, g = lane >> 4;
   const int64_t J = L * R;
-  const int64_t j = (int64_t)blockIdx.x * 16 + h;
+  const int64_t tile = WPT ? (int64_t)blockIdx.x * kPwWaves + wid : (int64_t)blockIdx.x;
+  const int rw = WPT ? 0 : wid;  // this wave's first chunk
+  const int64_t j = tile * 16 + h;
   const bool jok = j < J;
   const int64_t jc = jok ? j : J - 1;
   const int64_t r = jc / L;
@@ -53,14 +58,14 @@ k_pw_w(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
   f64x4 acc[NKT];
 #pragma unroll
   for (int kt = 0; kt < NKT; ++kt) acc[kt] = f64x4{0.0, 0.0, 0.0, 0.0};
-  // chunks wid, wid + 4, ...; kPwBatch of them have their loads in flight together
-  for (int64_t c0 = wid; c0 < nch; c0 += kPwWaves * kPwBatch) {
+  // chunks rw, rw + kSplit, ...; kPwBatch of them have their loads in flight together
+  for (int64_t c0 = rw; c0 < nch; c0 += kSplit * kPwBatch) {
     // all loads of the batch first (raw values), then masks and products
     Tin xr[kPwBatch][4];
     double yr[kPwBatch][4][NKT];
 #pragma unroll
     for (int u = 0; u < kPwBatch; ++u) {
-      const int64_t c = c0 + kPwWaves * u;
+      const int64_t c = c0 + kSplit * u;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         // rows 16c + 4g + t feed the t-th product of chunk c
@@ -79,7 +84,7 @@ k_pw_w(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
     for (int u = 0; u < kPwBatch; ++u)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const bool iok = 16 * (c0 + kPwWaves * u) + 4 * g + t < I;
+        const bool iok = 16 * (c0 + kSplit * u) + 4 * g + t < I;
         const double b = (double)xr[u][t] * ((jok && iok) ? 1.0 : 0.0);
 #pragma unroll
         for (int kt = 0; kt < NKT; ++kt) {
@@ -88,18 +93,22 @@ k_pw_w(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
         }
       }
   }
-  if (wid > 0) {
+  if constexpr (!WPT) {
+    if (wid > 0) {
 #pragma unroll
-    for (int kt = 0; kt < NKT; ++kt) red[wid - 1][kt][lane] = acc[kt];
+      for (int kt = 0; kt < NKT; ++kt) red[wid - 1][kt][lane] = acc[kt];
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  if (wid == 0 && jok) {
+  if ((WPT || wid == 0) && jok) {
     const double d = colw ? colw[j] : 1.0;
 #pragma unroll
     for (int kt = 0; kt < NKT; ++kt) {
       f64x4 v = acc[kt];
+      if constexpr (!WPT) {
 #pragma unroll
-      for (int w = 0; w < kPwWaves - 1; ++w) v += red[w][kt][lane];
+        for (int w = 0; w < kPwWaves - 1; ++w) v += red[w][kt][lane];
+      }
 #pragma unroll
       for (int q = 0; q < 4; ++q) W[j * SP + 16 * kt + g + 4 * q] = v[q] * d;
     }
@@ -218,15 +227,21 @@ k_pw_y(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
 // last group again; a column beyond R reads column R - 1, and its outputs are
 // not stored).  Work items are (tile, B steps); the loads of the next item
 // are in flight while the current one is multiplied out, from two
-// alternating register buffers.
-template <typename Tin, int B>
-__device__ __forceinline__ void ttm1_load(const Tin* __restrict__ col, int64_t I, int64_t s0,
-                                          int g, Tin (&xr)[B][4]) {
+// alternating register buffers.  STR: the columns are those of an L x I x R
+// view (column j = l + L r at X + l + L I r, rows at stride L, one scalar
+// load per row clamped to row I - 1; any I); the outputs keep the layout
+// Y[k + kout j] (the first product of a power step, W = X^T Y).
+template <typename Tin, int B, bool STR = false>
+__device__ __forceinline__ void ttm1_load(const Tin* __restrict__ col, int64_t L, int64_t I,
+                                          int64_t s0, int g, Tin (&xr)[B][4]) {
 #pragma unroll
   for (int u = 0; u < B; ++u) {
     const int64_t i0 = 16 * (s0 + u) + 4 * g;
     const int64_t ic = i0 + 4 <= I ? i0 : I - 4;
-    if constexpr (sizeof(Tin) == 4) {
+    if constexpr (STR) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) xr[u][t] = col[L * (i0 + t < I ? i0 + t : I - 1)];
+    } else if constexpr (sizeof(Tin) == 4) {
       const f32x4 v = *reinterpret_cast<const f32x4*>(col + ic);
 #pragma unroll
       for (int t = 0; t < 4; ++t) xr[u][t] = v[t];
@@ -241,10 +256,10 @@ __device__ __forceinline__ void ttm1_load(const Tin* __restrict__ col, int64_t I
   }
 }
 
-template <typename Tin, int NKT, int B>
+template <typename Tin, int NKT, int B, bool STR = false>
 __global__ void __launch_bounds__(kPwWaves * kWave)
-k_ttm1_mfma(const Tin* __restrict__ X, int64_t I, int64_t R, const double* __restrict__ Qt,
-            int width, int kout, double* __restrict__ Y) {
+k_ttm1_mfma(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
+            const double* __restrict__ Qt, int width, int kout, double* __restrict__ Y) {
   constexpr int SP = 16 * NKT;
   extern __shared__ double qs[];  // qs[i * SP + k] = Q(i, k), zero rows i >= I
   const int64_t nsteps = (I + 15) / 16;
@@ -263,11 +278,17 @@ k_ttm1_mfma(const Tin* __restrict__ X, int64_t I, int64_t R, const double* __res
   int64_t tile = (int64_t)blockIdx.x * kPwWaves + wid, s0 = 0;
   if (tile >= ntile) return;
   auto colp = [&](int64_t tl) {
-    const int64_t j = tl * 16 + h;
-    return X + (j < R ? j : R - 1) * I;
+    const int64_t j0 = tl * 16 + h;
+    const int64_t j = j0 < R ? j0 : R - 1;
+    if constexpr (STR) {
+      const int64_t r = j / L;
+      return X + (j - r * L) + L * I * r;
+    } else {
+      return X + j * I;
+    }
   };
   Tin xa[B][4], xb[B][4];
-  ttm1_load<Tin, B>(colp(tile), I, s0, g, xa);
+  ttm1_load<Tin, B, STR>(colp(tile), L, I, s0, g, xa);
   f64x4 acc[NKT];
 #pragma unroll
   for (int kt = 0; kt < NKT; ++kt) acc[kt] = f64x4{0.0, 0.0, 0.0, 0.0};
@@ -281,7 +302,7 @@ k_ttm1_mfma(const Tin* __restrict__ X, int64_t I, int64_t R, const double* __res
     const bool more = ntl < ntile;
     // unconditional (the last item reloads its own rows): a conditional
     // prefetch would make every wait below count as if it had not been issued
-    ttm1_load<Tin, B>(colp(more ? ntl : tile), I, more ? ns : s0, g, nxt);
+    ttm1_load<Tin, B, STR>(colp(more ? ntl : tile), L, I, more ? ns : s0, g, nxt);
     __builtin_amdgcn_sched_barrier(0);
     const double* qb = qs + (16 * s0 + 4 * g) * SP + h;
 #pragma unroll

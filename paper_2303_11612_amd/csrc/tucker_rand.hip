@@ -87,8 +87,8 @@ inline int64_t pw_width(int64_t s) { return 16 * cdiv(s, 16); }
 constexpr int kPwMT = 2;
 inline int64_t pw_itiles(int64_t I) { return cdiv(I, 16 * kPwMT); }
 inline int64_t pw_splits(int64_t I, int64_t J) {
-  // about one block per compute unit, at least 64 columns per range
-  return std::max<int64_t>(1, std::min<int64_t>(cdiv(256, pw_itiles(I)), cdiv(J, 64)));
+  // about four blocks per compute unit, at least 64 columns per range
+  return std::max<int64_t>(1, std::min<int64_t>(cdiv(1024, pw_itiles(I)), cdiv(J, 64)));
 }
 // Number of partial sketches a power step on this source produces.
 inline int64_t power_parts(int64_t I, int64_t J) {
@@ -433,42 +433,54 @@ inline int ttm1_batch(int64_t I) {
   return best;
 }
 
-template <typename Tin, int NKT, int B>
-void ttm1_mfma_k(const Tin* X, int64_t I, int64_t R, const double* Qt, int width, int kout,
-                 double* Y, hipStream_t st) {
+template <typename Tin, int NKT, int B, bool STR>
+void ttm1_mfma_k(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Qt, int width,
+                 int kout, double* Y, hipStream_t st) {
   const size_t lds = 8 * (size_t)(cdiv(cdiv(I, 16), B) * B * 16) * 16 * NKT;
   if (lds > 65536)
-    (void)hipFuncSetAttribute((const void*)&trk::k_ttm1_mfma<Tin, NKT, B>,
+    (void)hipFuncSetAttribute((const void*)&trk::k_ttm1_mfma<Tin, NKT, B, STR>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   const int64_t ntile = cdiv(R, 16);
   // persistent blocks: as many as fit three to a compute unit (by the Q^T
   // tile in LDS), capped by the tiles there are
   const int64_t per_cu = lds <= 53248 ? 3 : (lds <= 81920 ? 2 : 1);
   const int64_t nblk = std::max<int64_t>(1, std::min<int64_t>(256 * per_cu, cdiv(ntile, trk::kPwWaves)));
-  hipLaunchKernelGGL((trk::k_ttm1_mfma<Tin, NKT, B>), dim3((unsigned)nblk),
-                     dim3(trk::kPwWaves * trk::kWave), lds, st, X, I, R, Qt, width, kout, Y);
+  hipLaunchKernelGGL((trk::k_ttm1_mfma<Tin, NKT, B, STR>), dim3((unsigned)nblk),
+                     dim3(trk::kPwWaves * trk::kWave), lds, st, X, L, I, R, Qt, width, kout, Y);
 }
 
-template <typename Tin, int NKT>
-void ttm1_mfma_b(const Tin* X, int64_t I, int64_t R, const double* Qt, int width, int kout,
-                 double* Y, hipStream_t st) {
+template <typename Tin, int NKT, bool STR>
+void ttm1_mfma_b(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Qt, int width,
+                 int kout, double* Y, hipStream_t st) {
   switch (ttm1_batch(I)) {
-    case 4: ttm1_mfma_k<Tin, NKT, 4>(X, I, R, Qt, width, kout, Y, st); break;
-    case 5: ttm1_mfma_k<Tin, NKT, 5>(X, I, R, Qt, width, kout, Y, st); break;
-    case 6: ttm1_mfma_k<Tin, NKT, 6>(X, I, R, Qt, width, kout, Y, st); break;
-    default: ttm1_mfma_k<Tin, NKT, 8>(X, I, R, Qt, width, kout, Y, st); break;
+    case 4: ttm1_mfma_k<Tin, NKT, 4, STR>(X, L, I, R, Qt, width, kout, Y, st); break;
+    case 5: ttm1_mfma_k<Tin, NKT, 5, STR>(X, L, I, R, Qt, width, kout, Y, st); break;
+    case 6: ttm1_mfma_k<Tin, NKT, 6, STR>(X, L, I, R, Qt, width, kout, Y, st); break;
+    default: ttm1_mfma_k<Tin, NKT, 8, STR>(X, L, I, R, Qt, width, kout, Y, st); break;
   }
 }
 
+// Y[k + kout j] = sum_i Qt[i width + k] X_(n)(i, j) on the matrix cores, for
+// the columns j < J of a plain I x J matrix (L == 1: 16-byte loads, I a
+// multiple of 4, X 16-byte aligned) or of an L x I x R view (strided loads;
+// the caller must want the outputs in this layout).  False if not applicable.
 template <typename Tin>
-bool ttm1_mfma(const Tin* X, int64_t I, int64_t R, const double* Qt, int width, int kout,
-               double* Y, hipStream_t st) {
-  if (I % 4 != 0 || (reinterpret_cast<uintptr_t>(X) % 16) != 0 || kout > 32) return false;
+bool ttm1_mfma(const Tin* X, int64_t L, int64_t I, int64_t J, const double* Qt, int width,
+               int kout, double* Y, hipStream_t st) {
+  const bool str = L > 1;
+  if (kout > 32) return false;
+  if (!str && (I % 4 != 0 || (reinterpret_cast<uintptr_t>(X) % 16) != 0)) return false;
+  if (I < 4) return false;
   const int nkt = (int)cdiv(kout, 16);
   const int b = ttm1_batch(I);
   if (8 * (size_t)(cdiv(cdiv(I, 16), b) * b * 16) * 16 * nkt > 131072) return false;
-  if (nkt == 1) ttm1_mfma_b<Tin, 1>(X, I, R, Qt, width, kout, Y, st);
-  else ttm1_mfma_b<Tin, 2>(X, I, R, Qt, width, kout, Y, st);
+  if (str) {
+    if (nkt == 1) ttm1_mfma_b<Tin, 1, true>(X, L, I, J, Qt, width, kout, Y, st);
+    else ttm1_mfma_b<Tin, 2, true>(X, L, I, J, Qt, width, kout, Y, st);
+  } else {
+    if (nkt == 1) ttm1_mfma_b<Tin, 1, false>(X, 1, I, J, Qt, width, kout, Y, st);
+    else ttm1_mfma_b<Tin, 2, false>(X, 1, I, J, Qt, width, kout, Y, st);
+  }
   return true;
 }
 
@@ -494,7 +506,7 @@ void ttm_w(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Qt, int 
                        split, nsu, L, R, MU, kout, colscale, Y);
     return;
   }
-  if (L == 1 && !colscale && ttm1_mfma(X, I, R, Qt, MU, kout, Y, st)) return;
+  if (L == 1 && !colscale && ttm1_mfma(X, 1, I, R, Qt, MU, kout, Y, st)) return;
   if (L == 1)
     hipLaunchKernelGGL((trk::k_ttm_l1<Tin, MU>), grid, dim3(kNT), 0, st, X, I, R, Qt, kout,
                        colscale, Y);
@@ -546,8 +558,19 @@ template <typename Tin, int NKT>
 int pw_step(const Tin* X, int64_t L, int64_t I, int64_t R, const double* colw, const double* Yt,
             int sw, int s, double* W, double* part, int64_t* nparts, hipStream_t st) {
   const int64_t J = L * R;
-  hipLaunchKernelGGL((trk::k_pw_w<Tin, NKT>), dim3((unsigned)cdiv(J, 16)),
-                     dim3(trk::kPwWaves * trk::kWave), 0, st, X, L, I, R, colw, Yt, sw, W);
+  // W = X^T Y for a plain I x J matrix is the mode-1 shrink with Q^T = Yt:
+  // the persistent MFMA kernel (Yt staged in LDS, 16-byte loads, next tile in
+  // flight) when there are no column weights
+  if (!colw && ttm1_mfma(X, L, I, J, Yt, sw, 16 * NKT, W, st)) {
+    TR_TRY(check_launch());
+  } else if (cdiv(J, 16 * trk::kPwWaves) >= 1024)
+    // many columns: a tile per wave (no reduction across waves) still gives
+    // at least four workgroups per compute unit
+    hipLaunchKernelGGL((trk::k_pw_w<Tin, NKT, true>), dim3((unsigned)cdiv(J, 16 * trk::kPwWaves)),
+                       dim3(trk::kPwWaves * trk::kWave), 0, st, X, L, I, R, colw, Yt, sw, W);
+  else
+    hipLaunchKernelGGL((trk::k_pw_w<Tin, NKT>), dim3((unsigned)cdiv(J, 16)),
+                       dim3(trk::kPwWaves * trk::kWave), 0, st, X, L, I, R, colw, Yt, sw, W);
   TR_TRY(check_launch());
   const int64_t jper = cdiv(J, pw_splits(I, J));
   const int64_t ny = cdiv(J, jper);
