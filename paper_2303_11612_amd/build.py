@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 SOURCES = [
     # one unit per factor kernel instance (FactorVariant 0 .. 13), the slowest
     ("tr_factor_inst.hip", (f"-DTR_FACTOR_INST={k}",)) for k in range(14)] + [
-    ("tr_lowp_launch.hip", ()), ("tucker_rand.hip", ()), ("tr_factor_launch.hip", ())]
+    ("tr_lowp_launch.hip", ()), ("tucker_rand.hip", ()), ("tr_factor_launch.hip", ()),
+    ("tr_pw_fused.hip", ())]
 SRC = os.path.join(CSRC, "tucker_rand.hip")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libtucker_rand.so")

@@ -60,6 +60,20 @@ enum FactorVariant {
   kLds16, kLds32, kLds64, kGlb16, kGlb32, kGlb64, kRf24x1, kRf24x2
 };
 
+// Fused exact power step (k_pw_fused): I <= 128 rows and sketch width
+// s <= 32; one partial sketch per block, pw_fused_blocks(J) blocks.  In
+// tr_pw_fused.hip; TR_ENOTSUP (nothing launched) when not applicable.
+inline bool pw_fused_ok(int64_t I, int64_t J, int64_t s) {
+  return I >= 1 && I <= 128 && s >= 1 && s <= 32 && J >= 1;
+}
+inline int64_t pw_fused_blocks(int64_t J) {
+  // one block per compute unit: the wider instances hold one wave per SIMD
+  return std::max<int64_t>(1, std::min<int64_t>(256, cdiv(cdiv(J, 16), 4)));
+}
+int launch_pw_fused(bool f64, const void* X, int64_t L, int64_t I, int64_t R,
+                    const double* colw, const double* Yt, int sw, int64_t s, double* part,
+                    int64_t* nparts, hipStream_t st);
+
 // One launch of the factor kernel instance `var` over n jobs (one workgroup
 // each).  In tr_factor_launch.hip.
 int launch_factor_group(int var, const trk::FactorJobs& jobs, int n, int cast_f32,

@@ -336,4 +336,152 @@ k_ttm1_mfma(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
   }
 }
 
+// One exact power step in a single sweep, for I <= 16 NCH (NCH <= 8) rows and
+// sketch width s <= 16 NKT (NKT <= 2): for each 16-column tile J_t of
+// X_(n) (one wave per tile at a time, persistent),
+//   W_t = D_t X_(n)(:, J_t)^T Y      (16 x 16 NKT, on the matrix cores,
+//                                      Y staged in LDS, zero beyond I and s)
+//   P  += X_(n)(:, J_t) W_t          (I x 16 NKT, accumulated in registers)
+// so W never leaves the compute unit and X is read from HBM once.  W_t goes
+// through a per-wave LDS tile to change operand layout (row j = column of the
+// tile, scaled by the column weight d_j, zero for columns past J).  X is
+// loaded twice per tile, in the two operand layouts (the second load hits
+// the caches).  A block adds its four waves' P in wave order and writes
+// part[block] (column-major I x s); k_reduce_parts adds the blocks in order.
+__device__ __forceinline__ void wave_lds_order() {
+  // LDS operations of one wave complete in issue order; this keeps the
+  // compiler from moving LDS reads and writes across it
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
+template <typename Tin, int NKT, int NCH>
+__global__ void __launch_bounds__(kPwWaves * kWave)
+k_pw_fused(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
+           const double* __restrict__ colw, const double* __restrict__ Yt, int sw, int s,
+           double* __restrict__ part) {
+  constexpr int SP = 16 * NKT, IP = 16 * NCH;
+  __shared__ double ys[IP * SP];               // Y(i, k), zero for i >= I or k >= sw
+  __shared__ double wl[kPwWaves][16 * SP];     // per wave: W(j, k) of its tile, row j
+  __shared__ f64x4 red[kPwWaves - 1][NKT][kWave];
+  for (int e = threadIdx.x; e < IP * SP; e += kPwWaves * kWave) {
+    const int i = e / SP, k = e - i * SP;
+    ys[e] = (i < I && k < sw) ? Yt[(int64_t)(i < I ? i : 0) * sw + (k < sw ? k : 0)] : 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int h = lane & 15, g = lane >> 4;
+  const int64_t J = L * R, ntile = (J + 15) / 16;
+  const int64_t stride = (int64_t)gridDim.x * kPwWaves;
+  auto colp = [&](int64_t j) {
+    const int64_t jc = j < J ? j : J - 1;
+    const int64_t r = jc / L;
+    return X + (jc - r * L) + L * I * r;
+  };
+  f64x4 acc[NCH][NKT];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c)
+#pragma unroll
+    for (int kt = 0; kt < NKT; ++kt) acc[c][kt] = f64x4{0.0, 0.0, 0.0, 0.0};
+  double* w = wl[wid];
+  // B layout of the first product: rows 16c + 4g + t of column 16 tile + h;
+  // A layout of the second: row 16c + h of columns 16 tile + 4q + g.  Loads
+  // overlap the products: a tile's A operands are issued before its first
+  // product, the next tile's B operands before its second product (past the
+  // last tile a wave reloads its own tile).
+  auto load_b = [&](int64_t tl, Tin (&xb)[NCH][4]) __attribute__((always_inline)) {
+    const Tin* pb = colp(tl * 16 + h);
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int64_t i = 16 * c + 4 * g + t;
+        xb[c][t] = pb[L * (i < I ? i : I - 1)];
+      }
+  };
+  auto load_a = [&](int64_t tl, Tin (&xa)[NCH][4]) __attribute__((always_inline)) {
+    const Tin* pa[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) pa[q] = colp(tl * 16 + 4 * q + g);
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const int64_t i = 16 * c + h;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) xa[c][q] = pa[q][L * (i < I ? i : I - 1)];
+    }
+  };
+  int64_t tile = (int64_t)blockIdx.x * kPwWaves + wid;
+  if (tile < ntile) {
+    Tin xb[NCH][4], xa[NCH][4];
+    load_b(tile, xb);
+    for (; tile < ntile; tile += stride) {
+      load_a(tile, xa);
+      __builtin_amdgcn_sched_barrier(0);
+      // W^T(k, j) = sum_i Y(i, k) X(i, j): lane (g, h), item v holds k = 16 kt + g + 4 v, j = h
+      f64x4 aw[NKT];
+#pragma unroll
+      for (int kt = 0; kt < NKT; ++kt) aw[kt] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const double b = (double)xb[c][t];
+          const double* yr = ys + (16 * c + 4 * g + t) * SP + h;
+#pragma unroll
+          for (int kt = 0; kt < NKT; ++kt) aw[kt] = mfma_f64(yr[16 * kt], b, aw[kt]);
+        }
+      __builtin_amdgcn_sched_barrier(0);
+      load_b(tile + stride < ntile ? tile + stride : tile, xb);
+      __builtin_amdgcn_sched_barrier(0);
+      const int64_t jb = tile * 16 + h;
+      double d = 0.0;
+      if (jb < J) d = colw ? colw[jb] : 1.0;
+#pragma unroll
+      for (int kt = 0; kt < NKT; ++kt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) w[h * SP + 16 * kt + g + 4 * v] = aw[kt][v] * d;
+      wave_lds_order();
+      // P(i, k) += sum_j X(i, j) W(j, k): A = X(16c + h, 4q + g), B = W(4q + g, 16 kt + h)
+      double wb[4][NKT];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int kt = 0; kt < NKT; ++kt) wb[q][kt] = w[(4 * q + g) * SP + 16 * kt + h];
+#pragma unroll
+      for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double a = (double)xa[c][q];
+#pragma unroll
+          for (int kt = 0; kt < NKT; ++kt) acc[c][kt] = mfma_f64(a, wb[q][kt], acc[c][kt]);
+        }
+      wave_lds_order();
+    }
+  }
+  // lane (g, h), item v of acc[c][kt]: row 16c + g + 4v, column k = 16 kt + h
+  double* out = part + (int64_t)blockIdx.x * I * s;
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    if (wid > 0) {
+#pragma unroll
+      for (int kt = 0; kt < NKT; ++kt) red[wid - 1][kt][lane] = acc[c][kt];
+    }
+    __syncthreads();
+    if (wid == 0) {
+#pragma unroll
+      for (int kt = 0; kt < NKT; ++kt) {
+        f64x4 v = acc[c][kt];
+#pragma unroll
+        for (int ww = 0; ww < kPwWaves - 1; ++ww) v += red[ww][kt][lane];
+        const int k = 16 * kt + h;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t i = 16 * c + g + 4 * q;
+          if (i < I && k < s) out[i + I * k] = v[q];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace trk

@@ -90,10 +90,11 @@ inline int64_t pw_splits(int64_t I, int64_t J) {
   // about four blocks per compute unit, at least 64 columns per range
   return std::max<int64_t>(1, std::min<int64_t>(cdiv(1024, pw_itiles(I)), cdiv(J, 64)));
 }
-// Number of partial sketches a power step on this source produces.
-inline int64_t power_parts(int64_t I, int64_t J) {
+// Number of partial sketches a power step on this source produces (at most).
+inline int64_t power_parts(int64_t I, int64_t J, int64_t s) {
   const int64_t ns = pw_splits(I, J);
-  return cdiv(J, cdiv(J, ns));
+  const int64_t two = cdiv(J, cdiv(J, ns));
+  return pw_fused_ok(I, J, s) ? std::max(two, pw_fused_blocks(J)) : two;
 }
 
 // Views with few columns split their rows over blocks (k_ttm_split) so that
@@ -238,7 +239,7 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
     maxZ = std::max(maxZ, (size_t)(jsrc * pw_width(M.s)));
     // the shrink of this mode reads the tensor the mode is computed from
     maxSplit = std::max(maxSplit, (size_t)(ttm_splits(M.J, M.I) * M.J * M.muw));
-    maxPart = std::max(maxPart, (size_t)(power_parts(M.I, jsrc) * M.I * M.s));
+    maxPart = std::max(maxPart, (size_t)(power_parts(M.I, jsrc, M.s) * M.I * M.s));
     maxS = std::max(maxS, M.s);
     if (M.sampled) {
       maxJs = std::max(maxJs, (size_t)M.J);
@@ -598,7 +599,7 @@ size_t power_ws_bytes(int64_t L, int64_t I, int64_t R, int64_t s, bool f64) {
   (void)f64;
   const int64_t J = L * R;
   const int sw = pad_width(s);
-  return align_up(8 * (size_t)(J * pw_width(s))) + align_up(8 * (size_t)(power_parts(I, J) * I * s)) +
+  return align_up(8 * (size_t)(J * pw_width(s))) + align_up(8 * (size_t)(power_parts(I, J, s) * I * s)) +
          align_up(8 * (size_t)(I * sw));
 }
 
@@ -609,8 +610,13 @@ int run_power(bool f64, const void* X, int64_t L, int64_t I, int64_t R, const do
               uint32_t* status, hipStream_t st) {
   for (int step = 0; step < q; ++step) {
     int64_t nused = 0;
-    if (f64) TR_TRY(pw_step_t((const double*)X, L, I, R, colw, Yt, sw, s, Z, part, &nused, st));
-    else TR_TRY(pw_step_t((const float*)X, L, I, R, colw, Yt, sw, s, Z, part, &nused, st));
+    // one sweep with W kept on chip when the rows and the sketch are narrow
+    const int rc = launch_pw_fused(f64, X, L, I, R, colw, Yt, sw, s, part, &nused, st);
+    if (rc != TR_OK && rc != TR_ENOTSUP) return rc;
+    if (rc == TR_ENOTSUP) {
+      if (f64) TR_TRY(pw_step_t((const double*)X, L, I, R, colw, Yt, sw, s, Z, part, &nused, st));
+      else TR_TRY(pw_step_t((const float*)X, L, I, R, colw, Yt, sw, s, Z, part, &nused, st));
+    }
     hipLaunchKernelGGL(trk::k_reduce_parts, dim3((unsigned)cdiv(I * s, kNT)), dim3(kNT), 0, st,
                        part, nused, I, (int)s, sw, Y, Yt, status);
     TR_TRY(check_launch());
@@ -1161,7 +1167,7 @@ int tucker_rand_power(int dtype, const void* X, int64_t L, int64_t I, int64_t R,
   double* Z = (double*)ws;
   double* part = (double*)(ws + align_up(8 * (size_t)(J * pw_width(s))));
   double* Yt = (double*)(ws + align_up(8 * (size_t)(J * pw_width(s))) +
-                         align_up(8 * (size_t)(power_parts(I, J) * I * s)));
+                         align_up(8 * (size_t)(power_parts(I, J, s) * I * s)));
   hipLaunchKernelGGL(trk::k_transpose, dim3((unsigned)cdiv(I * sw, kNT)), dim3(kNT), 0, st, G, I,
                      s, (int64_t)sw, Yt);
   TR_TRY(check_launch());
