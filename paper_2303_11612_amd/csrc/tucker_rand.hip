@@ -559,12 +559,14 @@ template <typename Tin, int NKT>
 int pw_step(const Tin* X, int64_t L, int64_t I, int64_t R, const double* colw, const double* Yt,
             int sw, int s, double* W, double* part, int64_t* nparts, hipStream_t st) {
   const int64_t J = L * R;
-  // W = X^T Y for a plain I x J matrix is the mode-1 shrink with Q^T = Yt:
-  // the persistent MFMA kernel (Yt staged in LDS, 16-byte loads, next tile in
-  // flight) when there are no column weights
-  if (!colw && ttm1_mfma(X, L, I, J, Yt, sw, 16 * NKT, W, st)) {
+  // W = X^T Y has the shape of the mode-1 shrink with Q^T = Yt: the
+  // persistent MFMA kernel (Yt staged in LDS, next tile in flight) when there
+  // are no column weights and enough columns to occupy it (with few columns
+  // k_pw_w's one-tile blocks, rows split over four waves, are faster)
+  const bool many = cdiv(J, 16 * trk::kPwWaves) >= 1024;
+  if (!colw && many && ttm1_mfma(X, L, I, J, Yt, sw, 16 * NKT, W, st)) {
     TR_TRY(check_launch());
-  } else if (cdiv(J, 16 * trk::kPwWaves) >= 1024)
+  } else if (many)
     // many columns: a tile per wave (no reduction across waves) still gives
     // at least four workgroups per compute unit
     hipLaunchKernelGGL((trk::k_pw_w<Tin, NKT, true>), dim3((unsigned)cdiv(J, 16 * trk::kPwWaves)),
