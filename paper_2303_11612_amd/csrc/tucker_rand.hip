@@ -765,12 +765,45 @@ int factor_variant(int64_t I, int64_t s, int64_t mu, bool has_scratch, int* var)
 // sigma, optional cast copy of Q in the caller's dtype; gA: I x s float64
 // scratch, needed only when the working matrices do not fit in LDS (may
 // equal C).
+// Bounds of the register-resident instances: s <= SM, I <= 256 R, mu <= MU.
+struct RfBounds {
+  int var, sm, r, mu;
+};
+constexpr RfBounds kRfBounds[] = {
+    {kRf16x1, 16, 1, 16}, {kRf16x2, 16, 2, 16}, {kRf24x1, 24, 1, 24}, {kRf24x2, 24, 2, 16},
+    {kRf32x1, 32, 1, 32}, {kRf32x2, 32, 2, 16}, {kRf48x1, 48, 1, 48}, {kRf48x2, 48, 2, 32}};
+
+inline bool is_rf_variant(int var) {
+  for (const RfBounds& b : kRfBounds)
+    if (b.var == var) return true;
+  return false;
+}
+
 int launch_factor_jobs(const trk::FactorJob* job, int n, int cast_f32, uint32_t* status,
                        hipStream_t st) {
   if (n < 1 || n > trk::kMaxFactorJobs) return TR_EINVAL;
   int var[trk::kMaxFactorJobs];
   for (int b = 0; b < n; ++b)
     TR_TRY(factor_variant(job[b].I, job[b].s, job[b].mu, job[b].gA != nullptr, &var[b]));
+  // Jobs of different register-resident instances would run one launch after
+  // another; when one instance covers them all (the narrowest such), a single
+  // launch runs them side by side and takes about as long as its widest job.
+  bool all_rf = true, mixed = false;
+  for (int b = 0; b < n; ++b) {
+    all_rf = all_rf && is_rf_variant(var[b]);
+    mixed = mixed || var[b] != var[0];
+  }
+  if (all_rf && mixed) {
+    for (const RfBounds& c : kRfBounds) {
+      bool fits = true;
+      for (int b = 0; b < n; ++b)
+        fits = fits && job[b].s <= c.sm && job[b].I <= 256 * c.r && job[b].mu <= c.mu;
+      if (fits) {
+        for (int b = 0; b < n; ++b) var[b] = c.var;
+        break;
+      }
+    }
+  }
   bool done[trk::kMaxFactorJobs] = {};
   for (int b = 0; b < n; ++b) {
     if (done[b]) continue;
