@@ -15,8 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 # translation units, compiled in parallel and linked into one library: the
 # host driver, the factor kernel instances and the low-precision power steps
 SOURCES = [
-    # one unit per factor kernel instance (FactorVariant 0 .. 13), the slowest
-    ("tr_factor_inst.hip", (f"-DTR_FACTOR_INST={k}",)) for k in range(14)] + [
+    # one unit per factor kernel instance (FactorVariant 0 .. 15), the slowest
+    ("tr_factor_inst.hip", (f"-DTR_FACTOR_INST={k}",)) for k in range(16)] + [
     ("tr_lowp_launch.hip", ()), ("tucker_rand.hip", ()), ("tr_factor_launch.hip", ()),
     ("tr_pw_fused.hip", ())]
 SRC = os.path.join(CSRC, "tucker_rand.hip")

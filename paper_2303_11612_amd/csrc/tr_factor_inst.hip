@@ -143,5 +143,19 @@ int launch_factor_kRf24x2(const trk::FactorJobs& jobs, int n, int cast_f32, uint
   return factor_rf_jobs<24, 2, 16>(jobs, n, cast_f32, status, st);
 }
 #endif
+#if TR_FACTOR_INST == 14
+static_assert(kRf40x1 == 14, "instance numbering");
+int launch_factor_kRf40x1(const trk::FactorJobs& jobs, int n, int cast_f32, uint32_t* status,
+                      hipStream_t st) {
+  return factor_rf_jobs<40, 1, 40>(jobs, n, cast_f32, status, st);
+}
+#endif
+#if TR_FACTOR_INST == 15
+static_assert(kRf40x2 == 15, "instance numbering");
+int launch_factor_kRf40x2(const trk::FactorJobs& jobs, int n, int cast_f32, uint32_t* status,
+                      hipStream_t st) {
+  return factor_rf_jobs<40, 2, 32>(jobs, n, cast_f32, status, st);
+}
+#endif
 
 }  // namespace trh

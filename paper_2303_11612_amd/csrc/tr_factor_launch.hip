@@ -34,6 +34,10 @@ int launch_factor_kRf24x1(const trk::FactorJobs& jobs, int n, int cast_f32, uint
                       hipStream_t st);
 int launch_factor_kRf24x2(const trk::FactorJobs& jobs, int n, int cast_f32, uint32_t* status,
                       hipStream_t st);
+int launch_factor_kRf40x1(const trk::FactorJobs& jobs, int n, int cast_f32, uint32_t* status,
+                      hipStream_t st);
+int launch_factor_kRf40x2(const trk::FactorJobs& jobs, int n, int cast_f32, uint32_t* status,
+                      hipStream_t st);
 
 int launch_factor_group(int var, const trk::FactorJobs& jobs, int n, int cast_f32,
                         uint32_t* status, hipStream_t st) {
@@ -52,6 +56,8 @@ int launch_factor_group(int var, const trk::FactorJobs& jobs, int n, int cast_f3
     case kGlb64: return launch_factor_kGlb64(jobs, n, cast_f32, status, st);
     case kRf24x1: return launch_factor_kRf24x1(jobs, n, cast_f32, status, st);
     case kRf24x2: return launch_factor_kRf24x2(jobs, n, cast_f32, status, st);
+    case kRf40x1: return launch_factor_kRf40x1(jobs, n, cast_f32, status, st);
+    case kRf40x2: return launch_factor_kRf40x2(jobs, n, cast_f32, status, st);
     default: return TR_EINVAL;
   }
 }

@@ -7,7 +7,7 @@
 // constant (the column loops are instantiated per step), so nothing is
 // indexed dynamically.  Workgroup sums go through one LDS tile of per-thread
 // partials read back by 256/SM lanes per value and finished with DPP.
-// Supports s <= SM (16, 24, 32 or 48), I <= 256 R (mu <= MU).  The code is
+// Supports s <= SM (16, 24, 32, 40 or 48), I <= 256 R (mu <= MU).  The code is
 // straight-line per step, so a smaller SM also means fewer instructions to
 // fetch: a call after a large sweep fetches them from beyond the L2.
 #pragma once
@@ -288,7 +288,7 @@ k_factor_rf(FactorJobs jobs, int cast_f32, uint32_t* __restrict__ status) {
   // ---- 3. one-sided Jacobi on the columns of X.  SM == 16: wave 0 alone
   //         (no barrier between steps: one wave's LDS accesses complete in
   //         order), pair g on lanes 8g .. 8g + 7.  SM == 32: all four waves,
-  //         pair g on DPP row g / 4 of wave g % 4.  SM == 24 and 48: all four
+  //         pair g on DPP row g / 4 of wave g % 4.  SM == 24, 40, 48: all four
   //         waves, 8 lanes per pair, pair g on lanes 8 (g / 4) .. + 7 of wave
   //         g % 4.  Each lane holds RU
   //         consecutive rows of the pair's two columns.  Column norms are

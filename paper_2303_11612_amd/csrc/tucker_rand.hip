@@ -737,6 +737,8 @@ inline int factor_rf_variant(int64_t I, int64_t s, int64_t mu) {
   if (s <= 24 && mu <= 16) return kRf24x2;
   if (s <= 32 && r1) return kRf32x1;
   if (s <= 32 && mu <= 16) return kRf32x2;
+  if (s <= 40 && r1) return kRf40x1;
+  if (s <= 40 && mu <= 32) return kRf40x2;
   if (r1) return kRf48x1;
   return mu <= 32 ? kRf48x2 : -1;
 }
@@ -771,7 +773,8 @@ struct RfBounds {
 };
 constexpr RfBounds kRfBounds[] = {
     {kRf16x1, 16, 1, 16}, {kRf16x2, 16, 2, 16}, {kRf24x1, 24, 1, 24}, {kRf24x2, 24, 2, 16},
-    {kRf32x1, 32, 1, 32}, {kRf32x2, 32, 2, 16}, {kRf48x1, 48, 1, 48}, {kRf48x2, 48, 2, 32}};
+    {kRf32x1, 32, 1, 32}, {kRf32x2, 32, 2, 16}, {kRf40x1, 40, 1, 40}, {kRf40x2, 40, 2, 32},
+    {kRf48x1, 48, 1, 48}, {kRf48x2, 48, 2, 32}};
 
 inline bool is_rf_variant(int var) {
   for (const RfBounds& b : kRfBounds)

@@ -172,7 +172,8 @@ def factor_variant(request, monkeypatch):
                                     (1, 1, 1), (33, 1, 1), (96, 64, 40), (256, 16, 16),
                                     (300, 16, 8), (256, 32, 32), (512, 32, 16), (400, 30, 20),
                                     (257, 17, 16), (2, 2, 1), (40, 31, 3), (256, 24, 24),
-                                    (130, 21, 17), (400, 24, 16), (512, 17, 3)])
+                                    (130, 21, 17), (400, 24, 16), (512, 17, 3), (200, 36, 36),
+                                    (300, 33, 20), (256, 40, 40)])
 def test_factor_matches_svd(I, s, mu, factor_variant):
     C = _graded(I, s, I + s)
     Q, sig = tr.tucker_rand_factor(tr.to_device(C), mu)
