@@ -152,6 +152,33 @@ def test_power_products_match_oracle(dtype, q):
     assert np.linalg.norm(C - want) <= 1e-12 * np.linalg.norm(want)
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("s", [16, 17, 32])
+def test_power_products_wide_sketch(dtype, s):
+    """Sketch widths past one 16-column group, rows up to 128 (eight row
+    chunks) and a ragged last column tile, plain and column-weighted."""
+    shape = (128, 45, 21)
+    A = _rand_tensor(shape, dtype, 11)
+    X = tr.to_device(A)
+    for n, L, I, R in _views(shape):
+        if s > I:
+            continue
+        G = oracle.gaussian_matrix(I, s, n, 6)
+        M = oracle.unfold(A.astype(np.float64), n)
+        C = _np(tr.tucker_rand_power(X, L, I, R, tr.to_device(G), 1))
+        want = oracle.power_sketch(M, G, 1)
+        assert np.linalg.norm(C - want) <= 1e-12 * np.linalg.norm(want), n
+    I, T = 113, 1001
+    Cp = _rand_tensor((I, T), dtype, 12)
+    d = np.random.default_rng(2).random(T) + 0.5
+    G = oracle.gaussian_matrix(I, s, 0, 3)
+    C = _np(tr.tucker_rand_power(tr.to_device(Cp), 1, I, T, tr.to_device(G), 2,
+                                 torch.tensor(d, device=DEV)))
+    Ms = Cp.astype(np.float64) * np.sqrt(d)[None, :]
+    want = oracle.power_sketch(Ms, G, 2)
+    assert np.linalg.norm(C - want) <= 1e-12 * np.linalg.norm(want)
+
+
 def _graded(I, s, seed, decay=0.6):
     rng = np.random.default_rng(seed)
     U = np.linalg.qr(rng.standard_normal((I, s)))[0]
