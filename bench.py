@@ -200,7 +200,7 @@ def bench_decomp(args):
         # column norms: read the tensor, write J_1 float64 norms
         "colnorms": (dims[0] * J1 * elem + 8 * J1, "k_colnorms_l1<float, true>"),
         # shrink A x_1 Q_1^T: read the tensor, write mu_1 * J_1 float64 entries
-        "ttm": (dims[0] * J1 * elem + 8 * ranks[0] * J1, "k_ttm1_mfma<float, 1, 5, false>"),
+        "ttm": (dims[0] * J1 * elem + 8 * ranks[0] * J1, "k_ttm1_mfma<float, 1, 5, false, 8>"),
     }
     kern = {}
     for cls, (nbytes, kname) in sweeps.items():

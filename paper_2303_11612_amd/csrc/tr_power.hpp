@@ -221,8 +221,8 @@ k_pw_y(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
 // aligned), k < kout, written as Y[k + kout j] in float64.  Q^T is staged once
 // per block in LDS as rows of 16 NKT (zero beyond `width`) and zero rows up
 // to a whole number of batches, so rows beyond I contribute exactly 0 and no
-// product needs a mask.  Blocks loop over tiles of 16 columns, one tile per
-// wave at a time.  A 16-row step gives each lane group g rows 4g .. 4g + 3 of
+// product needs a mask.  Blocks of WAVES waves loop over tiles of 16 columns,
+// one tile per wave at a time.  A 16-row step gives each lane group g rows 4g .. 4g + 3 of
 // its column as one 16-byte vector load (a group beyond the column reads the
 // last group again; a column beyond R reads column R - 1, and its outputs are
 // not stored).  Work items are (tile, B steps); the loads of the next item
@@ -256,8 +256,8 @@ __device__ __forceinline__ void ttm1_load(const Tin* __restrict__ col, int64_t L
   }
 }
 
-template <typename Tin, int NKT, int B, bool STR = false>
-__global__ void __launch_bounds__(kPwWaves * kWave)
+template <typename Tin, int NKT, int B, bool STR = false, int WAVES = kPwWaves>
+__global__ void __launch_bounds__(WAVES * kWave)
 k_ttm1_mfma(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
             const double* __restrict__ Qt, int width, int kout, double* __restrict__ Y) {
   constexpr int SP = 16 * NKT;
@@ -265,7 +265,7 @@ k_ttm1_mfma(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
   const int64_t nsteps = (I + 15) / 16;
   const int64_t nitem = (nsteps + B - 1) / B;  // items per tile
   const int64_t ipad = nitem * B * 16;
-  for (int64_t e = threadIdx.x; e < ipad * SP; e += kPwWaves * kWave) {
+  for (int64_t e = threadIdx.x; e < ipad * SP; e += WAVES * kWave) {
     const int64_t i = e / SP;
     const int k = (int)(e - i * SP);
     qs[e] = (i < I && k < width) ? Qt[(i < I ? i : 0) * width + (k < width ? k : 0)] : 0.0;
@@ -274,8 +274,8 @@ k_ttm1_mfma(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int h = lane & 15, g = lane >> 4;
   const int64_t ntile = (R + 15) / 16;
-  const int64_t stride = (int64_t)gridDim.x * kPwWaves;
-  int64_t tile = (int64_t)blockIdx.x * kPwWaves + wid, s0 = 0;
+  const int64_t stride = (int64_t)gridDim.x * WAVES;
+  int64_t tile = (int64_t)blockIdx.x * WAVES + wid, s0 = 0;
   if (tile >= ntile) return;
   auto colp = [&](int64_t tl) {
     const int64_t j0 = tl * 16 + h;

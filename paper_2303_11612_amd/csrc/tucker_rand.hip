@@ -434,20 +434,36 @@ inline int ttm1_batch(int64_t I) {
   return best;
 }
 
+constexpr int kTtm1Waves = 8;
+
 template <typename Tin, int NKT, int B, bool STR>
 void ttm1_mfma_k(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Qt, int width,
                  int kout, double* Y, hipStream_t st) {
+  // eight waves share one Q^T tile: the LDS allows at most three tiles per
+  // compute unit, and twice the waves keep twice the loads in flight
+  constexpr int kW = kTtm1Waves;
   const size_t lds = 8 * (size_t)(cdiv(cdiv(I, 16), B) * B * 16) * 16 * NKT;
   if (lds > 65536)
-    (void)hipFuncSetAttribute((const void*)&trk::k_ttm1_mfma<Tin, NKT, B, STR>,
+    (void)hipFuncSetAttribute((const void*)&trk::k_ttm1_mfma<Tin, NKT, B, STR, kW>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   const int64_t ntile = cdiv(R, 16);
   // persistent blocks: as many as fit three to a compute unit (by the Q^T
   // tile in LDS), capped by the tiles there are
-  const int64_t per_cu = lds <= 53248 ? 3 : (lds <= 81920 ? 2 : 1);
-  const int64_t nblk = std::max<int64_t>(1, std::min<int64_t>(256 * per_cu, cdiv(ntile, trk::kPwWaves)));
-  hipLaunchKernelGGL((trk::k_ttm1_mfma<Tin, NKT, B, STR>), dim3((unsigned)nblk),
-                     dim3(trk::kPwWaves * trk::kWave), lds, st, X, L, I, R, Qt, width, kout, Y);
+  // and by the registers (a block that is not resident from the start would
+  // run its share of tiles after the others)
+  static const int64_t reg_cu = [] {
+    hipFuncAttributes fa{};
+    if (hipFuncGetAttributes(&fa, (const void*)&trk::k_ttm1_mfma<Tin, NKT, B, STR, kW>) !=
+            hipSuccess ||
+        fa.numRegs <= 0)
+      return (int64_t)1;
+    const int64_t per_simd = 512 / (8 * cdiv(fa.numRegs, 8));
+    return std::max<int64_t>(1, 4 * per_simd / kW);
+  }();
+  const int64_t per_cu = std::min<int64_t>(reg_cu, lds <= 53248 ? 3 : (lds <= 81920 ? 2 : 1));
+  const int64_t nblk = std::max<int64_t>(1, std::min<int64_t>(256 * per_cu, cdiv(ntile, kW)));
+  hipLaunchKernelGGL((trk::k_ttm1_mfma<Tin, NKT, B, STR, kW>), dim3((unsigned)nblk),
+                     dim3(kW * trk::kWave), lds, st, X, L, I, R, Qt, width, kout, Y);
 }
 
 template <typename Tin, int NKT, bool STR>
