@@ -506,15 +506,23 @@ void ttm_w(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Qt, int 
            const double* colscale, double* Y, double* split, hipStream_t st) {
   const int64_t J = L * R;
   const dim3 grid((unsigned)cdiv(J, kNT));
-  const int64_t ns = split ? ttm_splits(J, I) : 1;
+  const int64_t ns = ttm_splits(J, I);
   if (ns > 1 && MU <= 24) {
-    // segments combined inside the workgroup: one launch, no partials
-    constexpr int S = 16;
-    hipLaunchKernelGGL((trk::k_ttm_seg<Tin, MU, S>), dim3((unsigned)cdiv(J, kNT / S)),
-                       dim3(kNT), 0, st, X, L, I, R, Qt, kout, colscale, Y);
+    // segments combined inside the workgroup: one launch, no partials; the
+    // fewer the columns, the more (and shorter) segments per column, so that
+    // a view of a few hundred columns still spreads over the chip
+    if (J < 1024 && I >= 256)
+      hipLaunchKernelGGL((trk::k_ttm_seg<Tin, MU, 64>), dim3((unsigned)cdiv(J, kNT / 64)),
+                         dim3(kNT), 0, st, X, L, I, R, Qt, kout, colscale, Y);
+    else if (J < 8192 && I >= 128)
+      hipLaunchKernelGGL((trk::k_ttm_seg<Tin, MU, 32>), dim3((unsigned)cdiv(J, kNT / 32)),
+                         dim3(kNT), 0, st, X, L, I, R, Qt, kout, colscale, Y);
+    else
+      hipLaunchKernelGGL((trk::k_ttm_seg<Tin, MU, 16>), dim3((unsigned)cdiv(J, kNT / 16)),
+                         dim3(kNT), 0, st, X, L, I, R, Qt, kout, colscale, Y);
     return;
   }
-  if (ns > 1) {
+  if (ns > 1 && split) {
     const int64_t ich = cdiv(I, ns);
     const int64_t nsu = cdiv(I, ich);
     hipLaunchKernelGGL((trk::k_ttm_split<Tin, MU>), dim3((unsigned)cdiv(J, kNT), (unsigned)nsu),
