@@ -91,8 +91,8 @@ def _blas_threads():
 def main():
     args = _parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is a design note, not an implemented path.",
+        print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); "
+              "sharding over several GPUs is not implemented.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -49,7 +49,7 @@ typedef enum {
   TR_EINVAL = 1,   /* invalid argument (shape, rank, null pointer, ...)      */
   TR_ENOMEM = 2,   /* workspace smaller than tucker_rand_workspace_size()    */
   TR_EDEVICE = 3,  /* a HIP launch or runtime call failed                    */
-  TR_ENOTSUP = 4,  /* valid request outside what this build implements      */
+  TR_ENOTSUP = 4,  /* valid request outside what this library implements    */
   TR_ENUMERIC = 5  /* reserved for numeric failures detected on the host    */
 } tr_status;
 
@@ -123,7 +123,7 @@ const char *tucker_rand_status_string(int status);
 /*
  * Bytes of device workspace needed by tucker_rand_thosvd (sthosvd == 0) or
  * tucker_rand_sthosvd (sthosvd != 0) for these parameters and input dtype.
- * Validates the parameters exactly as the driver does.
+ * Validates the parameters exactly as the decomposition calls do.
  */
 int tucker_rand_workspace_size(const tr_params *p, int dtype, int sthosvd,
                                size_t *bytes);
@@ -267,7 +267,7 @@ int tucker_rand_ttm(int in_dtype, const void *X, int64_t L, int64_t I,
 
 /* ---------------------------------------------------------------------------
  * Kernel timing (benchmarking aid).  A timer owns a pool of HIP events; when it
- * is passed in tr_diag.timer, the drivers record an event pair on the launch
+ * is passed in tr_diag.timer, the decomposition calls record an event pair on the launch
  * stream around every kernel of the selected classes.  Read it after
  * synchronising the stream.
  * ------------------------------------------------------------------------- */

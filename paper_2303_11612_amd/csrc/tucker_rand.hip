@@ -1130,7 +1130,7 @@ const char* tucker_rand_status_string(int status) {
     case TR_EINVAL: return "invalid argument";
     case TR_ENOMEM: return "workspace too small";
     case TR_EDEVICE: return "HIP device error";
-    case TR_ENOTSUP: return "not supported by this build";
+    case TR_ENOTSUP: return "not supported by this library";
     case TR_ENUMERIC: return "numeric failure";
     default: return "unknown status";
   }
