@@ -58,6 +58,63 @@ k_gaussian(double* __restrict__ G, double* __restrict__ Gt, int64_t I, int64_t s
   }
 }
 
+// Every mode's Gaussian test matrix in one launch (the decompositions draw
+// all of them up front): mode m takes threads [t0, t0 + cdiv(I s, 4)) for its
+// entries, drawn exactly as k_gaussian draws them for that mode, then
+// I (ldgt - s) threads that zero the padding columns of its row-major copy;
+// threads 0 .. nzero - 1 also clear zero[0 .. nzero - 1].
+struct GaussMode {
+  double* G;
+  double* Gt;
+  int64_t I, s, ldgt, t0;
+};
+struct GaussModes {
+  GaussMode m[8];
+  int n;
+  int nzero;
+  unsigned long long* zero;
+};
+
+static __global__ void __launch_bounds__(kNT)
+k_gaussian_modes(GaussModes gm, uint64_t seed) {
+  const int64_t f = (int64_t)blockIdx.x * kNT + threadIdx.x;
+  if (gm.zero && f < gm.nzero) gm.zero[f] = 0ull;
+  int md = -1;
+  for (int q = 0; q < gm.n; ++q)
+    if (f >= gm.m[q].t0) md = q;
+  if (md < 0) return;
+  const GaussMode M = gm.m[md];
+  const int64_t total = M.I * M.s, ng = (total + 3) / 4;
+  const int64_t b = f - M.t0;
+  if (b >= ng) {
+    const int64_t pw = M.ldgt - M.s, p = b - ng;
+    if (pw > 0 && p < M.I * pw) {
+      const int64_t i = p / pw;
+      M.Gt[i * M.ldgt + M.s + (p - i * pw)] = 0.0;
+    }
+    return;
+  }
+  const U64x4 r = philox4x64_10((uint64_t)b, (uint64_t)md, kTagGauss, 0, seed, 0);
+#pragma unroll
+  for (int pair = 0; pair < 2; ++pair) {
+    const uint64_t ra = r.w[2 * pair], rb = r.w[2 * pair + 1];
+    const double u1 = (double)((ra >> 11) + 1) * 0x1p-53;
+    const double u2 = (double)(rb >> 11) * 0x1p-53;
+    const double rho = sqrt(-2.0 * log(u1));
+    const double th = kTwoPi * u2;
+    const double z[2] = {rho * cos(th), rho * sin(th)};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t e = 4 * b + 2 * pair + h;
+      if (e < total) {
+        M.G[e] = z[h];
+        const int64_t i = e % M.I, c = e / M.I;
+        M.Gt[i * M.ldgt + c] = z[h];
+      }
+    }
+  }
+}
+
 static __global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < n) p[e] = v;

@@ -146,7 +146,7 @@ struct Plan {
   int64_t dims[TR_MAX_ORDER];
   ModePlan m[TR_MAX_ORDER];
   // workspace offsets (bytes)
-  size_t oG, oY, oYt, oZ, oPart, oNorms, oW, oCdf, oBsum, oIdx, oScale, oScale2, oCp,
+  size_t oY, oYt, oZ, oPart, oNorms, oW, oCdf, oBsum, oIdx, oScale, oScale2, oCp,
       oMax, oSig, oX0, oX1, oCore, oSplit, total;
   // low-precision power steps
   int prec = TR_PREC_NATIVE;
@@ -158,6 +158,9 @@ struct Plan {
   // T-HOSVD, low precision, q > 1: every mode's current orthonormal iterate,
   // so that the modes advance one power step at a time together
   size_t oGn[TR_MAX_ORDER] = {};
+  // every mode's Gaussian G_n (I x s) and its zero-padded row-major copy
+  // (I x sw), drawn in one launch before the first mode
+  size_t oGs[TR_MAX_ORDER] = {}, oYts[TR_MAX_ORDER] = {};
 };
 
 // Validates and fills the plan; returns TR_OK or an error code.
@@ -272,7 +275,6 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
     off += align_up(std::max<size_t>(bytes, 8));
     return o;
   };
-  P->oG = take(8 * maxIs);
   P->oY = take(8 * maxIs);
   P->oYt = take(8 * maxIs);
   // the float64 power steps' W and partial sketches (unused in low precision)
@@ -286,7 +288,11 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
   P->oScale = take(8 * maxT);
   P->oScale2 = take(8 * maxT);
   P->oCp = take(lp ? 8 : 8 * maxCp);
-  P->oMax = take(8);
+  P->oMax = take(8 * (size_t)N);  // one running maximum per mode
+  for (int n = 0; n < N; ++n) {
+    P->oGs[n] = take(8 * (size_t)(P->m[n].I * P->m[n].s));
+    P->oYts[n] = take(8 * (size_t)(P->m[n].I * P->m[n].sw));
+  }
   P->oSig = take(8 * (size_t)maxS);
   for (int n = 0; n < N; ++n) {
     P->oQ[n] = take(8 * (size_t)(P->m[n].I * P->m[n].mu));
@@ -868,6 +874,27 @@ int copy_d2d(void* dst, const void* src, size_t bytes, hipStream_t st) {
              : TR_EDEVICE;
 }
 
+// Every mode's G_n and its padded row-major copy into the plan's buffers,
+// and every mode's running maximum of the column norms cleared, in one launch.
+int launch_gaussian_modes(const Plan& P, void* ws, hipStream_t st) {
+  static_assert(TR_MAX_ORDER <= 8, "GaussModes holds at most 8 modes");
+  trk::GaussModes gm{};
+  int64_t t = 0;
+  for (int n = 0; n < P.N; ++n) {
+    const ModePlan& M = P.m[n];
+    gm.m[n] = trk::GaussMode{at<double>(ws, P.oGs[n]), at<double>(ws, P.oYts[n]), M.I, M.s,
+                             M.sw, t};
+    t += cdiv(M.I * M.s, 4) + M.I * (M.sw - M.s);
+  }
+  gm.n = P.N;
+  gm.nzero = P.N;
+  gm.zero = at<unsigned long long>(ws, P.oMax);
+  t = std::max<int64_t>(t, P.N);
+  hipLaunchKernelGGL(trk::k_gaussian_modes, dim3((unsigned)cdiv(t, kNT)), dim3(kNT), 0, st, gm,
+                     P.seed);
+  return check_launch();
+}
+
 // Range finder of mode n on tensor X (3-D view from the plan): fills Q64 / Qt
 // of the mode in the workspace and the caller's Q (cast to dtype).
 // Sketch of mode n of tensor X (3-D view from the plan): C_n = (M M^T)^q G_n
@@ -877,18 +904,13 @@ int range_sketch(const Plan& P, int n, const void* X, void* ws, const tr_diag* d
   const ModePlan& M = P.m[n];
   tr_timer* tm = diag ? diag->timer : nullptr;
   uint32_t* status = diag ? diag->status : nullptr;
-  double* G = at<double>(ws, P.oG);
-  double* Yt = at<double>(ws, P.oYt);
+  // G_n, its row-major copy and the cleared running maximum of the column
+  // norms come from launch_gaussian_modes, earlier on the stream
+  double* G = at<double>(ws, P.oGs[n]);
+  double* Yt = at<double>(ws, P.oYts[n]);
   double* Z = at<double>(ws, P.oZ);
   double* part = at<double>(ws, P.oPart);
-  // the running maximum of the column norms starts at 0; the Gaussian
-  // launch, just before them on the stream, clears it
   const bool norms_needed = M.sampled && P.prob == TR_PROB_NEARLY_OPTIMAL;
-  {
-    TimeScope ts(tm, TR_KC_GAUSSIAN, n, st);
-    TR_TRY(launch_gaussian(G, Yt, M.I, M.s, M.sw, n, P.seed, st,
-                           norms_needed ? at<unsigned long long>(ws, P.oMax) : nullptr));
-  }
   const void* src = X;
   bool src_f64 = M.src_f64;
   int64_t L = M.L, R = M.R;
@@ -896,7 +918,7 @@ int range_sketch(const Plan& P, int n, const void* X, void* ws, const tr_diag* d
   const bool lp = P.prec != TR_PREC_NATIVE;
   if (M.sampled) {
     double* norms = at<double>(ws, P.oNorms);
-    auto* maxb = at<unsigned long long>(ws, P.oMax);
+    auto* maxb = at<unsigned long long>(ws, P.oMax) + n;
     int64_t* idx = at<int64_t>(ws, P.oIdx);
     double* scale = at<double>(ws, P.oScale);
     double* scale2 = at<double>(ws, P.oScale2);
@@ -1024,6 +1046,10 @@ int run_thosvd(const tr_params* p, int dtype, const void* A, void* const* Q, voi
     ntog += together[n] ? 1 : 0;
   }
   bool xmax_ready = false;
+  if (ntog < P.N) {
+    TimeScope ts(tm0, TR_KC_GAUSSIAN, 0, st);
+    TR_TRY(launch_gaussian_modes(P, ws, st));
+  }
   for (int n = 0; n < P.N; ++n) {
     if (together[n]) continue;
     TR_TRY(range_sketch(P, n, A, ws, diag, !xmax_ready, at<double>(ws, P.oYn[n]), st));
@@ -1106,6 +1132,10 @@ int run_sthosvd(const tr_params* p, int dtype, const void* A, void* const* Q, vo
   const void* cur = A;
   bool cur_f64 = dtype == TR_F64;
   tr_timer* tm = diag ? diag->timer : nullptr;
+  {
+    TimeScope ts(tm, TR_KC_GAUSSIAN, 0, st);
+    TR_TRY(launch_gaussian_modes(P, ws, st));
+  }
   for (int n = 0; n < P.N; ++n) {
     TR_TRY(range_finder(P, n, cur, ws, Q[n], diag, true, st));
     const ModePlan& M = P.m[n];
