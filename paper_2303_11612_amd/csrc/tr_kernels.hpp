@@ -24,18 +24,13 @@ namespace trk {
 // ---------------------------------------------------------------------------
 // K1  Gaussian test matrix (Alg. 1 step 2 / Alg. 4 step 5).  One thread per
 // Philox block of four outputs; Box-Muller on words (0,1) and (2,3).  Writes
-// G (I x s column-major) and Gt (row-major copy, row i = G(i, :)).  `zero`,
-// if given, is one word cleared on the way (the running maximum of the column
-// norms that the next kernel on the stream accumulates), which saves a launch.
+// G (I x s column-major) and Gt (row-major copy, row i = G(i, :), stride
+// ldgt).
 // ---------------------------------------------------------------------------
-static __global__ void __launch_bounds__(kNT)
-k_gaussian(double* __restrict__ G, double* __restrict__ Gt, int64_t I, int64_t s,
-           int64_t ldgt, uint64_t mode, uint64_t seed, unsigned long long* __restrict__ zero) {
-  const int64_t total = I * s;
-  const int64_t b = (int64_t)blockIdx.x * kNT + threadIdx.x;
-  if (zero && b == 0) *zero = 0ull;
-  if (4 * b >= total) return;
-  const U64x4 r = philox4x64_10((uint64_t)b, mode, kTagGauss, 0, seed, 0);
+// The four normals of Philox block b of a mode: entries 4b .. 4b + 3 of G.
+__device__ __forceinline__ void gauss_block(uint64_t b, uint64_t mode, uint64_t seed,
+                                            double (&z)[4]) {
+  const U64x4 r = philox4x64_10(b, mode, kTagGauss, 0, seed, 0);
 #pragma unroll
   for (int pair = 0; pair < 2; ++pair) {
     const uint64_t ra = r.w[2 * pair], rb = r.w[2 * pair + 1];
@@ -43,16 +38,27 @@ k_gaussian(double* __restrict__ G, double* __restrict__ Gt, int64_t I, int64_t s
     const double u2 = (double)(rb >> 11) * 0x1p-53;
     const double rho = sqrt(-2.0 * log(u1));
     const double th = kTwoPi * u2;
-    const double z[2] = {rho * cos(th), rho * sin(th)};
+    z[2 * pair] = rho * cos(th);
+    z[2 * pair + 1] = rho * sin(th);
+  }
+}
+
+static __global__ void __launch_bounds__(kNT)
+k_gaussian(double* __restrict__ G, double* __restrict__ Gt, int64_t I, int64_t s,
+           int64_t ldgt, uint64_t mode, uint64_t seed) {
+  const int64_t total = I * s;
+  const int64_t b = (int64_t)blockIdx.x * kNT + threadIdx.x;
+  if (4 * b >= total) return;
+  double z[4];
+  gauss_block((uint64_t)b, mode, seed, z);
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int64_t e = 4 * b + 2 * pair + h;
-      if (e < total) {
-        G[e] = z[h];
-        if (Gt) {
-          const int64_t i = e % I, c = e / I;
-          Gt[i * ldgt + c] = z[h];
-        }
+  for (int q = 0; q < 4; ++q) {
+    const int64_t e = 4 * b + q;
+    if (e < total) {
+      G[e] = z[q];
+      if (Gt) {
+        const int64_t i = e % I, c = e / I;
+        Gt[i * ldgt + c] = z[q];
       }
     }
   }
@@ -94,23 +100,15 @@ k_gaussian_modes(GaussModes gm, uint64_t seed) {
     }
     return;
   }
-  const U64x4 r = philox4x64_10((uint64_t)b, (uint64_t)md, kTagGauss, 0, seed, 0);
+  double z[4];
+  gauss_block((uint64_t)b, (uint64_t)md, seed, z);
 #pragma unroll
-  for (int pair = 0; pair < 2; ++pair) {
-    const uint64_t ra = r.w[2 * pair], rb = r.w[2 * pair + 1];
-    const double u1 = (double)((ra >> 11) + 1) * 0x1p-53;
-    const double u2 = (double)(rb >> 11) * 0x1p-53;
-    const double rho = sqrt(-2.0 * log(u1));
-    const double th = kTwoPi * u2;
-    const double z[2] = {rho * cos(th), rho * sin(th)};
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int64_t e = 4 * b + 2 * pair + h;
-      if (e < total) {
-        M.G[e] = z[h];
-        const int64_t i = e % M.I, c = e / M.I;
-        M.Gt[i * M.ldgt + c] = z[h];
-      }
+  for (int q = 0; q < 4; ++q) {
+    const int64_t e = 4 * b + q;
+    if (e < total) {
+      M.G[e] = z[q];
+      const int64_t i = e % M.I, c = e / M.I;
+      M.Gt[i * M.ldgt + c] = z[q];
     }
   }
 }

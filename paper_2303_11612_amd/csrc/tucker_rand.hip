@@ -329,14 +329,14 @@ int launch_fill_f64(double* p, int64_t n, double v, hipStream_t st) {
   return check_launch();
 }
 
-// G (I x s) and its row-major copy Gt with zero padding to stride ldgt;
-// `zero` (optional) is a word set to 0 by the same launch.
+// G (I x s) and its row-major copy Gt (optional) with zero padding to stride
+// ldgt.
 int launch_gaussian(double* G, double* Gt, int64_t I, int64_t s, int64_t ldgt, int mode,
-                    uint64_t seed, hipStream_t st, unsigned long long* zero = nullptr) {
+                    uint64_t seed, hipStream_t st) {
   if (Gt && ldgt > s) TR_TRY(launch_fill_f64(Gt, I * ldgt, 0.0, st));
   const int64_t blocks4 = cdiv(I * s, 4);
   hipLaunchKernelGGL(trk::k_gaussian, dim3((unsigned)cdiv(blocks4, kNT)), dim3(kNT), 0, st,
-                     G, Gt, I, s, ldgt, (uint64_t)mode, seed, zero);
+                     G, Gt, I, s, ldgt, (uint64_t)mode, seed);
   return check_launch();
 }
 
