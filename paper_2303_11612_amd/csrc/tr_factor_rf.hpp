@@ -224,7 +224,7 @@ k_factor_rf(FactorJobs jobs, int cast_f32, uint32_t* __restrict__ status) {
     for (int c0 = 0; c0 < SM; c0 += 8) {
       if (c0 + 8 > k + 1 && c0 < s) {
 #pragma unroll
-        for (int j = c0 > k ? c0 : k + 1; j < c0 + 8; ++j) {
+        for (int j = c0 > k ? c0 : k + 1; j < (c0 + 8 < SM ? c0 + 8 : SM); ++j) {
           const double w = rk[j] + inv * vec[j];
 #pragma unroll
           for (int r = 0; r < R; ++r) a[r][j] = fma(-tv[r], w, a[r][j]);
@@ -255,7 +255,7 @@ k_factor_rf(FactorJobs jobs, int cast_f32, uint32_t* __restrict__ status) {
       for (int c0 = 0; c0 < SM; c0 += 8) {
         if (c0 + 8 > k + 1 && c0 < s) {
 #pragma unroll
-          for (int i = c0 > k ? c0 : k + 1; i < c0 + 8; ++i) {
+          for (int i = c0 > k ? c0 : k + 1; i < (c0 + 8 < SM ? c0 + 8 : SM); ++i) {
             xs[i] = readlane_f64(m[i], k);
             pj = fma(xs[i], m[i], pj);
           }
@@ -271,7 +271,8 @@ k_factor_rf(FactorJobs jobs, int cast_f32, uint32_t* __restrict__ status) {
       for (int c0 = 0; c0 < SM; c0 += 8) {
         if (c0 + 8 > k + 1 && c0 < s) {
 #pragma unroll
-          for (int i = c0 > k ? c0 : k + 1; i < c0 + 8; ++i) m[i] = fma(-(inv * xs[i]), tw, m[i]);
+          for (int i = c0 > k ? c0 : k + 1; i < (c0 + 8 < SM ? c0 + 8 : SM); ++i)
+            m[i] = fma(-(inv * xs[i]), tw, m[i]);
         }
       }
       m[k] = lane == k ? beta : m[k] - tw;

@@ -200,6 +200,7 @@ def factor_variant(request, monkeypatch):
                                     (300, 16, 8), (256, 32, 32), (512, 32, 16), (400, 30, 20),
                                     (257, 17, 16), (2, 2, 1), (40, 31, 3), (256, 24, 24),
                                     (130, 21, 17), (400, 24, 16), (512, 17, 3), (200, 36, 36),
+                                    (200, 19, 16), (256, 20, 16), (400, 20, 10), (300, 18, 17),
                                     (300, 33, 20), (256, 40, 40)])
 def test_factor_matches_svd(I, s, mu, factor_variant):
     C = _graded(I, s, I + s)
