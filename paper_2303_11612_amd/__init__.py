@@ -71,6 +71,13 @@ def _stream(stream) -> c_void_p:
     return c_void_p(stream.cuda_stream)
 
 
+def _launch_stream(stream):
+    """Context in which the step wrappers allocate: the launch stream, so that
+    their fills precede the library's writes on it and a freed buffer is reused
+    only after the work queued there."""
+    return torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream())
+
+
 def _i64arr(vals):
     arr = (c_int64 * len(vals))(*[int(v) for v in vals])
     return arr
@@ -156,6 +163,17 @@ def _decompose(fn_name, A, ranks, oversample, power, prob, samples, seed, precis
         raise ValueError("A must be a device tensor")
     if not is_colmajor(A):
         raise ValueError("A must be column-major (use to_device / colmajor_empty)")
+    st = stream if stream is not None else torch.cuda.current_stream(A.device)
+    # every buffer is allocated and initialised on the launch stream, so the
+    # fills are ordered before the library's writes and the caching allocator
+    # reuses a freed buffer only after the work queued on that stream
+    with torch.cuda.stream(st):
+        return _decompose_on(fn_name, A, ranks, oversample, power, prob, samples, seed,
+                             precision, diag, timer, workspace, st, out)
+
+
+def _decompose_on(fn_name, A, ranks, oversample, power, prob, samples, seed, precision,
+                  diag, timer, workspace, stream, out):
     dims = tuple(A.shape)
     N = len(dims)
     dt = _dtype_code(A)
@@ -211,9 +229,10 @@ def _decompose(fn_name, A, ranks, oversample, power, prob, samples, seed, precis
         if timer is not None:
             dstruct.timer = timer.handle
     fn = getattr(lib(), fn_name)
+    dptr = byref(dstruct) if dstruct is not None else None
     rc = fn(byref(p), dt, c_void_p(A.data_ptr()), qptrs, c_void_p(core.data_ptr()),
-            c_void_p(workspace.data_ptr()), c_size_t(workspace.numel()),
-            byref(dstruct) if dstruct is not None else None, _stream(stream))
+            c_void_p(workspace.data_ptr()), c_size_t(workspace.numel()), dptr,
+            _stream(stream))
     check(fn_name, rc)
     return Qs, core, info
 
@@ -243,101 +262,109 @@ def _view3(X: torch.Tensor, L, I, R):
 
 def tucker_rand_gaussian(I: int, s: int, mode: int, seed: int, device="cuda", stream=None):
     """G_n (I x s, float64, column-major) from the library's Philox stream."""
-    G = colmajor_empty((I, s), torch.float64, device)
-    check("tucker_rand_gaussian",
-          lib().tucker_rand_gaussian(I, s, mode, int(seed) & ((1 << 64) - 1),
-                                     c_void_p(G.data_ptr()), _stream(stream)))
-    return G
+    with _launch_stream(stream):
+        G = colmajor_empty((I, s), torch.float64, device)
+        check("tucker_rand_gaussian",
+              lib().tucker_rand_gaussian(I, s, mode, int(seed) & ((1 << 64) - 1),
+                                         c_void_p(G.data_ptr()), _stream(stream)))
+        return G
 
 
 def tucker_rand_colnorms(X: torch.Tensor, L: int, I: int, R: int, stream=None):
     """(norms float64 [L*R], max bit pattern as int64 tensor [1])."""
-    _view3(X, L, I, R)
-    norms = torch.empty(L * R, dtype=torch.float64, device=X.device)
-    mb = torch.zeros(1, dtype=torch.int64, device=X.device)
-    check("tucker_rand_colnorms",
-          lib().tucker_rand_colnorms(_dtype_code(X), c_void_p(X.data_ptr()), L, I, R,
-                                     c_void_p(norms.data_ptr()), c_void_p(mb.data_ptr()),
-                                     _stream(stream)))
-    return norms, mb
+    with _launch_stream(stream):
+        _view3(X, L, I, R)
+        norms = torch.empty(L * R, dtype=torch.float64, device=X.device)
+        mb = torch.zeros(1, dtype=torch.int64, device=X.device)
+        check("tucker_rand_colnorms",
+              lib().tucker_rand_colnorms(_dtype_code(X), c_void_p(X.data_ptr()), L, I, R,
+                                         c_void_p(norms.data_ptr()), c_void_p(mb.data_ptr()),
+                                         _stream(stream)))
+        return norms, mb
 
 
 def tucker_rand_sample(norms: Optional[torch.Tensor], J: int, T: int, prob: str, seed: int,
                        mode: int, device="cuda", stream=None):
     """(idx int64 [T], scale float64 [T], status int32 [1])."""
-    ws = torch.empty(max(1, lib().tucker_rand_sample_workspace_size(J)), dtype=torch.uint8,
-                     device=device)
-    idx = torch.empty(T, dtype=torch.int64, device=device)
-    scale = torch.empty(T, dtype=torch.float64, device=device)
-    status = torch.zeros(1, dtype=torch.int32, device=device)
-    check("tucker_rand_sample",
-          lib().tucker_rand_sample(_ptr(norms), J, T, PROB[prob], int(seed) & ((1 << 64) - 1),
-                                   mode, c_void_p(idx.data_ptr()), c_void_p(scale.data_ptr()),
-                                   c_void_p(ws.data_ptr()), c_size_t(ws.numel()),
-                                   c_void_p(status.data_ptr()), _stream(stream)))
-    return idx, scale, status
+    with _launch_stream(stream):
+        ws = torch.empty(max(1, lib().tucker_rand_sample_workspace_size(J)), dtype=torch.uint8,
+                         device=device)
+        idx = torch.empty(T, dtype=torch.int64, device=device)
+        scale = torch.empty(T, dtype=torch.float64, device=device)
+        status = torch.zeros(1, dtype=torch.int32, device=device)
+        check("tucker_rand_sample",
+              lib().tucker_rand_sample(_ptr(norms), J, T, PROB[prob], int(seed) & ((1 << 64) - 1),
+                                       mode, c_void_p(idx.data_ptr()), c_void_p(scale.data_ptr()),
+                                       c_void_p(ws.data_ptr()), c_size_t(ws.numel()),
+                                       c_void_p(status.data_ptr()), _stream(stream)))
+        return idx, scale, status
 
 
 def tucker_rand_gather(X: torch.Tensor, L: int, I: int, R: int, idx: torch.Tensor,
                        stream=None):
     """C' = A_(n)(:, idx) without rescale, I x T column-major (X's dtype)."""
-    _view3(X, L, I, R)
-    T = idx.numel()
-    Cp = colmajor_empty((I, T), X.dtype, X.device)
-    check("tucker_rand_gather",
-          lib().tucker_rand_gather(_dtype_code(X), c_void_p(X.data_ptr()), L, I, R,
-                                   c_void_p(idx.data_ptr()), T, c_void_p(Cp.data_ptr()),
-                                   _stream(stream)))
-    return Cp
+    with _launch_stream(stream):
+        _view3(X, L, I, R)
+        T = idx.numel()
+        Cp = colmajor_empty((I, T), X.dtype, X.device)
+        check("tucker_rand_gather",
+              lib().tucker_rand_gather(_dtype_code(X), c_void_p(X.data_ptr()), L, I, R,
+                                       c_void_p(idx.data_ptr()), T, c_void_p(Cp.data_ptr()),
+                                       _stream(stream)))
+        return Cp
 
 
 def tucker_rand_power(X: torch.Tensor, L: int, I: int, R: int, G: torch.Tensor, q: int,
                       colweight: Optional[torch.Tensor] = None, stream=None):
     """C = (M D M^T)^q G for the mode-n unfolding M of the L x I x R view of X."""
-    _view3(X, L, I, R)
-    if not is_colmajor(G) or G.dtype != torch.float64:
-        raise ValueError("G must be column-major float64")
-    s = G.shape[1]
-    C = colmajor_empty((I, s), torch.float64, X.device)
-    wsn = lib().tucker_rand_power_workspace_size(_dtype_code(X), L, I, R, s)
-    ws = torch.empty(max(1, wsn), dtype=torch.uint8, device=X.device)
-    check("tucker_rand_power",
-          lib().tucker_rand_power(_dtype_code(X), c_void_p(X.data_ptr()), L, I, R,
-                                  _ptr(colweight), q, c_void_p(G.data_ptr()), s,
-                                  c_void_p(C.data_ptr()), c_void_p(ws.data_ptr()),
-                                  c_size_t(ws.numel()), _stream(stream)))
-    return C
+    with _launch_stream(stream):
+        _view3(X, L, I, R)
+        if not is_colmajor(G) or G.dtype != torch.float64:
+            raise ValueError("G must be column-major float64")
+        s = G.shape[1]
+        C = colmajor_empty((I, s), torch.float64, X.device)
+        wsn = lib().tucker_rand_power_workspace_size(_dtype_code(X), L, I, R, s)
+        ws = torch.empty(max(1, wsn), dtype=torch.uint8, device=X.device)
+        check("tucker_rand_power",
+              lib().tucker_rand_power(_dtype_code(X), c_void_p(X.data_ptr()), L, I, R,
+                                      _ptr(colweight), q, c_void_p(G.data_ptr()), s,
+                                      c_void_p(C.data_ptr()), c_void_p(ws.data_ptr()),
+                                      c_size_t(ws.numel()), _stream(stream)))
+        return C
 
 
 def tucker_rand_factor(C: torch.Tensor, mu: int, stream=None):
     """(Q I x mu float64 column-major, sigma [s]) from a sketch C (I x s float64)."""
-    if not is_colmajor(C) or C.dtype != torch.float64:
-        raise ValueError("C must be column-major float64")
-    I, s = C.shape
-    Q = colmajor_empty((I, mu), torch.float64, C.device)
-    sig = torch.empty(s, dtype=torch.float64, device=C.device)
-    wsn = lib().tucker_rand_factor_workspace_size(I, s, mu)
-    ws = torch.empty(max(1, wsn), dtype=torch.uint8, device=C.device)
-    check("tucker_rand_factor",
-          lib().tucker_rand_factor(c_void_p(C.data_ptr()), I, s, mu, c_void_p(Q.data_ptr()),
-                                   c_void_p(sig.data_ptr()), c_void_p(ws.data_ptr()),
-                                   c_size_t(ws.numel()), _stream(stream)))
-    return Q, sig
+    with _launch_stream(stream):
+        if not is_colmajor(C) or C.dtype != torch.float64:
+            raise ValueError("C must be column-major float64")
+        I, s = C.shape
+        Q = colmajor_empty((I, mu), torch.float64, C.device)
+        sig = torch.empty(s, dtype=torch.float64, device=C.device)
+        wsn = lib().tucker_rand_factor_workspace_size(I, s, mu)
+        ws = torch.empty(max(1, wsn), dtype=torch.uint8, device=C.device)
+        check("tucker_rand_factor",
+              lib().tucker_rand_factor(c_void_p(C.data_ptr()), I, s, mu, c_void_p(Q.data_ptr()),
+                                       c_void_p(sig.data_ptr()), c_void_p(ws.data_ptr()),
+                                       c_size_t(ws.numel()), _stream(stream)))
+        return Q, sig
 
 
 def tucker_rand_ttm(X: torch.Tensor, L: int, I: int, R: int, Q: torch.Tensor,
                     out_dtype=torch.float64, stream=None):
     """Y = X x_n Q^T as a flat column-major L x mu x R buffer (out_dtype)."""
-    _view3(X, L, I, R)
-    if not is_colmajor(Q) or Q.dtype != torch.float64:
-        raise ValueError("Q must be column-major float64")
-    mu = Q.shape[1]
-    wsn = lib().tucker_rand_ttm_workspace_size(L, I, R, mu)
-    ws = torch.empty(max(1, wsn), dtype=torch.uint8, device=X.device)
-    Y = torch.empty(L * mu * R, dtype=out_dtype, device=X.device)
-    check("tucker_rand_ttm",
-          lib().tucker_rand_ttm(_dtype_code(X), c_void_p(X.data_ptr()), L, I, R,
-                                c_void_p(Q.data_ptr()), mu, _DT[out_dtype],
-                                c_void_p(Y.data_ptr()), c_void_p(ws.data_ptr()),
-                                c_size_t(ws.numel()), _stream(stream)))
-    return Y
+    with _launch_stream(stream):
+        _view3(X, L, I, R)
+        if not is_colmajor(Q) or Q.dtype != torch.float64:
+            raise ValueError("Q must be column-major float64")
+        mu = Q.shape[1]
+        wsn = lib().tucker_rand_ttm_workspace_size(L, I, R, mu)
+        ws = torch.empty(max(1, wsn), dtype=torch.uint8, device=X.device)
+        Y = torch.empty(L * mu * R, dtype=out_dtype, device=X.device)
+        check("tucker_rand_ttm",
+              lib().tucker_rand_ttm(_dtype_code(X), c_void_p(X.data_ptr()), L, I, R,
+                                    c_void_p(Q.data_ptr()), mu, _DT[out_dtype],
+                                    c_void_p(Y.data_ptr()), c_void_p(ws.data_ptr()),
+                                    c_size_t(ws.numel()), _stream(stream)))
+        return Y
+
