@@ -22,8 +22,9 @@
  *    column j of the mode-n unfolding A_(n) is j = l + L*r (0-based).
  *  - Matrices are column-major with leading dimension equal to their row count.
  *  - "device" pointers are HIP device memory owned by the caller; the library
- *    never allocates or frees device memory and keeps no global state.  "host"
- *    pointers are read during the call only.
+ *    never allocates or frees device memory.  Its only global state is the
+ *    fixed scratch array of tucker_rand_sthosvd_noalloc and the per-device
+ *    address of that array.  "host" pointers are read during the call only.
  *  - Calls are asynchronous on `stream` (a hipStream_t; NULL = default stream).
  *    Argument errors are detected on the host before anything is launched and
  *    returned synchronously; nothing is written in that case.  Numeric trouble
@@ -155,6 +156,29 @@ int tucker_rand_thosvd(const tr_params *p, int dtype, const void *A,
 int tucker_rand_sthosvd(const tr_params *p, int dtype, const void *A,
                         void *const *Q, void *core, void *workspace,
                         size_t workspace_bytes, const tr_diag *diag, void *stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): randomized
+ * ST-HOSVD exactly as tucker_rand_sthosvd (same kernels, same results), with
+ * the workspace taken from a fixed device array of TR_NOALLOC_SCRATCH_BYTES
+ * inside the library instead of a caller buffer.  Nothing is allocated or
+ * freed during the call.
+ *   - Each GPU that runs it holds its own copy of the array until the process
+ *     ends; the first call on a device looks up its address (with that device
+ *     current).  `stream` must belong to the current device (TR_EINVAL).
+ *   - Problems whose workspace (tucker_rand_workspace_size(p, dtype, 1, ...))
+ *     exceeds TR_NOALLOC_SCRATCH_BYTES return TR_ENOMEM before anything runs.
+ *   - Every call on one GPU shares that GPU's array: calls that overlap in time
+ *     on one GPU (different streams, threads) race and give wrong results.
+ *     Nothing in the array needs to start at zero; its contents after a call
+ *     are unspecified.
+ * A, Q, core, diag: as tucker_rand_sthosvd (caller-allocated).
+ */
+#define TR_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int tucker_rand_sthosvd_noalloc(const tr_params *p, int dtype, const void *A,
+                                void *const *Q, void *core,
+                                const tr_diag *diag, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Individual steps of the per-mode range finder.

@@ -23,6 +23,7 @@ from ._abi import KC, PREC, PROB, TR_F32, TR_F64, check, lib
 __all__ = [
     "colmajor_empty", "to_device", "is_colmajor", "Timer",
     "tucker_rand_workspace_size", "tucker_rand_thosvd", "tucker_rand_sthosvd",
+    "tucker_rand_sthosvd_noalloc",
     "tucker_rand_gaussian", "tucker_rand_colnorms", "tucker_rand_sample",
     "tucker_rand_gather", "tucker_rand_power", "tucker_rand_factor",
     "tucker_rand_ttm", "tucker_rand_status_string",
@@ -177,12 +178,15 @@ def _decompose_on(fn_name, A, ranks, oversample, power, prob, samples, seed, pre
     dims = tuple(A.shape)
     N = len(dims)
     dt = _dtype_code(A)
-    sthosvd = fn_name == "tucker_rand_sthosvd"
+    noalloc = fn_name == "tucker_rand_sthosvd_noalloc"
+    sthosvd = fn_name != "tucker_rand_thosvd"
     p, keep = _params(dims, ranks, oversample, power, prob, samples, seed, precision)
     need = c_size_t(0)
     check("tucker_rand_workspace_size",
           lib().tucker_rand_workspace_size(byref(p), dt, int(sthosvd), byref(need)))
-    if workspace is None or workspace.numel() < need.value:
+    # (the allocation-free entry point rejects a workspace beyond its fixed
+    # scratch itself, with TR_ENOMEM)
+    if not noalloc and (workspace is None or workspace.numel() < need.value):
         workspace = torch.empty(max(need.value, 1), dtype=torch.uint8, device=A.device)
     if out is None:
         Qs = [colmajor_empty((dims[n], ranks[n]), A.dtype, A.device) for n in range(N)]
@@ -230,9 +234,13 @@ def _decompose_on(fn_name, A, ranks, oversample, power, prob, samples, seed, pre
             dstruct.timer = timer.handle
     fn = getattr(lib(), fn_name)
     dptr = byref(dstruct) if dstruct is not None else None
-    rc = fn(byref(p), dt, c_void_p(A.data_ptr()), qptrs, c_void_p(core.data_ptr()),
-            c_void_p(workspace.data_ptr()), c_size_t(workspace.numel()), dptr,
-            _stream(stream))
+    if noalloc:
+        rc = fn(byref(p), dt, c_void_p(A.data_ptr()), qptrs, c_void_p(core.data_ptr()), dptr,
+                _stream(stream))
+    else:
+        rc = fn(byref(p), dt, c_void_p(A.data_ptr()), qptrs, c_void_p(core.data_ptr()),
+                c_void_p(workspace.data_ptr()), c_size_t(workspace.numel()), dptr,
+                _stream(stream))
     check(fn_name, rc)
     return Qs, core, info
 
@@ -251,6 +259,17 @@ def tucker_rand_sthosvd(A: torch.Tensor, ranks, oversample=10, power=1, prob="no
     """Randomized ST-HOSVD (Alg. 2 / Alg. 5).  Returns (Q list, core, diag dict)."""
     return _decompose("tucker_rand_sthosvd", A, ranks, oversample, power, prob, samples,
                       seed, precision, diag, timer, workspace, stream, out)
+
+
+def tucker_rand_sthosvd_noalloc(A: torch.Tensor, ranks, oversample=10, power=1, prob="none",
+                                samples=None, seed=0, precision="native", diag=False,
+                                timer=None, stream=None, out=None):
+    """Randomized ST-HOSVD whose library call allocates nothing: the workspace is
+    the library's fixed device scratch (at most ``_abi.NOALLOC_SCRATCH_BYTES``).
+    Calls that overlap in time on one GPU race.  Pass ``out=(Qs, core)`` (and no
+    ``diag``) for a call with no allocation on the Python side either."""
+    return _decompose("tucker_rand_sthosvd_noalloc", A, ranks, oversample, power, prob,
+                      samples, seed, precision, diag, timer, None, stream, out)
 
 
 def _view3(X: torch.Tensor, L, I, R):

@@ -20,6 +20,8 @@ TR_DEV_NONFINITE, TR_DEV_ZERO_DIST = 0x1, 0x2
 KC = {"colnorms": 0, "sample": 1, "gather": 2, "power": 3, "factor": 4, "ttm": 5,
       "gaussian": 6}
 MAX_ORDER = 8
+# size of the fixed device scratch of tucker_rand_sthosvd_noalloc
+NOALLOC_SCRATCH_BYTES = 128 << 20
 
 
 class TrParams(ctypes.Structure):
@@ -46,6 +48,9 @@ _SIGS = {
                                    c_void_p, c_void_p, c_size_t, POINTER(TrDiag), c_void_p]),
     "tucker_rand_sthosvd": (c_int, [POINTER(TrParams), c_int, c_void_p, POINTER(c_void_p),
                                     c_void_p, c_void_p, c_size_t, POINTER(TrDiag), c_void_p]),
+    "tucker_rand_sthosvd_noalloc": (c_int, [POINTER(TrParams), c_int, c_void_p,
+                                            POINTER(c_void_p), c_void_p, POINTER(TrDiag),
+                                            c_void_p]),
     "tucker_rand_gaussian": (c_int, [c_int64, c_int64, c_int32, c_uint64, c_void_p, c_void_p]),
     "tucker_rand_colnorms": (c_int, [c_int, c_void_p, c_int64, c_int64, c_int64, c_void_p,
                                      c_void_p, c_void_p]),

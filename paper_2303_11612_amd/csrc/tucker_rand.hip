@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1124,6 +1125,40 @@ int run_thosvd(const tr_params* p, int dtype, const void* A, void* const* Q, voi
   return TR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Fixed device scratch for callers that cannot allocate (tucker_rand_sthosvd_
+// noalloc).  Each device that loads the library holds one copy of the array
+// for the life of the process; its device address is looked up once per
+// device (with that device current) and kept, because the array's name in
+// host code is only a host-side stand-in.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[TR_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, which must be the
+// device of `st` (the null stream belongs to the current device).
+int scratch_address(hipStream_t st, void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return TR_EDEVICE;
+  if (dev < 0 || dev >= kMaxDevices) return TR_ENOTSUP;
+  if (st) {
+    hipDevice_t sdev = -1;
+    if (hipStreamGetDevice(st, &sdev) != hipSuccess) return TR_EDEVICE;
+    if (sdev != dev) return TR_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return TR_EDEVICE;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return TR_OK;
+}
+
 int run_sthosvd(const tr_params* p, int dtype, const void* A, void* const* Q, void* core,
                 void* ws, size_t ws_bytes, const tr_diag* diag, hipStream_t st) {
   Plan P;
@@ -1186,6 +1221,17 @@ int tucker_rand_sthosvd(const tr_params* p, int dtype, const void* A, void* cons
                         void* stream) {
   return run_sthosvd(p, dtype, A, Q, core, workspace, workspace_bytes, diag,
                      (hipStream_t)stream);
+}
+
+int tucker_rand_sthosvd_noalloc(const tr_params* p, int dtype, const void* A, void* const* Q,
+                                void* core, const tr_diag* diag, void* stream) {
+  Plan P;
+  TR_TRY(make_plan(p, dtype, true, &P));
+  if (P.total > (size_t)TR_NOALLOC_SCRATCH_BYTES) return TR_ENOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  void* ws = nullptr;
+  TR_TRY(scratch_address(st, &ws));
+  return run_sthosvd(p, dtype, A, Q, core, ws, (size_t)TR_NOALLOC_SCRATCH_BYTES, diag, st);
 }
 
 int tucker_rand_gaussian(int64_t I, int64_t s, int32_t mode, uint64_t seed, double* G,
@@ -1311,6 +1357,8 @@ int tucker_rand_timer_create(int capacity, uint32_t class_mask, tr_timer** out) 
   if (!t) return TR_EINVAL;
   t->mask = class_mask;
   t->pool.resize(2 * (size_t)capacity);
+  // recording a launch never grows the list (no host allocation inside a call)
+  t->used.reserve((size_t)capacity);
   for (auto& e : t->pool) {
     if (hipEventCreate(&e) != hipSuccess) {
       delete t;

@@ -102,3 +102,18 @@ def test_binding_refuses_host_tensors():
     A = torch.zeros(4, 4, 4, dtype=torch.float64)
     with pytest.raises(ValueError):
         tr.tucker_rand_thosvd(A, (2, 2, 2), 1, 1)
+
+
+def test_noalloc_scratch_size_matches_header():
+    import re
+    with open(_abi.HEADER) as f:
+        m = re.search(r"#define\s+TR_NOALLOC_SCRATCH_BYTES\s+\(\(size_t\)(\d+)\s*<<\s*(\d+)\)",
+                      f.read())
+    assert m, "TR_NOALLOC_SCRATCH_BYTES not found"
+    assert int(m.group(1)) << int(m.group(2)) == _abi.NOALLOC_SCRATCH_BYTES
+    # the headline 400^3 sampled ST-HOSVD fits the fixed scratch
+    import torch
+    import paper_2303_11612_amd as tr
+    need = tr.tucker_rand_workspace_size((400, 400, 400), (10, 10, 10), 10, 1,
+                                         "nearly_optimal", (4000, 4000, 4000), 0, torch.float32)
+    assert need <= _abi.NOALLOC_SCRATCH_BYTES
