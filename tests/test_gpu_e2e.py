@@ -67,9 +67,7 @@ def _compare(A, algo, ranks, K, q, prob="none", samples=None, seed=0, tol=None,
             assert np.linalg.norm(Pg - Po, 2) <= tol, n
         else:
             assert _rel(Qg[n], Qo[n]) <= tol, (n, _rel(Qg[n], Qo[n]))
-        gsig = _np(info["sigma"][n])
-        assert np.allclose(gsig, sig, rtol=1e-9 if not f32 else 1e-4,
-                           atol=1e-12 * sig[0]), n
+        same_columns = True
         if prob != "none" and not infos[n]["exact"]:
             gi = _np(info["indices"][n])
             gs = _np(info["scales"][n])
@@ -79,6 +77,17 @@ def _compare(A, algo, ranks, K, q, prob="none", samples=None, seed=0, tol=None,
             else:
                 assert np.mean(gi == infos[n]["xi"]) > 0.999, n
                 assert np.allclose(gs, infos[n]["scale"], rtol=1e-12), n
+                same_columns = np.array_equal(gi, infos[n]["xi"])
+        # the sketch is computed in float64 from the same (exactly widened)
+        # data, so its singular values agree to float64 rounding; only a
+        # differently drawn column (a later ST-HOSVD mode, whose norms come
+        # from the library's own shrunk tensor) changes C_n itself, by about
+        # one column in T
+        gsig = _np(info["sigma"][n])
+        if same_columns:
+            assert np.allclose(gsig, sig, rtol=1e-9, atol=1e-12 * sig[0]), n
+        else:
+            assert np.allclose(gsig, sig, rtol=1e-2, atol=1e-12 * sig[0]), n
     if rotation_free:
         cr = co
         for n in range(A.ndim):
