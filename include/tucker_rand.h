@@ -74,9 +74,15 @@ typedef enum {
  *     C'_n; C is rounded per step (per-column scale for e4m3); M^T C is
  *     formed in that format with float32 accumulation and D M^T C enters the
  *     second product as a bfloat16 pair (about 16 bits).  Block partial sums
- *     are added in float64.  For q > 1 the iterate is replaced between steps
- *     by an orthonormal basis of its range (float64), which keeps the range
- *     of (M D M^T)^q G_n.  Column norms, sampling probabilities, the QR / SVD
+ *     are added in float64.  For q > 1 (or with TR_FLAG_STABILIZED_POWER)
+ *     the power scheme runs in its R-accumulated form (see the flag below):
+ *     the iterate that is rounded is always orthonormal, and Rbar keeps
+ *     C_n = Z_q Rbar equal to (M D M^T)^q G_n in exact arithmetic.  Only the
+ *     caller's tensor (and columns sampled from it) is rounded: the modes of
+ *     ST-HOSVD after the first are computed from the library's own float64
+ *     shrunk tensor, whose energy sits in few columns (rounding them would
+ *     rotate its range by the format's roundoff), with float64 products.
+ *     Column norms, sampling probabilities, the QR / SVD
  *     of the sketch and the shrink stay float64.  Supported for I_n <= 512,
  *     s_n <= 48 and, for unsampled modes, J_n < 2^32 (else TR_ENOTSUP).
  *     The rounding of M adds about the format's unit roundoff (2^-9 or 2^-4
@@ -102,8 +108,27 @@ typedef struct tr_params {
                                when prob == TR_PROB_NONE.                          */
   uint64_t seed;            /* Philox4x64-10 key word 0                            */
   int32_t precision;        /* tr_prec                                             */
-  uint32_t flags;           /* reserved, must be 0                                 */
+  uint32_t flags;           /* TR_FLAG_* bits; any other bit is TR_EINVAL          */
 } tr_params;
+
+/*
+ * tr_params.flags.
+ *   TR_FLAG_STABILIZED_POWER: the power scheme with an orthonormalisation
+ *     after every step and the triangular factors accumulated (the QR form of
+ *     the power iteration; equal to the plain products C_n = (M D M^T)^q G_n
+ *     in exact arithmetic): Z_0 R_0 = G_n, Z_i R_i = M D M^T Z_{i-1}
+ *     (i = 1..q), Rbar = R_q ... R_0, and Q_n = Z_q U'(:, 1:mu_n) for
+ *     Rbar = U' S V'^T; the singular values reported are those of Rbar (those
+ *     of C_n = Z_q Rbar).  Z_i is the orthonormal factor the factor kernel
+ *     computes and R_i = Z_i^T (M D M^T Z_{i-1}).  The low-precision modes
+ *     (TR_PREC_BF16 / TR_PREC_FP8E4M3) use this form whenever q > 1.
+ *   TR_FLAG_UNFUSED_POWER: every exact power step as its two products
+ *     (W = D M^T Y written to the workspace, then M W), as the Remark after
+ *     Alg. 1 writes Strategy A, instead of the one-sweep kernel that keeps W
+ *     on chip (where that kernel applies); same result up to rounding order.
+ */
+#define TR_FLAG_STABILIZED_POWER 0x1u
+#define TR_FLAG_UNFUSED_POWER 0x2u
 
 typedef struct tr_timer tr_timer;
 
@@ -253,7 +278,6 @@ int tucker_rand_power(int dtype, const void *X, int64_t L, int64_t I,
                       const double *G, int64_t s, double *C, void *workspace,
                       size_t workspace_bytes, void *stream);
 
-/*
 /* Device workspace bytes needed by tucker_rand_factor (0 when the working
  * matrices fit in the workgroup's LDS). */
 size_t tucker_rand_factor_workspace_size(int64_t I, int64_t s, int64_t mu);

@@ -34,9 +34,12 @@ sample matrix C' with D = diag(scale_t^2)):
   bfloat16 matrices (about 16 significant bits), and Mhat in bfloat16, which
   holds every bfloat16 and every e4m3 value exactly.
 
-For q > 1 the iterate is replaced between steps by an orthonormal basis of
-its range, its s left singular vectors with the canonical signs (subspace
-iteration): C_q = M D M^T Y_{q-1} has the range of (M D M^T)^q G.
+For q > 1 the power scheme runs in its R-accumulated form: Z_0 R_0 = G and
+Z_i R_i = M D M^T Z_{i-1} (i = 1..q), where Z_i is the iterate's s left
+singular vectors with the canonical signs and R_i = Z_i^T (M D M^T Z_{i-1}),
+and C_n = Z_q Rbar with Rbar = R_q ... R_0, equal to (M D M^T)^q G in exact
+arithmetic.  Only orthonormal iterates are rounded to the operand format, so
+directions far below the leading one survive the rounding.
 
 Scale arithmetic follows the device in float32: tau and sigma are
 max / 448 and the rounded value is x / scale; the tensor is multiplied by
@@ -163,12 +166,21 @@ def power_sketch_lp(X: np.ndarray, n: int, s: int, q: int, prec: str, seed: int,
         d = np.full(An.shape[1], d0)
     else:
         Mhat, d = quantize_samples(An[:, xi], scale, prec)
-    C = gaussian_matrix(I, s, n, seed)
-    for step in range(q):
-        C = power_step(Mhat, d, C, prec)
-        if step + 1 < q:
-            C, _ = leading_left_singular_vectors(C, s)
-    return C
+    G = gaussian_matrix(I, s, n, seed)
+    if q == 1:
+        return power_step(Mhat, d, G, prec)
+    Z, Rbar = _orth(G)
+    for _ in range(q):
+        Z, R = _orth(power_step(Mhat, d, Z, prec))
+        Rbar = R @ Rbar
+    return Z @ Rbar
+
+
+def _orth(Y: np.ndarray):
+    """(Z, R) with Z the s left singular vectors of Y (canonical signs) and
+    R = Z^T Y, so that Y = Z R."""
+    Z, _ = leading_left_singular_vectors(Y, Y.shape[1])
+    return Z, Z.T @ Y
 
 
 def range_finder_lp(X, n: int, mu: int, K: int, q: int, prec: str, seed: int,

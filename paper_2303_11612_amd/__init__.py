@@ -84,7 +84,17 @@ def _i64arr(vals):
     return arr
 
 
-def _params(dims, ranks, oversample, power, prob, samples, seed, precision):
+def _flag_bits(flags) -> int:
+    """tr_params.flags from an int or an iterable of names in _abi.FLAGS."""
+    if isinstance(flags, int):
+        return flags
+    bits = 0
+    for f in flags:
+        bits |= _abi.FLAGS[f]
+    return bits
+
+
+def _params(dims, ranks, oversample, power, prob, samples, seed, precision, flags=0):
     N = len(dims)
     if len(ranks) != N:
         raise ValueError("ranks needs one entry per mode")
@@ -103,7 +113,7 @@ def _params(dims, ranks, oversample, power, prob, samples, seed, precision):
         p.samples = ctypes.cast(keep[2], ctypes.POINTER(c_int64))
     p.seed = int(seed) & ((1 << 64) - 1)
     p.precision = PREC[precision] if isinstance(precision, str) else int(precision)
-    p.flags = 0
+    p.flags = _flag_bits(flags)
     return p, keep
 
 
@@ -113,9 +123,9 @@ def tucker_rand_status_string(code: int) -> str:
 
 def tucker_rand_workspace_size(dims, ranks, oversample=10, power=1, prob="none",
                                samples=None, seed=0, dtype=torch.float32,
-                               sthosvd=True, precision="native") -> int:
+                               sthosvd=True, precision="native", flags=0) -> int:
     """Bytes of workspace tucker_rand_(s)thosvd needs (validates the arguments)."""
-    p, _keep = _params(dims, ranks, oversample, power, prob, samples, seed, precision)
+    p, _keep = _params(dims, ranks, oversample, power, prob, samples, seed, precision, flags)
     out = c_size_t(0)
     check("tucker_rand_workspace_size",
           lib().tucker_rand_workspace_size(byref(p), _DT[dtype], int(bool(sthosvd)), byref(out)))
@@ -159,7 +169,7 @@ class Timer:
 
 
 def _decompose(fn_name, A, ranks, oversample, power, prob, samples, seed, precision,
-               diag, timer, workspace, stream, out=None):
+               diag, timer, workspace, stream, out=None, flags=0):
     if not A.is_cuda:
         raise ValueError("A must be a device tensor")
     if not is_colmajor(A):
@@ -170,17 +180,17 @@ def _decompose(fn_name, A, ranks, oversample, power, prob, samples, seed, precis
     # reuses a freed buffer only after the work queued on that stream
     with torch.cuda.stream(st):
         return _decompose_on(fn_name, A, ranks, oversample, power, prob, samples, seed,
-                             precision, diag, timer, workspace, st, out)
+                             precision, diag, timer, workspace, st, out, flags)
 
 
 def _decompose_on(fn_name, A, ranks, oversample, power, prob, samples, seed, precision,
-                  diag, timer, workspace, stream, out):
+                  diag, timer, workspace, stream, out, flags):
     dims = tuple(A.shape)
     N = len(dims)
     dt = _dtype_code(A)
     noalloc = fn_name == "tucker_rand_sthosvd_noalloc"
     sthosvd = fn_name != "tucker_rand_thosvd"
-    p, keep = _params(dims, ranks, oversample, power, prob, samples, seed, precision)
+    p, keep = _params(dims, ranks, oversample, power, prob, samples, seed, precision, flags)
     need = c_size_t(0)
     check("tucker_rand_workspace_size",
           lib().tucker_rand_workspace_size(byref(p), dt, int(sthosvd), byref(need)))
@@ -247,29 +257,29 @@ def _decompose_on(fn_name, A, ranks, oversample, power, prob, samples, seed, pre
 
 def tucker_rand_thosvd(A: torch.Tensor, ranks, oversample=10, power=1, prob="none",
                        samples=None, seed=0, precision="native", diag=False, timer=None,
-                       workspace=None, stream=None, out=None):
+                       workspace=None, stream=None, out=None, flags=0):
     """Randomized T-HOSVD (Alg. 1 / Alg. 4).  Returns (Q list, core, diag dict)."""
     return _decompose("tucker_rand_thosvd", A, ranks, oversample, power, prob, samples,
-                      seed, precision, diag, timer, workspace, stream, out)
+                      seed, precision, diag, timer, workspace, stream, out, flags)
 
 
 def tucker_rand_sthosvd(A: torch.Tensor, ranks, oversample=10, power=1, prob="none",
                         samples=None, seed=0, precision="native", diag=False, timer=None,
-                        workspace=None, stream=None, out=None):
+                        workspace=None, stream=None, out=None, flags=0):
     """Randomized ST-HOSVD (Alg. 2 / Alg. 5).  Returns (Q list, core, diag dict)."""
     return _decompose("tucker_rand_sthosvd", A, ranks, oversample, power, prob, samples,
-                      seed, precision, diag, timer, workspace, stream, out)
+                      seed, precision, diag, timer, workspace, stream, out, flags)
 
 
 def tucker_rand_sthosvd_noalloc(A: torch.Tensor, ranks, oversample=10, power=1, prob="none",
                                 samples=None, seed=0, precision="native", diag=False,
-                                timer=None, stream=None, out=None):
+                                timer=None, stream=None, out=None, flags=0):
     """Randomized ST-HOSVD whose library call allocates nothing: the workspace is
     the library's fixed device scratch (at most ``_abi.NOALLOC_SCRATCH_BYTES``).
     Calls that overlap in time on one GPU race.  Pass ``out=(Qs, core)`` (and no
     ``diag``) for a call with no allocation on the Python side either."""
     return _decompose("tucker_rand_sthosvd_noalloc", A, ranks, oversample, power, prob,
-                      samples, seed, precision, diag, timer, None, stream, out)
+                      samples, seed, precision, diag, timer, None, stream, out, flags)
 
 
 def _view3(X: torch.Tensor, L, I, R):

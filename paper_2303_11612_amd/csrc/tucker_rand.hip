@@ -20,6 +20,7 @@
 #include "tr_factor_rf.hpp"
 #include "tr_power.hpp"
 #include "tr_lowp.hpp"
+#include "tr_stab.hpp"
 #include "tr_host.hpp"
 #include "tucker_rand.h"
 
@@ -135,6 +136,8 @@ struct ModePlan {
   bool sampled;
   bool src_f64;         // the tensor of this mode is float64
   bool intermediate;    // ... and the library's own shrunk tensor (ST-HOSVD, n > 0)
+  bool lp;              // power products in the low-precision format (the
+                        // caller's tensor or samples of it; never an intermediate)
 };
 
 struct Plan {
@@ -156,12 +159,17 @@ struct Plan {
   // T-HOSVD: every mode's sketch and singular values are kept until the
   // factorizations of all modes run in one launch
   size_t oYn[TR_MAX_ORDER] = {}, oSign[TR_MAX_ORDER] = {};
-  // T-HOSVD, low precision, q > 1: every mode's current orthonormal iterate,
-  // so that the modes advance one power step at a time together
-  size_t oGn[TR_MAX_ORDER] = {};
   // every mode's Gaussian G_n (I x s) and its zero-padded row-major copy
   // (I x sw), drawn in one launch before the first mode
   size_t oGs[TR_MAX_ORDER] = {}, oYts[TR_MAX_ORDER] = {};
+  // power scheme with the triangular factors accumulated (tr_stab.hpp):
+  // TR_FLAG_STABILIZED_POWER, and always for low precision with q > 1
+  bool racc = false;
+  bool fused = true;  // one-sweep power steps allowed (TR_FLAG_UNFUSED_POWER clears it)
+  // per mode: orthonormal iterate Z (I x s), factor scratch (I x s), R_i and
+  // Rbar (s x s), the factor U' of Rbar (s x mu), singular-value scratch (s)
+  size_t oZn[TR_MAX_ORDER] = {}, oGA[TR_MAX_ORDER] = {}, oRst[TR_MAX_ORDER] = {},
+         oRbar[TR_MAX_ORDER] = {}, oUp[TR_MAX_ORDER] = {}, oSgs[TR_MAX_ORDER] = {};
 };
 
 // Validates and fills the plan; returns TR_OK or an error code.
@@ -174,12 +182,14 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
       p->prob != TR_PROB_UNIFORM)
     return TR_EINVAL;
   if (p->prob != TR_PROB_NONE && !p->samples) return TR_EINVAL;
-  if (p->flags != 0) return TR_EINVAL;
+  if (p->flags & ~(uint32_t)(TR_FLAG_STABILIZED_POWER | TR_FLAG_UNFUSED_POWER)) return TR_EINVAL;
   if (p->precision != TR_PREC_NATIVE && p->precision != TR_PREC_BF16 &&
       p->precision != TR_PREC_FP8E4M3)
     return TR_EINVAL;
   const bool lp = p->precision != TR_PREC_NATIVE;
   P->prec = p->precision;
+  P->racc = (p->flags & TR_FLAG_STABILIZED_POWER) != 0 || (lp && p->power > 1);
+  P->fused = (p->flags & TR_FLAG_UNFUSED_POWER) == 0;
   const int N = p->order;
   P->N = N;
   P->sthosvd = sthosvd;
@@ -198,6 +208,7 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
 
   size_t maxIs = 0, maxZ = 0, maxPart = 0, maxJs = 0, maxT = 0, maxCp = 0, maxInter = 0,
          maxSplit = 0, maxYq = 0, maxPartLp = 0, maxCq = 0;
+  bool any_lp = false, any_f64 = false;
   int64_t maxS = 0;
   for (int n = 0; n < N; ++n) {
     ModePlan& M = P->m[n];
@@ -222,7 +233,14 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
       }
     }
     if (!factor_supported(M.I, M.s)) return TR_ENOTSUP;
-    if (lp) {
+    // low precision rounds the caller's data only: an ST-HOSVD intermediate
+    // (float64, at most mu_1/I_1 of the input) keeps its energy in few
+    // columns, so rounding it would turn the format's roundoff directly into
+    // subspace error, for little traffic saved
+    M.lp = lp && !M.intermediate;
+    any_lp = any_lp || M.lp;
+    any_f64 = any_f64 || !M.lp;
+    if (M.lp) {
       if (!lp_supported(M.I, M.s)) return TR_ENOTSUP;
       const int64_t jl = M.sampled ? M.T : M.J;
       if (!M.sampled && M.J >= ((int64_t)1 << 32)) return TR_ENOTSUP;
@@ -279,8 +297,8 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
   P->oY = take(8 * maxIs);
   P->oYt = take(8 * maxIs);
   // the float64 power steps' W and partial sketches (unused in low precision)
-  P->oZ = take(lp ? 8 : 8 * maxZ);
-  P->oPart = take(lp ? 8 : 8 * maxPart);
+  P->oZ = take(any_f64 ? 8 * maxZ : 8);
+  P->oPart = take(any_f64 ? 8 * maxPart : 8);
   P->oNorms = take(8 * maxJs);
   P->oW = take(8 * maxJs);
   P->oCdf = take(8 * maxJs);
@@ -288,7 +306,7 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
   P->oIdx = take(8 * maxT);
   P->oScale = take(8 * maxT);
   P->oScale2 = take(8 * maxT);
-  P->oCp = take(lp ? 8 : 8 * maxCp);
+  P->oCp = take(any_f64 ? 8 * maxCp : 8);
   P->oMax = take(8 * (size_t)N);  // one running maximum per mode
   for (int n = 0; n < N; ++n) {
     P->oGs[n] = take(8 * (size_t)(P->m[n].I * P->m[n].s));
@@ -303,13 +321,22 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
     for (int n = 0; n < N; ++n) {
       P->oYn[n] = take(8 * (size_t)(P->m[n].I * P->m[n].s));
       P->oSign[n] = take(8 * (size_t)P->m[n].s);
-      if (lp && P->q > 1) P->oGn[n] = take(8 * (size_t)(P->m[n].I * P->m[n].sw));
+    }
+  if (P->racc)
+    for (int n = 0; n < N; ++n) {
+      const size_t Is = (size_t)(P->m[n].I * P->m[n].s), ss = (size_t)(P->m[n].s * P->m[n].s);
+      P->oZn[n] = take(8 * Is);
+      P->oGA[n] = take(8 * Is);
+      P->oRst[n] = take(8 * ss);
+      P->oRbar[n] = take(8 * ss);
+      P->oUp[n] = take(8 * (size_t)(P->m[n].s * P->m[n].mu));
+      P->oSgs[n] = take(8 * (size_t)P->m[n].s);
     }
   P->oX0 = take(8 * maxInter);
   P->oX1 = take(8 * maxInter);
   P->oCore = take(8 * core_el);
   P->oSplit = take(8 * maxSplit);
-  if (lp) {
+  if (any_lp) {
     P->oYq = take(2 * maxYq);
     P->oTau = take(4 * 64);
     P->oPartLp = take(4 * maxPartLp);
@@ -319,6 +346,11 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
   }
   P->total = off;
   return TR_OK;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
 }
 
 // ---------------------------------------------------------------------------
@@ -640,11 +672,12 @@ size_t power_ws_bytes(int64_t L, int64_t I, int64_t R, int64_t s, bool f64) {
 // Yt = G^T (row stride sw, zero-padded).  Z, part: scratch.
 int run_power(bool f64, const void* X, int64_t L, int64_t I, int64_t R, const double* colw,
               int q, int64_t s, int sw, double* Y, double* Yt, double* Z, double* part,
-              uint32_t* status, hipStream_t st) {
+              uint32_t* status, hipStream_t st, bool fused = true) {
   for (int step = 0; step < q; ++step) {
     int64_t nused = 0;
     // one sweep with W kept on chip when the rows and the sketch are narrow
-    const int rc = launch_pw_fused(f64, X, L, I, R, colw, Yt, sw, s, part, &nused, st);
+    const int rc = fused ? launch_pw_fused(f64, X, L, I, R, colw, Yt, sw, s, part, &nused, st)
+                         : TR_ENOTSUP;
     if (rc != TR_OK && rc != TR_ENOTSUP) return rc;
     if (rc == TR_ENOTSUP) {
       if (f64) TR_TRY(pw_step_t((const double*)X, L, I, R, colw, Yt, sw, s, Z, part, &nused, st));
@@ -733,19 +766,57 @@ int power_lp_step(const Plan& P, int kind, const void* M, int64_t L, int64_t I, 
   return check_launch();
 }
 
-int run_power_lp(const Plan& P, int kind, const void* M, int64_t L, int64_t I, int64_t R,
+int launch_factor_jobs(const trk::FactorJob* job, int n, int cast_f32, uint32_t* status,
+                       hipStream_t st);
+
+// Orthonormalisation steps of the R-accumulated power scheme for k modes at
+// once: Z_n = the orthonormal factor of C_n (its s left singular vectors; one
+// factor launch for all), Zt_n its zero-padded row-major copy (row stride
+// ldzt; skipped when null), then Rbar_n <- (Z_n^T C_n) Rbar_n (first: the
+// product alone).  C_n is left intact (the factor's scratch is its own).
+int stab_orth(const Plan& P, const int* modes, int k, double* const* C, double* const* Zt,
+              bool first, void* ws, uint32_t* status, hipStream_t st) {
+  trk::FactorJob jobs[TR_MAX_ORDER];
+  for (int b = 0; b < k; ++b) {
+    const int n = modes[b];
+    const ModePlan& M = P.m[n];
+    jobs[b] = trk::FactorJob{C[b], at<double>(ws, P.oZn[n]), Zt[b], at<double>(ws, P.oSgs[n]),
+                             nullptr, at<double>(ws, P.oGA[n]), (int)M.I, (int)M.s, (int)M.s,
+                             Zt[b] ? M.sw : 0};
+  }
+  TR_TRY(launch_factor_jobs(jobs, k, 0, status, st));
+  for (int b = 0; b < k; ++b) {
+    const int n = modes[b];
+    const ModePlan& M = P.m[n];
+    double* Rs = at<double>(ws, P.oRst[n]);
+    hipLaunchKernelGGL(trk::k_small_tn, dim3((unsigned)(M.s * M.s)), dim3(trk::kStabNT), 0, st,
+                       at<double>(ws, P.oZn[n]), C[b], M.I, (int)M.s, Rs);
+    TR_TRY(check_launch());
+    hipLaunchKernelGGL(trk::k_rbar_update, dim3(1), dim3(trk::kStabNT), 0, st, Rs,
+                       at<double>(ws, P.oRbar[n]), (int)M.s, first ? 1 : 0);
+    TR_TRY(check_launch());
+  }
+  return TR_OK;
+}
+
+// Low-precision power products of mode n from G (float64 I x s): without
+// R-accumulation (q = 1) C = M D M^T G; with it, Z_0 Rbar = G, then per step
+// C = M D M^T Z_{i-1} in the operand format and Z_i, Rbar updated (the
+// iterate that is rounded is always orthonormal, which keeps directions far
+// below the leading one; C_n = Z_q Rbar is left to the final factor).
+int run_power_lp(const Plan& P, int n, int kind, const void* M, int64_t L, int64_t I, int64_t R,
                  int64_t ldi, const float* omega, const unsigned* xmax, int64_t s,
                  double* G, double* C, void* ws, uint32_t* status, hipStream_t st) {
-  const double* src = G;
+  if (!P.racc)
+    return power_lp_step(P, kind, M, L, I, R, ldi, omega, xmax, s, G, C, ws, status, st);
+  double* const none[1] = {nullptr};
+  double* Zn = at<double>(ws, P.oZn[n]);
+  double* cs[1] = {G};
+  TR_TRY(stab_orth(P, &n, 1, cs, none, true, ws, status, st));
+  cs[0] = C;
   for (int step = 0; step < P.q; ++step) {
-    TR_TRY(power_lp_step(P, kind, M, L, I, R, ldi, omega, xmax, s, src, C, ws, status, st));
-    if (step + 1 < P.q) {
-      // C is dead after this call (it doubles as the factor's scratch)
-      TR_TRY(launch_factor(C, I, s, s, G, reinterpret_cast<double*>(static_cast<char*>(ws) + P.oYt),
-                           pad_width(s), reinterpret_cast<double*>(static_cast<char*>(ws) + P.oSig),
-                           nullptr, 0, status, C, st));
-      src = G;
-    }
+    TR_TRY(power_lp_step(P, kind, M, L, I, R, ldi, omega, xmax, s, Zn, C, ws, status, st));
+    TR_TRY(stab_orth(P, &n, 1, cs, none, false, ws, status, st));
   }
   return TR_OK;
 }
@@ -863,11 +934,6 @@ int launch_factor(const double* C, int64_t I, int64_t s, int64_t mu, double* Q, 
 // ---------------------------------------------------------------------------
 // Drivers
 // ---------------------------------------------------------------------------
-template <typename T>
-T* at(void* ws, size_t off) {
-  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
-}
-
 int copy_d2d(void* dst, const void* src, size_t bytes, hipStream_t st) {
   if (!dst || bytes == 0) return TR_OK;
   return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st) == hipSuccess
@@ -916,7 +982,7 @@ int range_sketch(const Plan& P, int n, const void* X, void* ws, const tr_diag* d
   bool src_f64 = M.src_f64;
   int64_t L = M.L, R = M.R;
   const double* colw = nullptr;
-  const bool lp = P.prec != TR_PREC_NATIVE;
+  const bool lp = M.lp;
   if (M.sampled) {
     double* norms = at<double>(ws, P.oNorms);
     auto* maxb = at<unsigned long long>(ws, P.oMax) + n;
@@ -959,16 +1025,31 @@ int range_sketch(const Plan& P, int n, const void* X, void* ws, const tr_diag* d
     }
     TimeScope ts(tm, TR_KC_POWER, n, st);
     if (M.sampled)
-      TR_TRY(run_power_lp(P, kLpStored, at<void>(ws, P.oCq), 1, M.I, M.T, lp_ip(M.I),
+      TR_TRY(run_power_lp(P, n, kLpStored, at<void>(ws, P.oCq), 1, M.I, M.T, lp_ip(M.I),
                           at<float>(ws, P.oOmega), nullptr, M.s, G, Y, ws, status, st));
     else
-      TR_TRY(run_power_lp(P, M.src_f64 ? kLpF64 : kLpF32, X, M.L, M.I, M.R, M.I, nullptr, xmax,
-                          M.s, G, Y, ws, status, st));
+      TR_TRY(run_power_lp(P, n, M.src_f64 ? kLpF64 : kLpF32, X, M.L, M.I, M.R, M.I, nullptr,
+                          xmax, M.s, G, Y, ws, status, st));
+  } else if (P.racc) {
+    // Z_0 Rbar = G (Yt = Z_0^T, padded), then per step Y = M D M^T Z_{i-1}
+    // and Z_i, Rbar updated
+    TimeScope ts(tm, TR_KC_POWER, n, st);
+    double* Gs[1] = {G};
+    double* Zts[1] = {Yt};
+    TR_TRY(stab_orth(P, &n, 1, Gs, Zts, true, ws, status, st));
+    double* Ys[1] = {Y};
+    for (int step = 0; step < P.q; ++step) {
+      TR_TRY(run_power(src_f64, src, L, M.I, R, colw, 1, M.s, M.sw, Y, Yt, Z, part, status, st,
+                       P.fused));
+      TR_TRY(stab_orth(P, &n, 1, Ys, Zts, false, ws, status, st));
+    }
   } else {
     TimeScope ts(tm, TR_KC_POWER, n, st);
-    TR_TRY(run_power(src_f64, src, L, M.I, R, colw, P.q, M.s, M.sw, Y, Yt, Z, part, status, st));
+    TR_TRY(run_power(src_f64, src, L, M.I, R, colw, P.q, M.s, M.sw, Y, Yt, Z, part, status, st,
+                     P.fused));
   }
-  if (diag && diag->sketch && diag->sketch[n])
+  // (with R-accumulation the sketch Z_q Rbar is written by the final factor step)
+  if (!P.racc && diag && diag->sketch && diag->sketch[n])
     TR_TRY(copy_d2d(diag->sketch[n], Y, 8 * (size_t)(M.I * M.s), st));
   return TR_OK;
 }
@@ -986,6 +1067,29 @@ double* mode_sigma(const Plan& P, int n, const tr_diag* diag, void* ws, size_t o
   return (diag && diag->sigma && diag->sigma[n]) ? diag->sigma[n] : at<double>(ws, off);
 }
 
+// R-accumulated form: the factor of Rbar_n (s x s) into U'_n (s x mu); its
+// singular values are those of C_n = Z_n Rbar_n.
+trk::FactorJob rbar_job(const Plan& P, int n, double* sig, void* ws) {
+  const ModePlan& M = P.m[n];
+  return trk::FactorJob{at<double>(ws, P.oRbar[n]), at<double>(ws, P.oUp[n]), nullptr, sig,
+                        nullptr, at<double>(ws, P.oGA[n]), (int)M.s, (int)M.s, (int)M.mu, 0};
+}
+
+// R-accumulated form, after rbar_job: Q_n = Z_n U'_n(:, 1:mu) with canonical
+// signs into the mode's Q64 / Qt and the caller's Q; the sketch Z_n Rbar_n
+// into the diagnostics when asked for.
+int stab_final(const Plan& P, int n, void* ws, void* Qout, const tr_diag* diag,
+               hipStream_t st) {
+  const ModePlan& M = P.m[n];
+  double* Cd = (diag && diag->sketch && diag->sketch[n]) ? diag->sketch[n] : nullptr;
+  const unsigned nb = (unsigned)(M.muw + (Cd ? M.s : 0));
+  hipLaunchKernelGGL(trk::k_stab_final, dim3(nb), dim3(trk::kStabNT), 0, st,
+                     at<double>(ws, P.oZn[n]), M.I, (int)M.s, at<double>(ws, P.oUp[n]),
+                     (int)M.mu, at<double>(ws, P.oRbar[n]), at<double>(ws, P.oQ[n]),
+                     at<double>(ws, P.oQt[n]), M.muw, Qout, P.dtype == TR_F32 ? 1 : 0, Cd);
+  return check_launch();
+}
+
 // Range finder of mode n (ST-HOSVD: sketch, then factor).
 int range_finder(const Plan& P, int n, const void* X, void* ws, void* Qout,
                  const tr_diag* diag, bool need_xmax, hipStream_t st) {
@@ -994,7 +1098,13 @@ int range_finder(const Plan& P, int n, const void* X, void* ws, void* Qout,
   tr_timer* tm = diag ? diag->timer : nullptr;
   uint32_t* status = diag ? diag->status : nullptr;
   TimeScope ts(tm, TR_KC_FACTOR, n, st);
-  const trk::FactorJob jb = factor_job(P, n, Y, mode_sigma(P, n, diag, ws, P.oSig), ws, Qout);
+  double* sig = mode_sigma(P, n, diag, ws, P.oSig);
+  if (P.racc) {
+    const trk::FactorJob jb = rbar_job(P, n, sig, ws);
+    TR_TRY(launch_factor_jobs(&jb, 1, 0, status, st));
+    return stab_final(P, n, ws, Qout, diag, st);
+  }
+  const trk::FactorJob jb = factor_job(P, n, Y, sig, ws, Qout);
   return launch_factor_jobs(&jb, 1, P.dtype == TR_F32, status, st);
 }
 
@@ -1039,7 +1149,7 @@ int run_thosvd(const tr_params* p, int dtype, const void* A, void* const* Q, voi
   uint32_t* status = diag ? diag->status : nullptr;
   // low precision with q > 1: the unsampled modes advance one power step at
   // a time together, so that each round of orthonormalisation between steps
-  // is one launch for all of them
+  // is one factor launch for all of them
   bool together[TR_MAX_ORDER] = {};
   int ntog = 0;
   for (int n = 0; n < P.N; ++n) {
@@ -1047,7 +1157,7 @@ int run_thosvd(const tr_params* p, int dtype, const void* A, void* const* Q, voi
     ntog += together[n] ? 1 : 0;
   }
   bool xmax_ready = false;
-  if (ntog < P.N) {
+  {
     TimeScope ts(tm0, TR_KC_GAUSSIAN, 0, st);
     TR_TRY(launch_gaussian_modes(P, ws, st));
   }
@@ -1059,53 +1169,51 @@ int run_thosvd(const tr_params* p, int dtype, const void* A, void* const* Q, voi
     if (!P.m[n].sampled) xmax_ready = true;
   }
   if (ntog > 0) {
+    // R-accumulated power steps (low precision, q > 1), all these modes per
+    // step: Z_0 Rbar = G_n, then C_n = A_(n) A_(n)^T Z_{i-1} in the operand
+    // format and Z_i, Rbar updated -- one factor launch per round for all
     unsigned* xmax = nullptr;
     if (P.prec == TR_PREC_FP8E4M3) {
       xmax = at<unsigned>(ws, P.oXmax);
       const ModePlan& M0 = P.m[0];
       if (!xmax_ready) TR_TRY(launch_maxabs(M0.src_f64, A, M0.L * M0.I * M0.R, xmax, st));
     }
+    int modes[TR_MAX_ORDER];
+    double* Cs[TR_MAX_ORDER];
+    double* const nozt[TR_MAX_ORDER] = {};
+    int k = 0;
     for (int n = 0; n < P.N; ++n)
       if (together[n]) {
-        const ModePlan& M = P.m[n];
-        TimeScope ts(tm0, TR_KC_GAUSSIAN, n, st);
-        TR_TRY(launch_gaussian(at<double>(ws, P.oGn[n]), at<double>(ws, P.oYt), M.I, M.s, M.sw, n,
-                               P.seed, st));
+        modes[k] = n;
+        Cs[k++] = at<double>(ws, P.oGs[n]);
       }
-    for (int step = 0; step < P.q; ++step) {
-      trk::FactorJob orth[TR_MAX_ORDER];
-      int k = 0;
-      for (int n = 0; n < P.N; ++n) {
-        if (!together[n]) continue;
-        const ModePlan& M = P.m[n];
-        double* Gn = at<double>(ws, P.oGn[n]);
-        double* Yn = at<double>(ws, P.oYn[n]);
-        {
-          TimeScope ts(tm0, TR_KC_POWER, n, st);
-          TR_TRY(power_lp_step(P, M.src_f64 ? kLpF64 : kLpF32, A, M.L, M.I, M.R, M.I, nullptr,
-                               xmax, M.s, Gn, Yn, ws, status, st));
-        }
-        // next iterate: an orthonormal basis of range(Y_n) (its s left
-        // singular vectors, float64); Y_n is the factor's scratch
-        orth[k++] = trk::FactorJob{Yn, Gn, nullptr, at<double>(ws, P.oSign[n]), nullptr, Yn,
-                                   (int)M.I, (int)M.s, (int)M.s, 0};
-      }
-      if (step + 1 < P.q) {
-        TimeScope ts(tm0, TR_KC_POWER, 0, st);
-        TR_TRY(launch_factor_jobs(orth, k, 0, status, st));
-      }
+    {
+      TimeScope ts(tm0, TR_KC_POWER, 0, st);
+      TR_TRY(stab_orth(P, modes, k, Cs, nozt, true, ws, status, st));
     }
-    for (int n = 0; n < P.N; ++n)
-      if (together[n] && diag && diag->sketch && diag->sketch[n])
-        TR_TRY(copy_d2d(diag->sketch[n], at<double>(ws, P.oYn[n]),
-                        8 * (size_t)(P.m[n].I * P.m[n].s), st));
+    for (int b = 0; b < k; ++b) Cs[b] = at<double>(ws, P.oYn[modes[b]]);
+    for (int step = 0; step < P.q; ++step) {
+      for (int b = 0; b < k; ++b) {
+        const int n = modes[b];
+        const ModePlan& M = P.m[n];
+        TimeScope ts(tm0, TR_KC_POWER, n, st);
+        TR_TRY(power_lp_step(P, M.src_f64 ? kLpF64 : kLpF32, A, M.L, M.I, M.R, M.I, nullptr,
+                             xmax, M.s, at<double>(ws, P.oZn[n]), Cs[b], ws, status, st));
+      }
+      TimeScope ts(tm0, TR_KC_POWER, 0, st);
+      TR_TRY(stab_orth(P, modes, k, Cs, nozt, false, ws, status, st));
+    }
   }
-  for (int n = 0; n < P.N; ++n)
-    jobs[n] = factor_job(P, n, at<double>(ws, P.oYn[n]), mode_sigma(P, n, diag, ws, P.oSign[n]),
-                         ws, Q[n]);
+  for (int n = 0; n < P.N; ++n) {
+    double* sig = mode_sigma(P, n, diag, ws, P.oSign[n]);
+    jobs[n] = P.racc ? rbar_job(P, n, sig, ws)
+                     : factor_job(P, n, at<double>(ws, P.oYn[n]), sig, ws, Q[n]);
+  }
   {
     TimeScope ts(diag ? diag->timer : nullptr, TR_KC_FACTOR, 0, st);
     TR_TRY(launch_factor_jobs(jobs, P.N, P.dtype == TR_F32, diag ? diag->status : nullptr, st));
+    if (P.racc)
+      for (int n = 0; n < P.N; ++n) TR_TRY(stab_final(P, n, ws, Q[n], diag, st));
   }
   int64_t shp[TR_MAX_ORDER];
   for (int k = 0; k < P.N; ++k) shp[k] = P.dims[k];

@@ -117,3 +117,16 @@ def test_noalloc_scratch_size_matches_header():
     need = tr.tucker_rand_workspace_size((400, 400, 400), (10, 10, 10), 10, 1,
                                          "nearly_optimal", (4000, 4000, 4000), 0, torch.float32)
     assert need <= _abi.NOALLOC_SCRATCH_BYTES
+
+
+def test_flag_bits_validated_on_host():
+    import paper_2303_11612_amd as tr
+    base = tr.tucker_rand_workspace_size((40, 30, 20), (4, 4, 4), 4, 2, "none")
+    stab = tr.tucker_rand_workspace_size((40, 30, 20), (4, 4, 4), 4, 2, "none",
+                                         flags=["stabilized_power"])
+    assert stab > base   # per mode: the orthonormal iterate, Rbar, U'
+    assert tr.tucker_rand_workspace_size((40, 30, 20), (4, 4, 4), 4, 2, "none",
+                                         flags=["unfused_power"]) == base
+    for bad in (0x4, 0x8, 0x80000000):
+        with pytest.raises(_abi.TuckerRandError, match="invalid argument"):
+            tr.tucker_rand_workspace_size((40, 30, 20), (4, 4, 4), 4, 2, "none", flags=bad)

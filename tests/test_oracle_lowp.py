@@ -96,8 +96,9 @@ def test_sketch_error_is_format_sized(prec, tol, q):
         Q, _ = oracle.leading_left_singular_vectors(C, 4)
         Ce = oracle.power_sketch(oracle.unfold(A64, n), oracle.gaussian_matrix(I, s, n, 7), q)
         Qe, _ = oracle.leading_left_singular_vectors(Ce, 4)
-        if q == 1:
-            assert np.linalg.norm(C - Ce) / np.linalg.norm(Ce) <= tol
+        # q = 2 too: the R-accumulated sketch Z_q Rbar is the plain product in
+        # exact arithmetic, so it carries only the format's rounding
+        assert np.linalg.norm(C - Ce) / np.linalg.norm(Ce) <= tol
         # the leading subspace: within the format's roundoff of the float64 one
         assert np.linalg.norm(Q @ Q.T - Qe @ Qe.T, 2) <= tol
 
