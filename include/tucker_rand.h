@@ -141,6 +141,13 @@ typedef struct tr_diag {
   double *const *sigma;     /* [N] -> s_n singular values of C_n, descending      */
   uint32_t *status;         /* one word; TR_DEV_* bits are OR-ed in (caller zeroes) */
   tr_timer *timer;          /* host handle from tucker_rand_timer_create, or NULL */
+  double *norms;            /* [3]: ||A||_F^2, ||G||_F^2 and the relative error
+                               RE = ||A - G x_1 Q_1 ... x_N Q_N||_F / ||A||_F of
+                               Eq. (8), as sqrt((||A||^2 - ||G||^2) / ||A||^2)
+                               (exact for orthonormal factors), all float64 from
+                               the float64 core.  ||A||^2 is the sum of mode 1's
+                               column norms when nearly-optimal sampling takes
+                               them, else one extra sweep over A.             */
 } tr_diag;
 
 /* Text for a tr_status value (static storage). */

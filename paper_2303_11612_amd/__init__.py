@@ -212,7 +212,11 @@ def _decompose_on(fn_name, A, ranks, oversample, power, prob, samples, seed, pre
             status = torch.zeros(1, dtype=torch.int32, device=A.device)
             info["status"] = status
             dstruct.status = status.data_ptr()
-        if diag and diag != "status":
+        if diag is True or diag == "norms":
+            # ||A||^2, ||G||^2, RE of Eq. (8)
+            info["norms"] = torch.zeros(3, dtype=torch.float64, device=A.device)
+            dstruct.norms = info["norms"].data_ptr()
+        if diag is True:
             # sketches and singular values for every mode
             s = [min(ranks[n] + oversample, dims[n]) for n in range(N)]
             cur = list(dims)

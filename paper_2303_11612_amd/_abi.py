@@ -39,7 +39,7 @@ class TrDiag(ctypes.Structure):
     _fields_ = [
         ("indices", POINTER(c_void_p)), ("scales", POINTER(c_void_p)),
         ("sketch", POINTER(c_void_p)), ("sigma", POINTER(c_void_p)),
-        ("status", c_void_p), ("timer", c_void_p),
+        ("status", c_void_p), ("timer", c_void_p), ("norms", c_void_p),
     ]
 
 

@@ -21,6 +21,7 @@
 #include "tr_power.hpp"
 #include "tr_lowp.hpp"
 #include "tr_stab.hpp"
+#include "tr_norms.hpp"
 #include "tr_host.hpp"
 #include "tucker_rand.h"
 
@@ -170,6 +171,8 @@ struct Plan {
   // Rbar (s x s), the factor U' of Rbar (s x mu), singular-value scratch (s)
   size_t oZn[TR_MAX_ORDER] = {}, oGA[TR_MAX_ORDER] = {}, oRst[TR_MAX_ORDER] = {},
          oRbar[TR_MAX_ORDER] = {}, oUp[TR_MAX_ORDER] = {}, oSgs[TR_MAX_ORDER] = {};
+  // partial sums of ||A||^2 for the norms / RE diagnostics
+  size_t oNparts = 0;
 };
 
 // Validates and fills the plan; returns TR_OK or an error code.
@@ -336,6 +339,7 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
   P->oX1 = take(8 * maxInter);
   P->oCore = take(8 * core_el);
   P->oSplit = take(8 * maxSplit);
+  P->oNparts = take(8 * (size_t)trk::kNormMaxParts);
   if (any_lp) {
     P->oYq = take(2 * maxYq);
     P->oTau = take(4 * 64);
@@ -962,6 +966,44 @@ int launch_gaussian_modes(const Plan& P, void* ws, hipStream_t st) {
   return check_launch();
 }
 
+// Partial sums (SQ: of squares) of n elements of x (float64, or float32 when
+// !f64) into kNormMaxParts or fewer partials; returns their count.
+int norm_parts(int64_t n) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(trk::kNormMaxParts, cdiv(n, 4 * trk::kNormNT)));
+}
+int launch_partial_sum(const void* x, bool f32, bool sq, int64_t n, double* parts,
+                       hipStream_t st) {
+  const dim3 g((unsigned)norm_parts(n)), b(trk::kNormNT);
+  if (f32 && sq)
+    hipLaunchKernelGGL((trk::k_partial_sum<float, true>), g, b, 0, st, (const float*)x, n, parts);
+  else if (sq)
+    hipLaunchKernelGGL((trk::k_partial_sum<double, true>), g, b, 0, st, (const double*)x, n,
+                       parts);
+  else
+    hipLaunchKernelGGL((trk::k_partial_sum<double, false>), g, b, 0, st, (const double*)x, n,
+                       parts);
+  return check_launch();
+}
+
+// ||A||^2, ||G||^2 and RE (Eq. (8)) into diag->norms after a decomposition:
+// ||A||^2 from the partials of mode 1's column norms when they were taken,
+// else from one sum-of-squares sweep of A; ||G||^2 from the float64 core.
+int launch_norms_re(const Plan& P, const void* A, void* ws, const tr_diag* diag,
+                    hipStream_t st) {
+  if (!diag || !diag->norms) return TR_OK;
+  const ModePlan& M0 = P.m[0];
+  const int64_t numel = M0.L * M0.I * M0.R;
+  double* parts = at<double>(ws, P.oNparts);
+  const bool have = M0.sampled && P.prob == TR_PROB_NEARLY_OPTIMAL;
+  const int np = norm_parts(have ? M0.J : numel);
+  if (!have) TR_TRY(launch_partial_sum(A, P.dtype == TR_F32, true, numel, parts, st));
+  int64_t ncore = 1;
+  for (int n = 0; n < P.N; ++n) ncore *= P.m[n].mu;
+  hipLaunchKernelGGL(trk::k_norms_re, dim3(1), dim3(trk::kNormNT), 0, st, parts, np,
+                     at<double>(ws, P.oCore), ncore, diag->norms);
+  return check_launch();
+}
+
 // Range finder of mode n on tensor X (3-D view from the plan): fills Q64 / Qt
 // of the mode in the workspace and the caller's Q (cast to dtype).
 // Sketch of mode n of tensor X (3-D view from the plan): C_n = (M M^T)^q G_n
@@ -993,6 +1035,9 @@ int range_sketch(const Plan& P, int n, const void* X, void* ws, const tr_diag* d
       TimeScope ts(tm, TR_KC_COLNORMS, n, st);
       TR_TRY(launch_colnorms(M.src_f64, X, M.L, M.I, M.R, norms, maxb, st, M.intermediate));
     }
+    // ||A||^2 for the diagnostics: the column norms of mode 1 add up to it
+    if (norms_needed && n == 0 && diag && diag->norms)
+      TR_TRY(launch_partial_sum(norms, false, false, M.J, at<double>(ws, P.oNparts), st));
     {
       TimeScope ts(tm, TR_KC_SAMPLE, n, st);
       TR_TRY(launch_sample(norms, maxb, M.J, M.T, P.prob, P.seed, n,
@@ -1230,7 +1275,7 @@ int run_thosvd(const tr_params* p, int dtype, const void* A, void* const* Q, voi
     cur = out;
     cur_f64 = true;
   }
-  return TR_OK;
+  return launch_norms_re(P, A, ws, diag, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -1287,7 +1332,7 @@ int run_sthosvd(const tr_params* p, int dtype, const void* A, void* const* Q, vo
     cur = out;
     cur_f64 = true;
   }
-  return TR_OK;
+  return launch_norms_re(P, A, ws, diag, st);
 }
 
 }  // namespace

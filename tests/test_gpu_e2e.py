@@ -98,7 +98,21 @@ def _compare(A, algo, ranks, K, q, prob="none", samples=None, seed=0, tol=None,
     re_g = oracle.relative_error(A, cg.astype(np.float64), [Q.astype(np.float64) for Q in Qg])
     re_o = oracle.relative_error(A, co, Qo)
     assert abs(re_g - re_o) <= (1e-4 if f32 else 1e-10) * max(re_o, 1e-3)
+    _check_norms(A, info, re_o)
     return Qg, cg, info
+
+
+def _check_norms(A, info, re_o):
+    """The library's ||A||^2 and RE (Eq. (8)) against the oracle's explicit
+    reconstruction.  RE comes from (||A||^2 - ||G||^2) / ||A||^2 in float64,
+    which carries an absolute error of ~1e-14 in RE^2, i.e. ~1e-14 / (2 RE) in
+    RE; the bar is 1e-13 / RE + 1e-9 RE."""
+    nrm = _np(info["norms"])
+    a2 = float(np.sum(np.asarray(A, dtype=np.float64) ** 2))
+    assert abs(nrm[0] - a2) <= 1e-12 * a2, (nrm[0], a2)
+    re = max(re_o, 1e-6)
+    assert abs(nrm[2] - re_o) <= 1e-13 / re + 1e-9 * re, (nrm[2], re_o)
+    assert abs(nrm[2] ** 2 - (1.0 - nrm[1] / nrm[0])) <= 1e-12
 
 
 def test_config1_thosvd_f64():

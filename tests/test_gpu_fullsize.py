@@ -103,6 +103,10 @@ def _fullsize_compare(A, algo, ranks, K, q, prob="none", samples=None, seed=0):
     re_g = oracle.relative_error(A, cg, Qg)
     re_o = oracle.relative_error(A, co, Qo)
     assert abs(re_g - re_o) <= (1e-7 if f32 else 1e-10), (re_g, re_o)
+    # the library's RE (Eq. (8), float64 from its float64 core) against the
+    # explicit reconstruction: ~1e-14 / (2 RE) absolute from the subtraction
+    re_lib = float(_np(info["norms"])[2])
+    assert abs(re_lib - re_o) <= 1e-13 / re_o + 1e-9 * re_o, (re_lib, re_o)
     print(f"{algo} q={q} {prob}: per mode (kappa, bar, projector distance) "
           f"{[(f'{k:.2e}', f'{b:.1e}', f'{d:.1e}') for _, k, b, d in report]}, "
           f"core {cerr:.1e}, RE {re_g:.6e} vs {re_o:.6e}")
