@@ -11,10 +11,13 @@ with nearly-optimal probabilities p_j ~ ||A_(n)(:, j)||^2.
 Prints one JSON line.  ``value`` is decompositions per second over K steps
 with nothing recorded between them; a second pass of K steps gives the
 per-step latency (event pair per step) and a third the per-kernel durations
-(HIP events on the launch stream around the timed kernel classes).  The
-roofline entry is the dominant full-tensor sweep (mode-1 column norms or
-mode-1 shrink, whichever takes longer).  The CPU baseline is the FP64 oracle
-on the same input and seed.
+(HIP events on the launch stream around every kernel class).  ``roofline``
+is the dominant kernel class by device time per step (its algorithmic bytes
+or flops per launch over its average launch time); ``sweep_roofline`` the
+longer of the two mode-1 sweeps over the whole tensor (column norms, shrink).
+RE comes from the library's float64 norms (Eq. (8)) and is cross-checked by
+an explicit float64 reconstruction.  The CPU baseline is the FP64 oracle on
+the same input and seed, with all host cores and with one.
 """
 import argparse
 import json
@@ -29,6 +32,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_TFLOPS = 78.6
 METRIC = "sketch HBM GB/s + decomps/sec at fixed rel. error; p50/p99 batched latency"
 
 
@@ -74,6 +78,24 @@ def _measured_traffic(kernel):
         return float(rec["traffic_bytes"])
     except (OSError, KeyError, ValueError):
         return None
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _factor_flops(I, s, mu):
+    """Algorithmic flops of one factorization of an I x s sketch: Householder QR
+    (2 I s^2 - 2 s^3 / 3), SVD of the s x s factor (~22 s^3 with both singular
+    vector sets, Golub & Van Loan), Q_n = Q1 [U; 0] (4 I s mu - 2 s^2 mu)."""
+    return 2 * I * s * s - 2 * s ** 3 / 3 + 22 * s ** 3 + 4 * I * s * mu - 2 * s * s * mu
 
 
 def _blas_threads():
@@ -187,20 +209,25 @@ def bench_decomp(args):
     # Pass 3: the same K steps with HIP events on the launch stream around the
     # kernels of the timed classes (each event costs a few microseconds of
     # idle device time, which is why pass 1 records none).
-    timer = tr.Timer(capacity=64 * (args.steps + 1), classes=("colnorms", "ttm", "factor"))
+    classes = ("colnorms", "ttm", "factor", "power", "sample", "gather", "gaussian")
+    timer = tr.Timer(capacity=64 * (args.steps + 1), classes=classes)
     timer.reset()
     for _ in range(args.steps):
         step(timer)
     torch.cuda.synchronize()
+    per_step = {c: timer.read(c)[0] / args.steps for c in classes}
 
     # the two full-tensor sweeps of mode 1, in algorithmic bytes per launch
+    # (counting rule: a read of the tensor at its storage dtype, plus the
+    # outputs the method needs at storage dtype; the shrink's float64
+    # intermediate, twice the size, is the library's choice and not counted)
     elem = 4
     J1 = dims[1] * dims[2]
     sweeps = {
         # column norms: read the tensor, write J_1 float64 norms
         "colnorms": (dims[0] * J1 * elem + 8 * J1, "k_colnorms_l1<float, true>"),
-        # shrink A x_1 Q_1^T: read the tensor, write mu_1 * J_1 float64 entries
-        "ttm": (dims[0] * J1 * elem + 8 * ranks[0] * J1, "k_ttm1_mfma<float, 1, 5, false, 8>"),
+        # shrink A x_1 Q_1^T: read the tensor, write mu_1/I_1 of it
+        "ttm": (dims[0] * J1 * elem + elem * ranks[0] * J1, "k_ttm1_mfma<float, 1, 5, false, 8>"),
     }
     kern = {}
     for cls, (nbytes, kname) in sweeps.items():
@@ -211,22 +238,45 @@ def bench_decomp(args):
                      "algorithmic_bytes": nbytes,
                      "achieved_GBs": nbytes / (avg0 * 1e-3) / 1e9 if avg0 > 0 else None}
     tot, cnt, tot0, cnt0 = timer.read("factor")
-    kern["factor"] = {"kernel": "k_factor_rf", "avg_ms": tot / max(cnt, 1), "launches": cnt,
+    sf = [min(ranks[n] + K, dims[n]) for n in range(N)]
+    fl = sum(_factor_flops(dims[n], sf[n], ranks[n]) for n in range(N)) / N
+    favg = tot / max(cnt, 1)
+    kern["factor"] = {"kernel": "k_factor_rf<24, 2, 16>", "avg_ms": favg, "launches": cnt,
                       "all_modes_ms_per_step": tot / args.steps,
-                      "bound": "latency (one workgroup: QR, QR of R^T, Jacobi, Q formation)"}
+                      "algorithmic_flops": fl,
+                      "bound": "latency (one workgroup per sketch: QR, QR of R^T, Jacobi, "
+                               "Q formation, each a chain of dependent steps)"}
     dom = max(sweeps, key=lambda c: kern[c]["mode1_avg_ms"])
     ach = kern[dom]["achieved_GBs"]
     traffic = _measured_traffic(kern[dom]["kernel"])
-    roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4),
-                "traffic": None if traffic is None else round(traffic),
-                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "algorithmic_bytes": kern[dom]["algorithmic_bytes"],
-                "kernel": kern[dom]["kernel"]}
+    sweep_roofline = {
+        "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(ach / HBM_PEAK_GBS, 4),
+        "traffic": None if traffic is None else round(traffic),
+        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+        "algorithmic_bytes": kern[dom]["algorithmic_bytes"],
+        "kernel": kern[dom]["kernel"]}
+    # the dominant kernel class by device time per step
+    share = {c: per_step[c] / ms_per_step for c in classes}
+    top = max(classes, key=lambda c: per_step[c])
+    if top == "factor":
+        fach = fl / (favg * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": round(fach, 6), "peak": FP64_VECTOR_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(fach / FP64_VECTOR_TFLOPS, 7),
+                    "traffic": None, "algorithmic_flops": fl, "kernel": kern["factor"]["kernel"],
+                    "note": "one workgroup per sketch; a chain of dependent steps on one "
+                            "compute unit, so latency and not throughput bounds it"}
+    else:
+        roofline = dict(sweep_roofline)
+    roofline["share_of_step"] = round(share[top], 4)
 
-    # relative error of the GPU result (orthogonal projection identity, Eq. (8))
-    nA2 = float(torch.sum(X.double() ** 2))
-    re_gpu = math.sqrt(max(0.0, 1.0 - float(torch.sum(core.double() ** 2)) / nA2))
+    # relative error of the GPU result: the library's float64 norms (Eq. (8)),
+    # and an explicit float64 reconstruction from the float32 outputs
+    _, _, info = tr.tucker_rand_sthosvd(X, ranks, K, q, w.prob, samples, args.seed,
+                                        diag="norms", stream=stream)
+    torch.cuda.synchronize()
+    re_gpu = float(info["norms"][2])
+    re_recon = _re_fp64(X, Qs, core)
 
     out = {
         "metric": METRIC, "value": round(args.steps / wall, 2), "unit": "decomp/s",
@@ -242,8 +292,11 @@ def bench_decomp(args):
         "latency_ms": {"p50": round(statistics.median(lat), 4),
                        "p99": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 4)},
         "roofline": roofline,
+        "sweep_roofline": sweep_roofline,
+        "device_ms_per_step_by_class": {c: round(per_step[c], 4) for c in classes},
         "kernels": kern,
         "re_gpu": re_gpu,
+        "re_gpu_reconstruction": re_recon,
     }
 
     if not args.no_cpu_baseline:
@@ -259,11 +312,28 @@ def bench_decomp(args):
             if time.perf_counter() - t_start > args.cpu_seconds and len(times) >= 2:
                 break
         med = statistics.median(times)
+        # one thread, as the paper times its MATLAB code (one computational thread)
+        t1s = []
+        try:
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=1, user_api="blas"):
+                t_start = time.perf_counter()
+                while True:
+                    t1 = time.perf_counter()
+                    oracle.rand_sthosvd(A64, ranks, K, q, w.prob, samples, args.seed)
+                    t1s.append(time.perf_counter() - t1)
+                    if time.perf_counter() - t_start > args.cpu_seconds / 2 or len(t1s) >= 3:
+                        break
+        except ImportError:
+            pass
         out["cpu_baseline"] = {
             "value": round(1.0 / med, 4), "unit": "decomp/s", "cores": _blas_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
             "sample": f"{len(times)} full decompositions of the same 400^3 input and seed "
-                      f"(median {med:.3f} s each), numpy float64 with multithreaded BLAS"}
+                      f"(median {med:.3f} s each), numpy float64 with multithreaded BLAS",
+            "one_thread": None if not t1s else {
+                "value": round(1.0 / statistics.median(t1s), 4), "unit": "decomp/s",
+                "cores": 1, "sample": f"{len(t1s)} decompositions, BLAS limited to one thread"}}
         Qg = [Q.double().cpu().numpy() for Q in Qs]
         cg = core.double().cpu().numpy()
         out["re_oracle"] = oracle.relative_error(A64, co, Qo)
@@ -277,7 +347,7 @@ def bench_decomp(args):
 def _re_fp64(X, Qs, core):
     """||A - core x_1 Q_1 ... x_N Q_N||_F / ||A||_F in float64 on the device (Eq. (8))."""
     import torch
-    A = X.double()
+    A = X.to(core.device).double()
     B = core.double()
     for n, Q in enumerate(Qs):
         B = torch.movedim(torch.tensordot(Q.double(), B, dims=([1], [n])), 0, n)
@@ -413,12 +483,9 @@ def bench_serving(args):
     same = all(torch.equal(a.core, b.core) and
                all(torch.equal(x, y) for x, y in zip(a.factors, b.factors))
                for a, b in zip(sat1, mix))
-    # relative Tucker error of each request: ||A||^2 - ||core||^2 (Eq. (8) with
-    # orthonormal factors), from the mix's outputs
-    re = []
-    for r, m in zip(reqs, mix):
-        nA2 = float(torch.sum(r.X.double() ** 2))
-        re.append(math.sqrt(max(0.0, 1.0 - float(torch.sum(m.core.double() ** 2)) / nA2)))
+    # relative Tucker error of each request (Eq. (8)), by explicit float64
+    # reconstruction from the mix's outputs
+    re = [_re_fp64(r.X, m.factors, m.core) for r, m in zip(reqs, mix)]
     out = {
         "workload": f"serving stream, {n} requests, modes U{{32..384}}^3 float32, ranks "
                     f"U{{4..24}}, rand ST-HOSVD + nearly-optimal sampling T_n = 4 mu_n, "
