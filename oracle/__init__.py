@@ -16,5 +16,5 @@ from .tucker import (  # noqa: F401
     canonical_signs, ceil_log2, column_sq_norms, draw_columns, fold, frobenius,
     gaussian_matrix, leading_left_singular_vectors, mode_product, power_sketch,
     power_sketch_stabilised, rand_sthosvd, rand_thosvd, randsample,
-    range_finder, reconstruct, relative_error, sampling_weights, unfold,
+    range_finder, reconstruct, related_factor, relative_error, sampling_weights, unfold,
 )

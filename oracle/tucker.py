@@ -19,6 +19,10 @@ and notation, with numpy (float64) as the only arithmetic:
 * Q_n = first mu_n left singular vectors of C_n (Remark after Alg. 5);
 * T-HOSVD core G = A x_1 Q_1^T ... x_N Q_N^T (Alg. 1 / Alg. 4);
   ST-HOSVD update A <- A x_n Q_n^T after each mode (Alg. 2 / Alg. 5);
+* the related forms (Alg. 6 for Alg. 1, Alg. 7 for Alg. 2, and by the Remark
+  closing that subsection the same change to Alg. 4 / Alg. 5): a thin QR
+  C_n = P_n R, then U_n = the mu_n leading left singular vectors of
+  P_n^T A_(n), and Q_n = P_n U_n;
 * relative error RE of Eq. (8).
 
 Readings where the paper is silent (all listed in the design notes):
@@ -235,12 +239,25 @@ def check_mode_args(I: int, J: int, mu: int, K: int, q: int, prob: str, T):
         raise ValueError("sampling needs T_n >= 1")
 
 
+def related_factor(An: np.ndarray, C: np.ndarray, mu: int):
+    """Q_n of the related forms (Alg. 6 / Alg. 7 steps 5-7): thin QR
+    C_n = P_n R (Householder, numpy), U_n = the mu leading left singular
+    vectors of C'_n = P_n^T A_(n), Q_n = P_n U_n (canonical signs).  Returns
+    (Q_n, P_n, singular values of C'_n)."""
+    P, _ = np.linalg.qr(C)
+    Cp = P.T @ An
+    U, sig, _ = np.linalg.svd(Cp, full_matrices=False)
+    return canonical_signs(P @ U[:, :mu]), P, sig
+
+
 def range_finder(X: np.ndarray, n: int, mu: int, K: int, q: int, prob: str,
-                 T: Optional[int], seed: int, stabilised: bool = False):
+                 T: Optional[int], seed: int, stabilised: bool = False,
+                 related: bool = False):
     """Q_n for mode n of the current tensor X, plus intermediates for tests.
 
     prob == "none": Alg. 1 steps 2-5 (C_n = (A_(n) A_(n)^T)^q G_n).
     otherwise:      Alg. 4 steps 2-7 (C'_n = A_(n) S_n, C_n = (C'_n C'_n^T)^q G_n).
+    related:        Q_n from C_n by the related form (``related_factor``).
     """
     An = unfold(np.asarray(X, dtype=np.float64), n)
     I, J = An.shape
@@ -265,6 +282,9 @@ def range_finder(X: np.ndarray, n: int, mu: int, K: int, q: int, prob: str,
         C = power_sketch(M, G, q)
         Q, sig = leading_left_singular_vectors(C, mu)
         info.update(C=C, sigma=sig)
+    if related:
+        Q, P, sig_cp = related_factor(An, info["C"], mu)
+        info.update(P=P, sigma_related=sig_cp)
     return Q, info
 
 
@@ -286,8 +306,9 @@ def _per_mode(v, N, name):
 
 
 def rand_thosvd(A, ranks, K: int, q: int, prob: str = PROB_NONE, samples=None,
-                seed: int = 0, stabilised: bool = False):
-    """Alg. 1 (prob == "none") or Alg. 4 (sampled): returns (Q list, core, infos)."""
+                seed: int = 0, stabilised: bool = False, related: bool = False):
+    """Alg. 1 (prob == "none") or Alg. 4 (sampled), or with ``related`` their
+    related form (Alg. 6): returns (Q list, core, infos)."""
     X = _as_f64(A)
     N = X.ndim
     ranks = _per_mode(ranks, N, "ranks")
@@ -296,7 +317,7 @@ def rand_thosvd(A, ranks, K: int, q: int, prob: str = PROB_NONE, samples=None,
     infos = []
     for n in range(N):
         Q, info = range_finder(X, n, ranks[n], K, q, prob, samples[n], seed,
-                               stabilised)
+                               stabilised, related)
         Qs.append(Q)
         infos.append(info)
     core = X
@@ -306,8 +327,9 @@ def rand_thosvd(A, ranks, K: int, q: int, prob: str = PROB_NONE, samples=None,
 
 
 def rand_sthosvd(A, ranks, K: int, q: int, prob: str = PROB_NONE, samples=None,
-                 seed: int = 0, stabilised: bool = False):
-    """Alg. 2 (prob == "none") or Alg. 5 (sampled): returns (Q list, core, infos)."""
+                 seed: int = 0, stabilised: bool = False, related: bool = False):
+    """Alg. 2 (prob == "none") or Alg. 5 (sampled), or with ``related`` their
+    related form (Alg. 7): returns (Q list, core, infos)."""
     X = _as_f64(A)
     N = X.ndim
     ranks = _per_mode(ranks, N, "ranks")
@@ -316,7 +338,7 @@ def rand_sthosvd(A, ranks, K: int, q: int, prob: str = PROB_NONE, samples=None,
     infos = []
     for n in range(N):
         Q, info = range_finder(X, n, ranks[n], K, q, prob, samples[n], seed,
-                               stabilised)
+                               stabilised, related)
         info["X_before"] = X
         X = mode_product(X, Q.T, n)              # A <- A x_n Q_n^T
         Qs.append(Q)
