@@ -129,6 +129,20 @@ typedef struct tr_params {
  */
 #define TR_FLAG_STABILIZED_POWER 0x1u
 #define TR_FLAG_UNFUSED_POWER 0x2u
+/*
+ *   TR_FLAG_RELATED_FORM: the related forms of the subsection "Related forms
+ *     for Algorithms 1 and 2" -- Alg. 6 (tucker_rand_thosvd) and Alg. 7
+ *     (tucker_rand_sthosvd), and with sampling the same change to Alg. 4 / 5
+ *     (the Remark closing that subsection): Q_n = P_n U_n where P_n is an
+ *     orthonormal basis of range(C_n) and U_n the mu_n leading left singular
+ *     vectors of P_n^T A_(n) (A_(n) the full unfolding of the mode's tensor).
+ *     P_n is the s_n left singular vectors of C_n (with
+ *     TR_FLAG_STABILIZED_POWER, Z_q); any orthonormal basis of range(C_n)
+ *     gives the same Q_n in exact arithmetic.  U_n comes from the
+ *     eigenvectors of P_n^T A_(n) A_(n)^T P_n, which one more exact power step
+ *     over the mode's tensor forms.  Singular values reported: those of C_n.
+ */
+#define TR_FLAG_RELATED_FORM 0x4u
 
 typedef struct tr_timer tr_timer;
 

@@ -18,7 +18,7 @@ PROB = {"none": 0, "nearly_optimal": 1, "uniform": 2}
 PREC = {"native": 0, "bf16": 1, "fp8e4m3": 2}
 TR_DEV_NONFINITE, TR_DEV_ZERO_DIST = 0x1, 0x2
 # tr_params.flags bits
-FLAGS = {"stabilized_power": 0x1, "unfused_power": 0x2}
+FLAGS = {"stabilized_power": 0x1, "unfused_power": 0x2, "related_form": 0x4}
 KC = {"colnorms": 0, "sample": 1, "gather": 2, "power": 3, "factor": 4, "ttm": 5,
       "gaussian": 6}
 MAX_ORDER = 8

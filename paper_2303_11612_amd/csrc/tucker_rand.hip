@@ -167,6 +167,8 @@ struct Plan {
   // TR_FLAG_STABILIZED_POWER, and always for low precision with q > 1
   bool racc = false;
   bool fused = true;  // one-sweep power steps allowed (TR_FLAG_UNFUSED_POWER clears it)
+  // related forms (Alg. 6 / Alg. 7): Q_n = P_n U_n with U_n from P_n^T A_(n)
+  bool related = false;
   // per mode: orthonormal iterate Z (I x s), factor scratch (I x s), R_i and
   // Rbar (s x s), the factor U' of Rbar (s x mu), singular-value scratch (s)
   size_t oZn[TR_MAX_ORDER] = {}, oGA[TR_MAX_ORDER] = {}, oRst[TR_MAX_ORDER] = {},
@@ -185,7 +187,9 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
       p->prob != TR_PROB_UNIFORM)
     return TR_EINVAL;
   if (p->prob != TR_PROB_NONE && !p->samples) return TR_EINVAL;
-  if (p->flags & ~(uint32_t)(TR_FLAG_STABILIZED_POWER | TR_FLAG_UNFUSED_POWER)) return TR_EINVAL;
+  if (p->flags & ~(uint32_t)(TR_FLAG_STABILIZED_POWER | TR_FLAG_UNFUSED_POWER |
+                             TR_FLAG_RELATED_FORM))
+    return TR_EINVAL;
   if (p->precision != TR_PREC_NATIVE && p->precision != TR_PREC_BF16 &&
       p->precision != TR_PREC_FP8E4M3)
     return TR_EINVAL;
@@ -193,6 +197,7 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
   P->prec = p->precision;
   P->racc = (p->flags & TR_FLAG_STABILIZED_POWER) != 0 || (lp && p->power > 1);
   P->fused = (p->flags & TR_FLAG_UNFUSED_POWER) == 0;
+  P->related = (p->flags & TR_FLAG_RELATED_FORM) != 0;
   const int N = p->order;
   P->N = N;
   P->sthosvd = sthosvd;
@@ -300,6 +305,15 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
   P->oY = take(8 * maxIs);
   P->oYt = take(8 * maxIs);
   // the float64 power steps' W and partial sketches (unused in low precision)
+  // (the related forms' Gram step is a float64 power step on the mode's tensor)
+  if (P->related) {
+    any_f64 = true;
+    for (int n = 0; n < N; ++n) {
+      const ModePlan& M = P->m[n];
+      maxZ = std::max(maxZ, (size_t)(M.J * pw_width(M.s)));
+      maxPart = std::max(maxPart, (size_t)(power_parts(M.I, M.J, M.s) * M.I * M.s));
+    }
+  }
   P->oZ = take(any_f64 ? 8 * maxZ : 8);
   P->oPart = take(any_f64 ? 8 * maxPart : 8);
   P->oNorms = take(8 * maxJs);
@@ -325,7 +339,7 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
       P->oYn[n] = take(8 * (size_t)(P->m[n].I * P->m[n].s));
       P->oSign[n] = take(8 * (size_t)P->m[n].s);
     }
-  if (P->racc)
+  if (P->racc || P->related)
     for (int n = 0; n < N; ++n) {
       const size_t Is = (size_t)(P->m[n].I * P->m[n].s), ss = (size_t)(P->m[n].s * P->m[n].s);
       P->oZn[n] = take(8 * Is);
@@ -1126,13 +1140,77 @@ trk::FactorJob rbar_job(const Plan& P, int n, double* sig, void* ws) {
 int stab_final(const Plan& P, int n, void* ws, void* Qout, const tr_diag* diag,
                hipStream_t st) {
   const ModePlan& M = P.m[n];
-  double* Cd = (diag && diag->sketch && diag->sketch[n]) ? diag->sketch[n] : nullptr;
+  // (without R-accumulation the sketch was copied out when it was formed)
+  double* Cd =
+      (P.racc && diag && diag->sketch && diag->sketch[n]) ? diag->sketch[n] : nullptr;
   const unsigned nb = (unsigned)(M.muw + (Cd ? M.s : 0));
   hipLaunchKernelGGL(trk::k_stab_final, dim3(nb), dim3(trk::kStabNT), 0, st,
                      at<double>(ws, P.oZn[n]), M.I, (int)M.s, at<double>(ws, P.oUp[n]),
                      (int)M.mu, at<double>(ws, P.oRbar[n]), at<double>(ws, P.oQ[n]),
                      at<double>(ws, P.oQt[n]), M.muw, Qout, P.dtype == TR_F32 ? 1 : 0, Cd);
   return check_launch();
+}
+
+// Related forms (Alg. 6 / Alg. 7), for k modes at once.  Step 1: P_n, an
+// orthonormal basis of range(C_n), into the mode's Z buffer and its padded
+// row-major copy into the mode's Yt (the start of the Gram's power step).
+// Without R-accumulation P_n is the s left singular vectors of the sketch
+// Y_n (one factor launch; their singular values, C_n's, go to sig); with it
+// P_n = Z_q, and the factor of Rbar gives C_n's singular values.
+int related_basis(const Plan& P, const int* modes, int k, double* const* Y, double* const* sig,
+                  void* ws, uint32_t* status, hipStream_t st) {
+  trk::FactorJob jobs[TR_MAX_ORDER];
+  for (int b = 0; b < k; ++b) {
+    const int n = modes[b];
+    const ModePlan& M = P.m[n];
+    jobs[b] = P.racc ? rbar_job(P, n, sig[b], ws)
+                     : trk::FactorJob{Y[b], at<double>(ws, P.oZn[n]), at<double>(ws, P.oYts[n]),
+                                      sig[b], nullptr, at<double>(ws, P.oGA[n]), (int)M.I,
+                                      (int)M.s, (int)M.s, M.sw};
+  }
+  TR_TRY(launch_factor_jobs(jobs, k, 0, status, st));
+  if (P.racc)
+    for (int b = 0; b < k; ++b) {
+      const ModePlan& M = P.m[modes[b]];
+      hipLaunchKernelGGL(trk::k_transpose, dim3((unsigned)cdiv(M.I * M.sw, kNT)), dim3(kNT), 0,
+                         st, at<double>(ws, P.oZn[modes[b]]), M.I, M.s, (int64_t)M.sw,
+                         at<double>(ws, P.oYts[modes[b]]));
+      TR_TRY(check_launch());
+    }
+  return TR_OK;
+}
+
+// Step 2 for mode n: the Gram matrix P_n^T A_(n) A_(n)^T P_n (s x s, into the
+// mode's R_i buffer) by one exact float64 power step over the mode's tensor X
+// (the full unfolding, also for sampled modes) and P_n^T times its result;
+// Y (I x s) is scratch.
+int related_gram(const Plan& P, int n, const void* X, double* Y, void* ws, uint32_t* status,
+                 hipStream_t st) {
+  const ModePlan& M = P.m[n];
+  TR_TRY(run_power(M.src_f64, X, M.L, M.I, M.R, nullptr, 1, M.s, M.sw, Y,
+                   at<double>(ws, P.oYts[n]), at<double>(ws, P.oZ), at<double>(ws, P.oPart),
+                   status, st, P.fused));
+  hipLaunchKernelGGL(trk::k_small_tn, dim3((unsigned)(M.s * M.s)), dim3(trk::kStabNT), 0, st,
+                     at<double>(ws, P.oZn[n]), Y, M.I, (int)M.s, at<double>(ws, P.oRst[n]));
+  return check_launch();
+}
+
+// Step 3 for k modes: U_n = the mu leading eigenvectors of the Gram matrix
+// (its left singular vectors: it is symmetric positive semidefinite), one
+// factor launch; then step 4 per mode: Q_n = P_n U_n with canonical signs.
+int related_finish(const Plan& P, const int* modes, int k, void* ws, void* const* Qout,
+                   const tr_diag* diag, uint32_t* status, hipStream_t st) {
+  trk::FactorJob jobs[TR_MAX_ORDER];
+  for (int b = 0; b < k; ++b) {
+    const int n = modes[b];
+    const ModePlan& M = P.m[n];
+    jobs[b] = trk::FactorJob{at<double>(ws, P.oRst[n]), at<double>(ws, P.oUp[n]), nullptr,
+                             at<double>(ws, P.oSgs[n]), nullptr, at<double>(ws, P.oGA[n]),
+                             (int)M.s, (int)M.s, (int)M.mu, 0};
+  }
+  TR_TRY(launch_factor_jobs(jobs, k, 0, status, st));
+  for (int b = 0; b < k; ++b) TR_TRY(stab_final(P, modes[b], ws, Qout[b], diag, st));
+  return TR_OK;
 }
 
 // Range finder of mode n (ST-HOSVD: sketch, then factor).
@@ -1144,6 +1222,14 @@ int range_finder(const Plan& P, int n, const void* X, void* ws, void* Qout,
   uint32_t* status = diag ? diag->status : nullptr;
   TimeScope ts(tm, TR_KC_FACTOR, n, st);
   double* sig = mode_sigma(P, n, diag, ws, P.oSig);
+  if (P.related) {  // Alg. 7: Q_n = P_n U_n, U_n from P_n^T A_(n)
+    double* Ys[1] = {Y};
+    double* sigs[1] = {sig};
+    TR_TRY(related_basis(P, &n, 1, Ys, sigs, ws, status, st));
+    TR_TRY(related_gram(P, n, X, Y, ws, status, st));
+    void* qo[1] = {Qout};
+    return related_finish(P, &n, 1, ws, qo, diag, status, st);
+  }
   if (P.racc) {
     const trk::FactorJob jb = rbar_job(P, n, sig, ws);
     TR_TRY(launch_factor_jobs(&jb, 1, 0, status, st));
@@ -1249,12 +1335,28 @@ int run_thosvd(const tr_params* p, int dtype, const void* A, void* const* Q, voi
       TR_TRY(stab_orth(P, modes, k, Cs, nozt, false, ws, status, st));
     }
   }
-  for (int n = 0; n < P.N; ++n) {
+  if (P.related) {
+    // Alg. 6: every mode's P_n (one launch), its Gram matrix (a power step
+    // over A each), then every mode's U_n (one launch) and Q_n = P_n U_n
+    TimeScope ts(diag ? diag->timer : nullptr, TR_KC_FACTOR, 0, st);
+    int modes[TR_MAX_ORDER];
+    double* Ys[TR_MAX_ORDER];
+    double* sigs[TR_MAX_ORDER];
+    for (int n = 0; n < P.N; ++n) {
+      modes[n] = n;
+      Ys[n] = at<double>(ws, P.oYn[n]);
+      sigs[n] = mode_sigma(P, n, diag, ws, P.oSign[n]);
+    }
+    TR_TRY(related_basis(P, modes, P.N, Ys, sigs, ws, status, st));
+    for (int n = 0; n < P.N; ++n) TR_TRY(related_gram(P, n, A, Ys[n], ws, status, st));
+    TR_TRY(related_finish(P, modes, P.N, ws, Q, diag, status, st));
+  }
+  for (int n = 0; n < P.N && !P.related; ++n) {
     double* sig = mode_sigma(P, n, diag, ws, P.oSign[n]);
     jobs[n] = P.racc ? rbar_job(P, n, sig, ws)
                      : factor_job(P, n, at<double>(ws, P.oYn[n]), sig, ws, Q[n]);
   }
-  {
+  if (!P.related) {
     TimeScope ts(diag ? diag->timer : nullptr, TR_KC_FACTOR, 0, st);
     TR_TRY(launch_factor_jobs(jobs, P.N, P.dtype == TR_F32, diag ? diag->status : nullptr, st));
     if (P.racc)

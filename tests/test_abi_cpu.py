@@ -127,6 +127,8 @@ def test_flag_bits_validated_on_host():
     assert stab > base   # per mode: the orthonormal iterate, Rbar, U'
     assert tr.tucker_rand_workspace_size((40, 30, 20), (4, 4, 4), 4, 2, "none",
                                          flags=["unfused_power"]) == base
-    for bad in (0x4, 0x8, 0x80000000):
+    assert tr.tucker_rand_workspace_size((40, 30, 20), (4, 4, 4), 4, 2, "none",
+                                         flags=["related_form"]) > base
+    for bad in (0x8, 0x10, 0x80000000):
         with pytest.raises(_abi.TuckerRandError, match="invalid argument"):
             tr.tucker_rand_workspace_size((40, 30, 20), (4, 4, 4), 4, 2, "none", flags=bad)

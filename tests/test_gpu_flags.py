@@ -110,7 +110,7 @@ def test_unfused_power_equals_fused(algo, q):
 def test_unknown_flag_bits_rejected():
     A = tr.to_device(synth.low_rank_plus_noise((20, 10, 5), (2, 2, 2), 0.1, 0))
     with pytest.raises(_abi.TuckerRandError, match="invalid argument"):
-        tr.tucker_rand_thosvd(A, (2, 2, 2), 2, 1, flags=0x4)
+        tr.tucker_rand_thosvd(A, (2, 2, 2), 2, 1, flags=0x8)
 
 
 @pytest.mark.parametrize("prob", ["none", "nearly_optimal"])
