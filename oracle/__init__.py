@@ -13,8 +13,8 @@ unpinned") except the paper's plotted numbers, which the paper never prints.
 from .philox import philox4x64  # noqa: F401
 from .tucker import (  # noqa: F401
     PROB_NEARLY_OPTIMAL, PROB_NONE, PROB_UNIFORM, TAG_GAUSS, TAG_SAMPLE,
-    canonical_signs, ceil_log2, column_sq_norms, draw_columns, fold, frobenius,
+    canonical_signs, ceil_log2, choose_rank, column_sq_norms, draw_columns, fold, frobenius,
     gaussian_matrix, leading_left_singular_vectors, mode_product, power_sketch,
-    power_sketch_stabilised, rand_sthosvd, rand_thosvd, randsample,
+    power_sketch_stabilised, rand_sthosvd, rand_thosvd, rand_tucker_adaptive, randsample,
     range_finder, reconstruct, related_factor, relative_error, sampling_weights, unfold,
 )

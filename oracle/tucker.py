@@ -358,3 +358,68 @@ def relative_error(A, core, Qs) -> float:
     """RE = ||A - A^||_F / ||A||_F, Eq. (8)."""
     A = _as_f64(A)
     return frobenius(A - reconstruct(core, Qs)) / frobenius(A)
+
+
+# --------------------------------------------------------------------------
+# Fixed-precision problem (Problem 2, Section 7): ranks chosen for a tolerance
+# --------------------------------------------------------------------------
+
+def choose_rank(lam: np.ndarray, x2: float, budget: float, mu_max: int) -> int:
+    """Smallest mu in [1, mu_max] whose residual x2 - sum_{k <= mu} lam_k is at
+    most ``budget`` (mu_max when none is).  lam: squared singular values of
+    P_n^T X_(n), descending; x2 = ||X||_F^2."""
+    for mu in range(1, mu_max + 1):
+        if x2 - float(np.sum(lam[:mu])) <= budget:
+            return mu
+    return mu_max
+
+
+def rand_tucker_adaptive(A, eps: float, max_ranks, K: int, q: int, prob: str = PROB_NONE,
+                         samples=None, seed: int = 0, sthosvd: bool = True):
+    """Problem 2 (find mu_n and orthonormal Q_n with ||A - A^||_F <= eps).
+
+    The paper poses it without an algorithm; this is the rule the library
+    implements.  Each mode is computed by the related form (Alg. 6 / Alg. 7),
+    whose P_n^T X_(n) gives the residual of every candidate rank exactly:
+    ||X x_n (I - Q_n Q_n^T)||_F^2 = ||X||_F^2 - sum_{k <= mu} sigma_k(P_n^T X_(n))^2
+    for Q_n = P_n U_n(:, 1:mu).  mu_n is the smallest rank (at most
+    min(max_ranks[n], J_n)) whose residual fits the mode's budget:
+    T-HOSVD eps^2 / N per mode (Eq. (5)); ST-HOSVD the budget left by the
+    modes before, split evenly over the remaining ones (Eq. (23)).  Returns
+    (Q list, core, chosen ranks, bound) with bound = sqrt(sum of the chosen
+    residuals) >= ||A - A^||_F (Eq. (5) / Eq. (23)).  The residuals are float64
+    differences with an absolute error of ~u ||A||^2, so tolerances below
+    ~sqrt(u) ||A|| cannot be certified."""
+    X = _as_f64(A)
+    N = X.ndim
+    max_ranks = _per_mode(max_ranks, N, "max_ranks")
+    samples = _per_mode(samples, N, "samples")
+    eps2 = float(eps) ** 2
+    used = 0.0
+    Qs, mus = [], []
+    cur = X
+    for n in range(N):
+        src = cur if sthosvd else X
+        An = unfold(src, n)
+        # the sketch width follows the largest allowed rank, s_n =
+        # min(max_rank_n + K, I_n), whatever ranks the earlier modes chose
+        # (range_finder with rank 1 and oversampling s_n - 1 draws that sketch)
+        s_n = min(max_ranks[n] + K, An.shape[0])
+        _, info = range_finder(src, n, 1, s_n - 1, q, prob, samples[n], seed)
+        P, _ = np.linalg.qr(info["C"])
+        U, sig, _ = np.linalg.svd(P.T @ An, full_matrices=False)
+        lam = sig ** 2
+        x2 = frobenius(src) ** 2
+        budget = (eps2 - used) / (N - n) if sthosvd else eps2 / N
+        mu = choose_rank(lam, x2, budget, min(max_ranks[n], An.shape[1], len(lam)))
+        used += max(x2 - float(np.sum(lam[:mu])), 0.0)
+        Q = canonical_signs(P @ U[:, :mu])
+        Qs.append(Q)
+        mus.append(mu)
+        if sthosvd:
+            cur = mode_product(cur, Q.T, n)
+    core = cur
+    if not sthosvd:
+        for n in range(N):
+            core = mode_product(core, Qs[n].T, n)
+    return Qs, core, mus, math.sqrt(used)
