@@ -204,6 +204,41 @@ int tucker_rand_sthosvd(const tr_params *p, int dtype, const void *A,
                         size_t workspace_bytes, const tr_diag *diag, void *stream);
 
 /*
+ * Fixed-precision problem (Problem 2 of Section 7): multilinear ranks mu_n
+ * and orthonormal Q_n with ||A - A x_1 Q_1 Q_1^T ... x_N Q_N Q_N^T||_F <= eps.
+ * The paper poses it without an algorithm; the rule implemented: each mode is
+ * computed by the related form (TR_FLAG_RELATED_FORM is implied), whose
+ * P_n^T X_(n) gives the residual of every rank mu <= s_n exactly,
+ * ||X||_F^2 - sum_{k <= mu} sigma_k(P_n^T X_(n))^2, and mu_n is the smallest
+ * rank whose residual fits the mode's budget -- eps^2 / N per mode for
+ * T-HOSVD (sthosvd == 0; Eq. (5)), the budget the earlier modes left split
+ * evenly over the remaining ones for ST-HOSVD (Eq. (23)) -- capped at
+ * p->ranks[n], at J_n and at s_n.
+ *   p          p->ranks[n] are the largest ranks allowed; the sketch widths are
+ *              s_n = min(p->ranks[n] + K, I_n) whatever ranks are chosen.
+ *   tol        eps (relative == 0) or eps / ||A||_F (relative == 1), > 0.
+ *   Q, core    as tucker_rand_thosvd / _sthosvd, sized for the largest ranks;
+ *              Q[n] receives I_n x mu_n (its first mu_n columns), core the
+ *              mu_1 x ... x mu_N tensor (its first prod mu_n entries).
+ *   workspace  >= tucker_rand_workspace_size(p with TR_FLAG_RELATED_FORM set,
+ *              dtype, sthosvd).
+ *   ranks_out  host [N]: the chosen mu_n.
+ *   bound_out  host: sqrt of the sum of the chosen residuals, which bounds
+ *              ||A - A^||_F by Eq. (5) / Eq. (23); above eps when even the
+ *              largest ranks do not reach the tolerance.
+ * Unlike the other calls this one waits for the device: ||A||_F^2 and each
+ * mode's s_n eigenvalues are read back (once per mode for ST-HOSVD, once for
+ * all modes for T-HOSVD), because the later shapes depend on the ranks.  The
+ * residuals are float64 differences with an absolute error of ~u ||A||_F^2,
+ * so tolerances below ~1e-7 ||A||_F cannot be certified.
+ */
+int tucker_rand_adaptive(const tr_params *p, int dtype, int sthosvd, double tol,
+                         int relative, const void *A, void *const *Q, void *core,
+                         void *workspace, size_t workspace_bytes,
+                         int64_t *ranks_out, double *bound_out,
+                         const tr_diag *diag, void *stream);
+
+/*
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): randomized
  * ST-HOSVD exactly as tucker_rand_sthosvd (same kernels, same results), with

@@ -12,6 +12,7 @@ Tensors are column-major: a tensor of shape (I_1, ..., I_N) must have strides
 from __future__ import annotations
 
 import ctypes
+import math
 from ctypes import byref, c_double, c_int64, c_size_t, c_void_p
 from typing import Optional, Sequence
 
@@ -23,7 +24,7 @@ from ._abi import KC, PREC, PROB, TR_F32, TR_F64, check, lib
 __all__ = [
     "colmajor_empty", "to_device", "is_colmajor", "Timer",
     "tucker_rand_workspace_size", "tucker_rand_thosvd", "tucker_rand_sthosvd",
-    "tucker_rand_sthosvd_noalloc",
+    "tucker_rand_sthosvd_noalloc", "tucker_rand_adaptive",
     "tucker_rand_gaussian", "tucker_rand_colnorms", "tucker_rand_sample",
     "tucker_rand_gather", "tucker_rand_power", "tucker_rand_factor",
     "tucker_rand_ttm", "tucker_rand_status_string",
@@ -284,6 +285,57 @@ def tucker_rand_sthosvd_noalloc(A: torch.Tensor, ranks, oversample=10, power=1, 
     ``diag``) for a call with no allocation on the Python side either."""
     return _decompose("tucker_rand_sthosvd_noalloc", A, ranks, oversample, power, prob,
                       samples, seed, precision, diag, timer, None, stream, out, flags)
+
+
+def tucker_rand_adaptive(A: torch.Tensor, tol: float, max_ranks, oversample=10, power=1,
+                         prob="none", samples=None, seed=0, sthosvd=True, relative=True,
+                         precision="native", flags=0, diag=False, stream=None):
+    """Fixed-precision Problem 2: ranks mu_n <= max_ranks[n] and factors with
+    ||A - A^||_F <= tol (times ||A||_F when ``relative``), by the rule of
+    tucker_rand_adaptive in include/tucker_rand.h.  Returns
+    (Q list (I_n x mu_n views), core (mu view), ranks, bound, diag dict);
+    ``bound`` is the certified bound on ||A - A^||_F.  Synchronises the stream."""
+    if not A.is_cuda or not is_colmajor(A):
+        raise ValueError("A must be a column-major device tensor")
+    st = stream if stream is not None else torch.cuda.current_stream(A.device)
+    with torch.cuda.stream(st):
+        dims = tuple(A.shape)
+        N = len(dims)
+        dt = _dtype_code(A)
+        bits = _flag_bits(flags) | _abi.FLAGS["related_form"]
+        p, keep = _params(dims, max_ranks, oversample, power, prob, samples, seed, precision,
+                          bits)
+        need = c_size_t(0)
+        check("tucker_rand_workspace_size",
+              lib().tucker_rand_workspace_size(byref(p), dt, int(bool(sthosvd)), byref(need)))
+        ws = torch.empty(max(need.value, 1), dtype=torch.uint8, device=A.device)
+        Qb = [colmajor_empty((dims[n], max_ranks[n]), A.dtype, A.device) for n in range(N)]
+        cb = torch.empty(int(math.prod(max_ranks)), dtype=A.dtype, device=A.device)
+        qptrs = (c_void_p * N)(*[q.data_ptr() for q in Qb])
+        info, dptr = {}, None
+        if diag:
+            d = _abi.TrDiag()
+            info["status"] = torch.zeros(1, dtype=torch.int32, device=A.device)
+            info["norms"] = torch.zeros(3, dtype=torch.float64, device=A.device)
+            d.status = info["status"].data_ptr()
+            d.norms = info["norms"].data_ptr()
+            dptr = byref(d)
+        ranks = (c_int64 * N)()
+        bound = c_double(0.0)
+        check("tucker_rand_adaptive",
+              lib().tucker_rand_adaptive(byref(p), dt, int(bool(sthosvd)), float(tol),
+                                         int(bool(relative)), c_void_p(A.data_ptr()), qptrs,
+                                         c_void_p(cb.data_ptr()), c_void_p(ws.data_ptr()),
+                                         c_size_t(ws.numel()), ranks, byref(bound), dptr,
+                                         _stream(st)))
+        mus = [int(r) for r in ranks]
+        Qs = [Qb[n][:, :mus[n]] for n in range(N)]
+        strides, acc = [], 1
+        for m in mus:
+            strides.append(acc)
+            acc *= m
+        core = cb.as_strided(tuple(mus), tuple(strides))
+        return Qs, core, mus, bound.value, info
 
 
 def _view3(X: torch.Tensor, L, I, R):

@@ -53,6 +53,10 @@ _SIGS = {
     "tucker_rand_sthosvd_noalloc": (c_int, [POINTER(TrParams), c_int, c_void_p,
                                             POINTER(c_void_p), c_void_p, POINTER(TrDiag),
                                             c_void_p]),
+    "tucker_rand_adaptive": (c_int, [POINTER(TrParams), c_int, c_int, c_double, c_int, c_void_p,
+                                     POINTER(c_void_p), c_void_p, c_void_p, c_size_t,
+                                     POINTER(c_int64), POINTER(c_double), POINTER(TrDiag),
+                                     c_void_p]),
     "tucker_rand_gaussian": (c_int, [c_int64, c_int64, c_int32, c_uint64, c_void_p, c_void_p]),
     "tucker_rand_colnorms": (c_int, [c_int, c_void_p, c_int64, c_int64, c_int64, c_void_p,
                                      c_void_p, c_void_p]),

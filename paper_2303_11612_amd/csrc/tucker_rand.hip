@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -173,8 +174,10 @@ struct Plan {
   // Rbar (s x s), the factor U' of Rbar (s x mu), singular-value scratch (s)
   size_t oZn[TR_MAX_ORDER] = {}, oGA[TR_MAX_ORDER] = {}, oRst[TR_MAX_ORDER] = {},
          oRbar[TR_MAX_ORDER] = {}, oUp[TR_MAX_ORDER] = {}, oSgs[TR_MAX_ORDER] = {};
-  // partial sums of ||A||^2 for the norms / RE diagnostics
-  size_t oNparts = 0;
+  // partial sums of ||A||^2 for the norms / RE diagnostics, and a small
+  // output slot (||A||^2 read back by the fixed-precision driver)
+  size_t oNparts = 0, oNout = 0;
+  size_t splitBytes = 0;  // capacity of the split-rows scratch
 };
 
 // Validates and fills the plan; returns TR_OK or an error code.
@@ -353,7 +356,9 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
   P->oX1 = take(8 * maxInter);
   P->oCore = take(8 * core_el);
   P->oSplit = take(8 * maxSplit);
+  P->splitBytes = 8 * maxSplit;
   P->oNparts = take(8 * (size_t)trk::kNormMaxParts);
+  P->oNout = take(8 * 4);
   if (any_lp) {
     P->oYq = take(2 * maxYq);
     P->oTau = take(4 * 64);
@@ -1198,8 +1203,10 @@ int related_gram(const Plan& P, int n, const void* X, double* Y, void* ws, uint3
 // Step 3 for k modes: U_n = the mu leading eigenvectors of the Gram matrix
 // (its left singular vectors: it is symmetric positive semidefinite), one
 // factor launch; then step 4 per mode: Q_n = P_n U_n with canonical signs.
-int related_finish(const Plan& P, const int* modes, int k, void* ws, void* const* Qout,
-                   const tr_diag* diag, uint32_t* status, hipStream_t st) {
+// (the eigenvalues, descending, are left in the mode's singular-value
+// scratch: the fixed-precision driver reads them)
+int related_eig(const Plan& P, const int* modes, int k, void* ws, uint32_t* status,
+                hipStream_t st) {
   trk::FactorJob jobs[TR_MAX_ORDER];
   for (int b = 0; b < k; ++b) {
     const int n = modes[b];
@@ -1208,7 +1215,12 @@ int related_finish(const Plan& P, const int* modes, int k, void* ws, void* const
                              at<double>(ws, P.oSgs[n]), nullptr, at<double>(ws, P.oGA[n]),
                              (int)M.s, (int)M.s, (int)M.mu, 0};
   }
-  TR_TRY(launch_factor_jobs(jobs, k, 0, status, st));
+  return launch_factor_jobs(jobs, k, 0, status, st);
+}
+
+int related_finish(const Plan& P, const int* modes, int k, void* ws, void* const* Qout,
+                   const tr_diag* diag, uint32_t* status, hipStream_t st) {
+  TR_TRY(related_eig(P, modes, k, ws, status, st));
   for (int b = 0; b < k; ++b) TR_TRY(stab_final(P, modes[b], ws, Qout[b], diag, st));
   return TR_OK;
 }
@@ -1259,8 +1271,12 @@ int shrink(const Plan& P, int n, int step, const void* cur, bool cur_f64, int64_
   double* dst = at<double>(ws, last ? P.oCore : ((step % 2 == 0) ? P.oX0 : P.oX1));
   {
     TimeScope ts(tm, TR_KC_TTM, n, st);
+    // (the fixed-precision driver shrinks views its plan did not size the
+    // split-rows scratch for; those run the one-pass kernels)
+    const size_t need = 8 * (size_t)(ttm_splits(L * R, I) * L * R * M.muw);
+    double* split = need <= P.splitBytes ? at<double>(ws, P.oSplit) : nullptr;
     TR_TRY(launch_ttm(cur_f64, cur, L, I, R, at<double>(ws, P.oQt[n]), M.muw, (int)M.mu,
-                      nullptr, dst, at<double>(ws, P.oSplit), st));
+                      nullptr, dst, split, st));
   }
   if (last) TR_TRY(launch_cast(dst, L * M.mu * R, P.dtype == TR_F32, core, st));
   *out = dst;
@@ -1381,6 +1397,180 @@ int run_thosvd(const tr_params* p, int dtype, const void* A, void* const* Q, voi
 }
 
 // ---------------------------------------------------------------------------
+// Fixed-precision problem (Problem 2): ranks chosen for a tolerance.
+// ---------------------------------------------------------------------------
+
+// The core chain of T-HOSVD over the plan's (possibly patched) ranks.
+int core_chain(const Plan& P, const void* A, void* ws, void* core, tr_timer* tm,
+               hipStream_t st) {
+  int64_t shp[TR_MAX_ORDER];
+  for (int k = 0; k < P.N; ++k) shp[k] = P.dims[k];
+  const void* cur = A;
+  bool cur_f64 = P.dtype == TR_F64;
+  for (int n = 0; n < P.N; ++n) {
+    int64_t L = 1, R = 1;
+    for (int k = 0; k < n; ++k) L *= shp[k];
+    for (int k = n + 1; k < P.N; ++k) R *= shp[k];
+    void* out = nullptr;
+    TR_TRY(shrink(P, n, n, cur, cur_f64, L, shp[n], R, ws, core, tm, &out, st));
+    shp[n] = P.m[n].mu;
+    cur = out;
+    cur_f64 = true;
+  }
+  return TR_OK;
+}
+
+// Reads `count` doubles from the device (synchronising the stream).
+int read_back(const double* dev, double* host, int count, hipStream_t st) {
+  if (hipMemcpyAsync(host, dev, 8 * (size_t)count, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return TR_EDEVICE;
+  return TR_OK;
+}
+
+// Smallest mu in [1, cap] with x2 - sum_{k <= mu} lam_k <= budget (cap when
+// none is); *resid receives that residual (clamped at 0).
+int64_t choose_rank(const double* lam, int64_t cap, double x2, double budget, double* resid) {
+  double acc = 0.0;
+  for (int64_t mu = 1; mu <= cap; ++mu) {
+    acc += lam[mu - 1];
+    if (x2 - acc <= budget || mu == cap) {
+      *resid = std::max(x2 - acc, 0.0);
+      return mu;
+    }
+  }
+  *resid = x2;
+  return cap;
+}
+
+// After the ranks of modes 0..done are chosen, the views of the later modes
+// (ST-HOSVD) follow the shrunk tensor; a sampled mode whose columns no
+// longer outnumber its samples becomes exact.
+void repatch_views(Plan& P, int done, int64_t T_of_mode(const tr_params*, int),
+                   const tr_params* p) {
+  int64_t cur[TR_MAX_ORDER];
+  for (int k = 0; k < P.N; ++k) cur[k] = k <= done ? P.m[k].mu : P.dims[k];
+  for (int n = done + 1; n < P.N; ++n) {
+    ModePlan& M = P.m[n];
+    M.L = 1;
+    M.R = 1;
+    for (int k = 0; k < n; ++k) M.L *= cur[k];
+    for (int k = n + 1; k < P.N; ++k) M.R *= cur[k];
+    M.J = M.L * M.R;
+    const int64_t T = T_of_mode(p, n);
+    M.sampled = P.prob != TR_PROB_NONE && T >= 1 && T <= M.J;
+    M.T = M.sampled ? T : 0;
+  }
+}
+
+int64_t samples_of(const tr_params* p, int n) {
+  return (p->prob != TR_PROB_NONE && p->samples) ? p->samples[n] : 0;
+}
+
+int run_adaptive(const tr_params* p0, int dtype, bool sthosvd, double tol, int relative,
+                 const void* A, void* const* Q, void* core, void* ws, size_t ws_bytes,
+                 int64_t* ranks_out, double* bound_out, const tr_diag* diag, hipStream_t st) {
+  if (!(tol > 0.0) || (relative != 0 && relative != 1) || !ranks_out || !bound_out)
+    return TR_EINVAL;
+  if (!p0) return TR_EINVAL;
+  tr_params p = *p0;
+  p.flags |= TR_FLAG_RELATED_FORM;
+  Plan P;
+  TR_TRY(make_plan(&p, dtype, sthosvd, &P));
+  TR_TRY(check_buffers(P, A, Q, core, ws, ws_bytes));
+  uint32_t* status = diag ? diag->status : nullptr;
+  tr_timer* tm = diag ? diag->timer : nullptr;
+  const int N = P.N;
+  int64_t mumax[TR_MAX_ORDER];
+  for (int n = 0; n < N; ++n) mumax[n] = P.m[n].mu;
+  // ||A||^2 (one sum-of-squares sweep), read back
+  const ModePlan& M0 = P.m[0];
+  const int64_t numel = M0.L * M0.I * M0.R;
+  double* out3 = at<double>(ws, P.oNout);
+  TR_TRY(launch_partial_sum(A, dtype == TR_F32, true, numel, at<double>(ws, P.oNparts), st));
+  hipLaunchKernelGGL(trk::k_norms_re, dim3(1), dim3(trk::kNormNT), 0, st,
+                     at<double>(ws, P.oNparts), norm_parts(numel), at<double>(ws, P.oCore),
+                     (int64_t)0, out3);
+  TR_TRY(check_launch());
+  double h3[3];
+  TR_TRY(read_back(out3, h3, 3, st));
+  const double a2 = h3[0];
+  const double eps2 = relative ? tol * tol * a2 : tol * tol;
+  {
+    TimeScope ts(tm, TR_KC_GAUSSIAN, 0, st);
+    TR_TRY(launch_gaussian_modes(P, ws, st));
+  }
+  double lam[64];
+  double used = 0.0;
+  if (!sthosvd) {
+    // every mode from A: sketches, bases, Gram matrices and their
+    // eigenvalues for all modes, one read-back, then the chosen factors
+    int modes[TR_MAX_ORDER];
+    double* Ys[TR_MAX_ORDER];
+    double* sigs[TR_MAX_ORDER];
+    bool xmax_ready = false;
+    for (int n = 0; n < N; ++n) {
+      TR_TRY(range_sketch(P, n, A, ws, diag, !xmax_ready, at<double>(ws, P.oYn[n]), st));
+      // an unsampled mode in FP8 has taken the tensor's max |entry|
+      if (!P.m[n].sampled) xmax_ready = true;
+      modes[n] = n;
+      Ys[n] = at<double>(ws, P.oYn[n]);
+      sigs[n] = mode_sigma(P, n, diag, ws, P.oSign[n]);
+    }
+    TimeScope ts(tm, TR_KC_FACTOR, 0, st);
+    TR_TRY(related_basis(P, modes, N, Ys, sigs, ws, status, st));
+    for (int n = 0; n < N; ++n) TR_TRY(related_gram(P, n, A, Ys[n], ws, status, st));
+    TR_TRY(related_eig(P, modes, N, ws, status, st));
+    for (int n = 0; n < N; ++n) {
+      ModePlan& M = P.m[n];
+      TR_TRY(read_back(at<double>(ws, P.oSgs[n]), lam, (int)M.s, st));
+      double r2 = 0.0;
+      const int64_t cap = std::min<int64_t>(std::min<int64_t>(mumax[n], M.J), M.s);
+      M.mu = choose_rank(lam, cap, a2, eps2 / N, &r2);
+      M.muw = pad_width(M.mu);
+      used += r2;
+      TR_TRY(stab_final(P, n, ws, Q[n], diag, st));
+    }
+    TR_TRY(core_chain(P, A, ws, core, tm, st));
+  } else {
+    const void* cur = A;
+    bool cur_f64 = dtype == TR_F64;
+    double x2 = a2;  // ||current tensor||^2
+    for (int n = 0; n < N; ++n) {
+      ModePlan& M = P.m[n];
+      double* Y = at<double>(ws, P.oY);
+      TR_TRY(range_sketch(P, n, cur, ws, diag, true, Y, st));
+      {
+        TimeScope ts(tm, TR_KC_FACTOR, n, st);
+        double* Ys[1] = {Y};
+        double* sigs[1] = {mode_sigma(P, n, diag, ws, P.oSig)};
+        TR_TRY(related_basis(P, &n, 1, Ys, sigs, ws, status, st));
+        TR_TRY(related_gram(P, n, cur, Y, ws, status, st));
+        TR_TRY(related_eig(P, &n, 1, ws, status, st));
+      }
+      TR_TRY(read_back(at<double>(ws, P.oSgs[n]), lam, (int)M.s, st));
+      double r2 = 0.0;
+      const int64_t cap = std::min<int64_t>(std::min<int64_t>(mumax[n], M.J), M.s);
+      M.mu = choose_rank(lam, cap, x2, (eps2 - used) / (N - n), &r2);
+      M.muw = pad_width(M.mu);
+      used += r2;
+      double kept = 0.0;
+      for (int64_t k = 0; k < M.mu; ++k) kept += lam[k];
+      x2 = kept;
+      TR_TRY(stab_final(P, n, ws, Q[n], diag, st));
+      void* out = nullptr;
+      TR_TRY(shrink(P, n, n, cur, cur_f64, M.L, M.I, M.R, ws, core, tm, &out, st));
+      cur = out;
+      cur_f64 = true;
+      repatch_views(P, n, samples_of, &p);
+    }
+  }
+  for (int n = 0; n < N; ++n) ranks_out[n] = P.m[n].mu;
+  *bound_out = std::sqrt(used);
+  return launch_norms_re(P, A, ws, diag, st);
+}
+
+// ---------------------------------------------------------------------------
 // Fixed device scratch for callers that cannot allocate (tucker_rand_sthosvd_
 // noalloc).  Each device that loads the library holds one copy of the array
 // for the life of the process; its device address is looked up once per
@@ -1487,6 +1677,14 @@ int tucker_rand_sthosvd_noalloc(const tr_params* p, int dtype, const void* A, vo
   void* ws = nullptr;
   TR_TRY(scratch_address(st, &ws));
   return run_sthosvd(p, dtype, A, Q, core, ws, (size_t)TR_NOALLOC_SCRATCH_BYTES, diag, st);
+}
+
+int tucker_rand_adaptive(const tr_params* p, int dtype, int sthosvd, double tol, int relative,
+                         const void* A, void* const* Q, void* core, void* workspace,
+                         size_t workspace_bytes, int64_t* ranks_out, double* bound_out,
+                         const tr_diag* diag, void* stream) {
+  return run_adaptive(p, dtype, sthosvd != 0, tol, relative, A, Q, core, workspace,
+                      workspace_bytes, ranks_out, bound_out, diag, (hipStream_t)stream);
 }
 
 int tucker_rand_gaussian(int64_t I, int64_t s, int32_t mode, uint64_t seed, double* G,

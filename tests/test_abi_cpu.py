@@ -132,3 +132,17 @@ def test_flag_bits_validated_on_host():
     for bad in (0x8, 0x10, 0x80000000):
         with pytest.raises(_abi.TuckerRandError, match="invalid argument"):
             tr.tucker_rand_workspace_size((40, 30, 20), (4, 4, 4), 4, 2, "none", flags=bad)
+
+
+def test_adaptive_arguments_validated_on_host():
+    # tol <= 0, relative outside {0, 1} or missing outputs: TR_EINVAL before
+    # anything is launched (no device pointer is touched)
+    p, _keep = tr._params((20, 16, 12), (4, 4, 4), 4, 1, "none", None, 0, "native")
+    ranks = (ctypes.c_int64 * 3)()
+    bound = ctypes.c_double()
+    qp = (ctypes.c_void_p * 3)(1, 1, 1)
+    for tol, rel in ((0.0, 1), (-1.0, 0), (0.1, 2)):
+        rc = _abi.lib().tucker_rand_adaptive(ctypes.byref(p), 0, 1, tol, rel, ctypes.c_void_p(1),
+                                             qp, ctypes.c_void_p(1), ctypes.c_void_p(1), 1 << 30,
+                                             ranks, ctypes.byref(bound), None, None)
+        assert rc == _abi.TR_EINVAL
