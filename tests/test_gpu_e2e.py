@@ -98,20 +98,27 @@ def _compare(A, algo, ranks, K, q, prob="none", samples=None, seed=0, tol=None,
     re_g = oracle.relative_error(A, cg.astype(np.float64), [Q.astype(np.float64) for Q in Qg])
     re_o = oracle.relative_error(A, co, Qo)
     assert abs(re_g - re_o) <= (1e-4 if f32 else 1e-10) * max(re_o, 1e-3)
-    _check_norms(A, info, re_o)
+    _check_norms(A, info, re_o, re_g, f32)
     return Qg, cg, info
 
 
-def _check_norms(A, info, re_o):
-    """The library's ||A||^2 and RE (Eq. (8)) against the oracle's explicit
-    reconstruction.  RE comes from (||A||^2 - ||G||^2) / ||A||^2 in float64,
-    which carries an absolute error of ~1e-14 in RE^2, i.e. ~1e-14 / (2 RE) in
-    RE; the bar is 1e-13 / RE + 1e-9 RE."""
+def _check_norms(A, info, re_o, re_g, f32):
+    """The library's ||A||^2 and RE (Eq. (8)) against the explicit
+    reconstruction of its own outputs.  RE comes from (||A||^2 - ||G||^2) /
+    ||A||^2 in float64, which carries an absolute error of ~1e-14 in RE^2,
+    i.e. ~1e-14 / (2 RE) in RE: for float64 outputs the bar is
+    1e-13 / RE + 1e-9 RE.  Float32 outputs are rounded after the library's
+    float64 core and factors, which moves the reconstruction's RE by about
+    u32 (N + 1) ||A|| / ||A|| -- the bar there is 3e-7 absolute.  (Against the
+    oracle's decomposition RE agrees only as well as the factors do: ||G||^2
+    changes to first order with Q_n, whose weakest kept directions carry the
+    sketch's conditioning; that comparison is the one above, on re_g.)"""
     nrm = _np(info["norms"])
     a2 = float(np.sum(np.asarray(A, dtype=np.float64) ** 2))
     assert abs(nrm[0] - a2) <= 1e-12 * a2, (nrm[0], a2)
-    re = max(re_o, 1e-6)
-    assert abs(nrm[2] - re_o) <= 1e-13 / re + 1e-9 * re, (nrm[2], re_o)
+    re = max(re_g, 1e-6)
+    bar = 3e-7 if f32 else 1e-13 / re + 1e-9 * re
+    assert abs(nrm[2] - re_g) <= bar, (nrm[2], re_g, re_o)
     assert abs(nrm[2] ** 2 - (1.0 - nrm[1] / nrm[0])) <= 1e-12
 
 

@@ -60,10 +60,10 @@ def _projector_dist(Qa, Qb):
     return float(max(da, db))
 
 
-def _fullsize_compare(A, algo, ranks, K, q, prob="none", samples=None, seed=0):
+def _fullsize_compare(A, algo, ranks, K, q, prob="none", samples=None, seed=0, flags=0):
     f = tr.tucker_rand_thosvd if algo == "thosvd" else tr.tucker_rand_sthosvd
     X = tr.to_device(A)
-    Qs, core, info = f(X, ranks, K, q, prob, samples, seed, diag=True)
+    Qs, core, info = f(X, ranks, K, q, prob, samples, seed, diag=True, flags=flags)
     torch.cuda.synchronize()
     del X
     Qg = [_np(Q).astype(np.float64) for Q in Qs]
@@ -104,9 +104,10 @@ def _fullsize_compare(A, algo, ranks, K, q, prob="none", samples=None, seed=0):
     re_o = oracle.relative_error(A, co, Qo)
     assert abs(re_g - re_o) <= (1e-7 if f32 else 1e-10), (re_g, re_o)
     # the library's RE (Eq. (8), float64 from its float64 core) against the
-    # explicit reconstruction: ~1e-14 / (2 RE) absolute from the subtraction
+    # explicit reconstruction of its own outputs: ~1e-14 / (2 RE) absolute
+    # from the subtraction, plus the outputs' float32 rounding (3e-7)
     re_lib = float(_np(info["norms"])[2])
-    assert abs(re_lib - re_o) <= 1e-13 / re_o + 1e-9 * re_o, (re_lib, re_o)
+    assert abs(re_lib - re_g) <= (3e-7 if f32 else 1e-13 / re_g + 1e-9 * re_g), (re_lib, re_g)
     print(f"{algo} q={q} {prob}: per mode (kappa, bar, projector distance) "
           f"{[(f'{k:.2e}', f'{b:.1e}', f'{d:.1e}') for _, k, b, d in report]}, "
           f"core {cerr:.1e}, RE {re_g:.6e} vs {re_o:.6e}")

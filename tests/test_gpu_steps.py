@@ -179,6 +179,35 @@ def test_power_products_wide_sketch(dtype, s):
     assert np.linalg.norm(C - want) <= 1e-12 * np.linalg.norm(want)
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("s", [12, 20, 32])
+def test_power_products_rows_past_128(dtype, s):
+    """Rows past the one-sweep kernel's 128 (144 to 512, not multiples of 16),
+    L = 1 and L > 1 views, a ragged last column tile, q = 1 and 2, plain and
+    column-weighted: the two-product form at these widths."""
+    for shape in ((144, 300, 7), (512, 21, 9), (129, 17, 40), (400, 33, 12), (257, 6, 11)):
+        A = _rand_tensor(shape, dtype, 13)
+        X = tr.to_device(A)
+        for n, L, I, R in _views(shape):
+            if I <= 128 or s > I:
+                continue
+            for q in (1, 2):
+                G = oracle.gaussian_matrix(I, s, n, 7)
+                M = oracle.unfold(A.astype(np.float64), n)
+                C = _np(tr.tucker_rand_power(X, L, I, R, tr.to_device(G), q))
+                want = oracle.power_sketch(M, G, q)
+                assert np.linalg.norm(C - want) <= 1e-12 * np.linalg.norm(want), (shape, n, q)
+    I, T = 333, 1001
+    Cp = _rand_tensor((I, T), dtype, 14)
+    d = np.random.default_rng(3).random(T) + 0.5
+    G = oracle.gaussian_matrix(I, s, 0, 5)
+    C = _np(tr.tucker_rand_power(tr.to_device(Cp), 1, I, T, tr.to_device(G), 2,
+                                 torch.tensor(d, device=DEV)))
+    Ms = Cp.astype(np.float64) * np.sqrt(d)[None, :]
+    want = oracle.power_sketch(Ms, G, 2)
+    assert np.linalg.norm(C - want) <= 1e-12 * np.linalg.norm(want)
+
+
 def _graded(I, s, seed, decay=0.6):
     rng = np.random.default_rng(seed)
     U = np.linalg.qr(rng.standard_normal((I, s)))[0]
