@@ -239,6 +239,42 @@ int tucker_rand_adaptive(const tr_params *p, int dtype, int sthosvd, double tol,
                          const tr_diag *diag, void *stream);
 
 /*
+ * Batched randomized ST-HOSVD with sampled products (Alg. 5) for the serving
+ * path: nreq independent requests of the same order N but different sizes,
+ * ranks, sample counts and seeds advance through the modes together, and
+ * every stage of a mode (column norms, weights and prefix sums, draws, gather,
+ * power products, factorization, shrink) is one grouped launch over all of
+ * them, driven by per-request descriptors the call writes to the start of the
+ * workspace -- about eight launches per mode for the whole batch.  Each
+ * request's arithmetic does not depend on the rest of the batch, so its
+ * result is bitwise the same alone or in any batch (it is not bitwise the
+ * same as tucker_rand_sthosvd, whose kernels sum in other orders).  A mode
+ * whose T_n exceeds J_n takes every column once with weight 1 (the exact
+ * product), as tucker_rand_sthosvd does.
+ *   p          [nreq] host pointers to each request's parameters: the same
+ *              order N, prob TR_PROB_NEARLY_OPTIMAL or TR_PROB_UNIFORM,
+ *              precision native, flags 0.  Supported for I_n <= 512,
+ *              s_n <= 48, mu_n <= 32, min(T_n, J_n) <= 8192 and
+ *              J_n <= 2^20 per mode (else TR_ENOTSUP).
+ *   dtype      storage type of every A, Q and core.
+ *   A, Q, core host arrays [nreq] of device pointers (Q[r] is a host array [N]
+ *              of device pointers), laid out as for tucker_rand_sthosvd.
+ *   workspace  >= tucker_rand_batch_workspace_size(nreq, p, dtype, ...) bytes.
+ *   status     device [nreq] (may be NULL): TR_DEV_* bits OR-ed into word r for
+ *              request r (the caller zeroes them).
+ * The call copies the descriptor table to the workspace synchronously with
+ * respect to the host (after the stream's earlier work), then enqueues the
+ * launches; a caller that overlaps batches gives each its own stream.
+ */
+int tucker_rand_batch_workspace_size(int nreq, const tr_params *const *p, int dtype,
+                                     size_t *bytes);
+int tucker_rand_sthosvd_batch(int nreq, const tr_params *const *p, int dtype,
+                              const void *const *A, void *const *const *Q,
+                              void *const *core, void *workspace,
+                              size_t workspace_bytes, uint32_t *status,
+                              void *stream);
+
+/*
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): randomized
  * ST-HOSVD exactly as tucker_rand_sthosvd (same kernels, same results), with

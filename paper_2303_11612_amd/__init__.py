@@ -25,6 +25,7 @@ __all__ = [
     "colmajor_empty", "to_device", "is_colmajor", "Timer",
     "tucker_rand_workspace_size", "tucker_rand_thosvd", "tucker_rand_sthosvd",
     "tucker_rand_sthosvd_noalloc", "tucker_rand_adaptive",
+    "BatchRequest", "tucker_rand_batch_workspace_size", "tucker_rand_sthosvd_batch",
     "tucker_rand_gaussian", "tucker_rand_colnorms", "tucker_rand_sample",
     "tucker_rand_gather", "tucker_rand_power", "tucker_rand_factor",
     "tucker_rand_ttm", "tucker_rand_status_string",
@@ -285,6 +286,87 @@ def tucker_rand_sthosvd_noalloc(A: torch.Tensor, ranks, oversample=10, power=1, 
     ``diag``) for a call with no allocation on the Python side either."""
     return _decompose("tucker_rand_sthosvd_noalloc", A, ranks, oversample, power, prob,
                       samples, seed, precision, diag, timer, None, stream, out, flags)
+
+
+class BatchRequest:
+    """One request of tucker_rand_sthosvd_batch: a column-major device tensor
+    and its parameters (sampled products, Alg. 5)."""
+
+    def __init__(self, A, ranks, samples, oversample=10, power=1, prob="nearly_optimal",
+                 seed=0):
+        self.A, self.ranks, self.samples = A, tuple(ranks), tuple(samples)
+        self.oversample, self.power, self.prob, self.seed = oversample, power, prob, seed
+
+    def params(self, dims=None):
+        return _params(tuple(dims if dims is not None else self.A.shape), self.ranks,
+                       self.oversample, self.power, self.prob, self.samples, self.seed,
+                       "native")
+
+
+def _batch_params(reqs, dims=None):
+    ps, keep = [], []
+    for i, r in enumerate(reqs):
+        p, k = r.params(None if dims is None else dims[i])
+        ps.append(p)
+        keep.append(k)
+    arr = (ctypes.POINTER(_abi.TrParams) * len(ps))(*[ctypes.pointer(p) for p in ps])
+    return arr, (ps, keep)
+
+
+def tucker_rand_batch_workspace_size(reqs, dtype=torch.float32, dims=None) -> int:
+    """Bytes of workspace tucker_rand_sthosvd_batch needs for these requests
+    (``dims``: their shapes, when the tensors are not given yet)."""
+    arr, _keep = _batch_params(reqs, dims)
+    out = c_size_t(0)
+    check("tucker_rand_batch_workspace_size",
+          lib().tucker_rand_batch_workspace_size(len(reqs), arr, _DT[dtype], byref(out)))
+    return out.value
+
+
+def tucker_rand_sthosvd_batch(reqs, workspace=None, stream=None, status=True, out=None):
+    """Randomized ST-HOSVD with sampled products (Alg. 5) for a batch of
+    requests of one order and dtype, every stage one grouped launch.  Returns
+    (list of Q lists, list of cores, status tensor [nreq] or None).  The
+    descriptor copy synchronises the host with the stream's earlier work."""
+    if not reqs:
+        raise ValueError("empty batch")
+    A0 = reqs[0].A
+    dt = _dtype_code(A0)
+    for r in reqs:
+        if not r.A.is_cuda or not is_colmajor(r.A):
+            raise ValueError("every A must be a column-major device tensor")
+        if r.A.dtype != A0.dtype or r.A.dim() != A0.dim():
+            raise ValueError("every request needs the same dtype and order")
+    st = stream if stream is not None else torch.cuda.current_stream(A0.device)
+    arr, keep = _batch_params(reqs)
+    need = c_size_t(0)
+    check("tucker_rand_batch_workspace_size",
+          lib().tucker_rand_batch_workspace_size(len(reqs), arr, dt, byref(need)))
+    with torch.cuda.stream(st):
+        # (a workspace the caller passes is used as it is: the library rejects
+        # one that is too small)
+        if workspace is None:
+            workspace = torch.empty(max(need.value, 1), dtype=torch.uint8, device=A0.device)
+        if out is None:
+            Qs = [[colmajor_empty((r.A.shape[n], r.ranks[n]), r.A.dtype, r.A.device)
+                   for n in range(r.A.dim())] for r in reqs]
+            cores = [colmajor_empty(r.ranks, r.A.dtype, r.A.device) for r in reqs]
+        else:
+            Qs, cores = out
+        stat = torch.zeros(len(reqs), dtype=torch.int32, device=A0.device) if status else None
+    nreq, N = len(reqs), A0.dim()
+    qrows = [(c_void_p * N)(*[q.data_ptr() for q in Qs[i]]) for i in range(nreq)]
+    qtab = (ctypes.POINTER(c_void_p) * nreq)(
+        *[ctypes.cast(q, ctypes.POINTER(c_void_p)) for q in qrows])
+    atab = (c_void_p * nreq)(*[r.A.data_ptr() for r in reqs])
+    ctab = (c_void_p * nreq)(*[c.data_ptr() for c in cores])
+    check("tucker_rand_sthosvd_batch",
+          lib().tucker_rand_sthosvd_batch(nreq, arr, dt, atab, qtab, ctab,
+                                          c_void_p(workspace.data_ptr()),
+                                          c_size_t(workspace.numel()), _ptr(stat),
+                                          _stream(st)))
+    del keep
+    return Qs, cores, stat
 
 
 def tucker_rand_adaptive(A: torch.Tensor, tol: float, max_ranks, oversample=10, power=1,

@@ -57,6 +57,12 @@ _SIGS = {
                                      POINTER(c_void_p), c_void_p, c_void_p, c_size_t,
                                      POINTER(c_int64), POINTER(c_double), POINTER(TrDiag),
                                      c_void_p]),
+    "tucker_rand_batch_workspace_size": (c_int, [c_int, POINTER(POINTER(TrParams)), c_int,
+                                                 POINTER(c_size_t)]),
+    "tucker_rand_sthosvd_batch": (c_int, [c_int, POINTER(POINTER(TrParams)), c_int,
+                                          POINTER(c_void_p), POINTER(POINTER(c_void_p)),
+                                          POINTER(c_void_p), c_void_p, c_size_t, c_void_p,
+                                          c_void_p]),
     "tucker_rand_gaussian": (c_int, [c_int64, c_int64, c_int32, c_uint64, c_void_p, c_void_p]),
     "tucker_rand_colnorms": (c_int, [c_int, c_void_p, c_int64, c_int64, c_int64, c_void_p,
                                      c_void_p, c_void_p]),

@@ -13,12 +13,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 # translation units, compiled in parallel and linked into one library: the
-# host driver, the factor kernel instances and the low-precision power steps
+# host driver, the factor kernel instances, the low-precision power steps and
+# the batched driver
 SOURCES = [
     # one unit per factor kernel instance (FactorVariant 0 .. 15), the slowest
     ("tr_factor_inst.hip", (f"-DTR_FACTOR_INST={k}",)) for k in range(16)] + [
     ("tr_lowp_launch.hip", ()), ("tucker_rand.hip", ()), ("tr_factor_launch.hip", ()),
-    ("tr_pw_fused.hip", ())]
+    ("tr_pw_fused.hip", ()), ("tr_batch.hip", ())]
 SRC = os.path.join(CSRC, "tucker_rand.hip")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libtucker_rand.so")

@@ -28,6 +28,19 @@ int factor_rf_jobs(const trk::FactorJobs& jobs, int n, int cast_f32, uint32_t* s
   return check_launch();
 }
 
+template <int SM, int R, int MU>
+int factor_rf_tab(const trk::FactorJob* tab, int n, int cast_f32, uint32_t* const* status_tab,
+                  hipStream_t st) {
+  const size_t lds = trk::RfShape<SM>::lds_bytes();
+  if (lds > 65536 &&
+      hipFuncSetAttribute((const void*)&trk::k_factor_rf_tab<SM, R, MU>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return TR_EDEVICE;
+  hipLaunchKernelGGL((trk::k_factor_rf_tab<SM, R, MU>), dim3((unsigned)n),
+                     dim3(trk::RfShape<SM>::NT), lds, st, tab, cast_f32, status_tab);
+  return check_launch();
+}
+
 template <int SM, bool G>
 int factor_k_jobs(const trk::FactorJobs& jobs, int n, int cast_f32, uint32_t* status,
                   hipStream_t st) {
@@ -86,6 +99,10 @@ int launch_factor_kRf48x2(const trk::FactorJobs& jobs, int n, int cast_f32, uint
                       hipStream_t st) {
   return factor_rf_jobs<48, 2, 32>(jobs, n, cast_f32, status, st);
 }
+int launch_factor_tab_kRf48x2(const trk::FactorJob* tab, int n, int cast_f32,
+                         uint32_t* const* status_tab, hipStream_t st) {
+  return factor_rf_tab<48, 2, 32>(tab, n, cast_f32, status_tab, st);
+}
 #endif
 #if TR_FACTOR_INST == 6
 static_assert(kLds16 == 6, "instance numbering");
@@ -142,6 +159,10 @@ int launch_factor_kRf24x2(const trk::FactorJobs& jobs, int n, int cast_f32, uint
                       hipStream_t st) {
   return factor_rf_jobs<24, 2, 16>(jobs, n, cast_f32, status, st);
 }
+int launch_factor_tab_kRf24x2(const trk::FactorJob* tab, int n, int cast_f32,
+                         uint32_t* const* status_tab, hipStream_t st) {
+  return factor_rf_tab<24, 2, 16>(tab, n, cast_f32, status_tab, st);
+}
 #endif
 #if TR_FACTOR_INST == 14
 static_assert(kRf40x1 == 14, "instance numbering");
@@ -155,6 +176,10 @@ static_assert(kRf40x2 == 15, "instance numbering");
 int launch_factor_kRf40x2(const trk::FactorJobs& jobs, int n, int cast_f32, uint32_t* status,
                       hipStream_t st) {
   return factor_rf_jobs<40, 2, 32>(jobs, n, cast_f32, status, st);
+}
+int launch_factor_tab_kRf40x2(const trk::FactorJob* tab, int n, int cast_f32,
+                         uint32_t* const* status_tab, hipStream_t st) {
+  return factor_rf_tab<40, 2, 32>(tab, n, cast_f32, status_tab, st);
 }
 #endif
 

@@ -142,11 +142,10 @@ __device__ __forceinline__ void householder(double alpha, double sum2, double* b
   }
 }
 
-// Workgroup b factors jobs.j[b] (several independent sketches per launch).
+// One factorization by the calling workgroup.
 template <int SM, int R, int MU>
-__global__ void __launch_bounds__(256)
-k_factor_rf(FactorJobs jobs, int cast_f32, uint32_t* __restrict__ status) {
-  const FactorJob& jb = jobs.j[blockIdx.x];
+__device__ __forceinline__ void factor_rf_body(const FactorJob& jb, int cast_f32,
+                                               uint32_t* __restrict__ status) {
   const double* __restrict__ C = jb.C;
   const int I = jb.I, s = jb.s, mu = jb.mu, ldqt = jb.ldqt;
   double* __restrict__ Q = jb.Q;
@@ -504,6 +503,23 @@ k_factor_rf(FactorJobs jobs, int cast_f32, uint32_t* __restrict__ status) {
         for (int c = mu; c < ldqt; ++c) Qt[(int64_t)i * ldqt + c] = 0.0;
     }
   }
+}
+
+// Workgroup b factors jobs.j[b] (several independent sketches per launch).
+template <int SM, int R, int MU>
+__global__ void __launch_bounds__(256)
+k_factor_rf(FactorJobs jobs, int cast_f32, uint32_t* __restrict__ status) {
+  factor_rf_body<SM, R, MU>(jobs.j[blockIdx.x], cast_f32, status);
+}
+
+// Jobs from a device table (the batched driver, whose batches outnumber the
+// kernel-argument job list): workgroup b factors tab[b] and reports to
+// status_tab[b] (no status when status_tab is null).
+template <int SM, int R, int MU>
+__global__ void __launch_bounds__(256)
+k_factor_rf_tab(const FactorJob* __restrict__ tab, int cast_f32, uint32_t* const* status_tab) {
+  factor_rf_body<SM, R, MU>(tab[blockIdx.x], cast_f32,
+                            status_tab ? status_tab[blockIdx.x] : nullptr);
 }
 
 }  // namespace trk

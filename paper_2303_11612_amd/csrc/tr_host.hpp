@@ -79,4 +79,15 @@ int launch_pw_fused(bool f64, const void* X, int64_t L, int64_t I, int64_t R,
 int launch_factor_group(int var, const trk::FactorJobs& jobs, int n, int cast_f32,
                         uint32_t* status, hipStream_t st);
 
+// Factorizations whose jobs sit in a device table (n workgroups), in the
+// register-resident instances for up to 512 rows: kRf24x2, kRf40x2, kRf48x2.
+// status_tab (device, may be null): one status word pointer per job.  In
+// tr_factor_inst.hip (those instances' units).
+int launch_factor_tab_kRf24x2(const trk::FactorJob* tab, int n, int cast_f32,
+                              uint32_t* const* status_tab, hipStream_t st);
+int launch_factor_tab_kRf40x2(const trk::FactorJob* tab, int n, int cast_f32,
+                              uint32_t* const* status_tab, hipStream_t st);
+int launch_factor_tab_kRf48x2(const trk::FactorJob* tab, int n, int cast_f32,
+                              uint32_t* const* status_tab, hipStream_t st);
+
 }  // namespace trh

@@ -160,13 +160,15 @@ __device__ __forceinline__ unsigned long long block_exscan_u64(
   return before + inc - v;
 }
 
-static __global__ void __launch_bounds__(kNT)
-k_weights(const double* __restrict__ norms, int64_t J,
-          const unsigned long long* __restrict__ max_bits, int kexp, int uniform,
-          unsigned long long* __restrict__ w, unsigned long long* __restrict__ bsum,
-          uint32_t* __restrict__ status) {
+// Chunk `blk` of the weights (the calling workgroup; every thread calls).
+__device__ __forceinline__ void weights_block(const double* __restrict__ norms, int64_t J,
+                                              const unsigned long long* __restrict__ max_bits,
+                                              int kexp, int uniform,
+                                              unsigned long long* __restrict__ w,
+                                              unsigned long long* __restrict__ bsum,
+                                              uint32_t* __restrict__ status, int64_t blk) {
   __shared__ unsigned long long scr[kNT / kWave];
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  const int64_t base = blk * kScanChunk;
   double M = 0.0;
   bool bad = false;
   if (!uniform) {
@@ -196,9 +198,17 @@ k_weights(const double* __restrict__ norms, int64_t J,
     }
   }
   const unsigned long long t = block_sum_u64(local, scr);
-  if (threadIdx.x == 0) bsum[blockIdx.x] = t;
-  if (bad && status && blockIdx.x == 0 && threadIdx.x == 0)
+  if (threadIdx.x == 0) bsum[blk] = t;
+  if (bad && status && blk == 0 && threadIdx.x == 0)
     atomicOr(status, isfinite(M) ? kDevZeroDist : (kDevNonFinite | kDevZeroDist));
+}
+
+static __global__ void __launch_bounds__(kNT)
+k_weights(const double* __restrict__ norms, int64_t J,
+          const unsigned long long* __restrict__ max_bits, int kexp, int uniform,
+          unsigned long long* __restrict__ w, unsigned long long* __restrict__ bsum,
+          uint32_t* __restrict__ status) {
+  weights_block(norms, J, max_bits, kexp, uniform, w, bsum, status, blockIdx.x);
 }
 
 // In-place exclusive scan of the block sums (one workgroup of 1024 threads).
@@ -223,12 +233,14 @@ k_scan_bsum(unsigned long long* __restrict__ bsum, int64_t nb) {
 // offset (the scanned block sums), or with `raw` the block sums themselves:
 // block b then adds up those of blocks 0 .. b-1 itself (exact integer sums;
 // used for a few blocks, where it saves the scan launch).
-static __global__ void __launch_bounds__(kNT)
-k_cdf(const unsigned long long* __restrict__ w, const unsigned long long* __restrict__ boff,
-      int raw, int64_t J, unsigned long long* __restrict__ cdf) {
+// Chunk `blk` of the inclusive prefix sums (the calling workgroup).
+__device__ __forceinline__ void cdf_block(const unsigned long long* __restrict__ w,
+                                          const unsigned long long* __restrict__ boff, int raw,
+                                          int64_t J, unsigned long long* __restrict__ cdf,
+                                          int64_t blk) {
   __shared__ unsigned long long scr[kNT / kWave];
   constexpr int E = kScanChunk / kNT;
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * E;
+  const int64_t base = blk * kScanChunk + (int64_t)threadIdx.x * E;
   unsigned long long v[E];
   unsigned long long local = 0;
 #pragma unroll
@@ -239,10 +251,10 @@ k_cdf(const unsigned long long* __restrict__ w, const unsigned long long* __rest
   unsigned long long off;
   if (raw) {
     unsigned long long part = 0;
-    for (int64_t k = threadIdx.x; k < (int64_t)blockIdx.x; k += kNT) part += boff[k];
+    for (int64_t k = threadIdx.x; k < blk; k += kNT) part += boff[k];
     off = block_sum_u64(part, scr);
   } else {
-    off = boff[blockIdx.x];
+    off = boff[blk];
   }
   unsigned long long total;
   unsigned long long run = off + block_exscan_u64(local, scr, &total);
@@ -253,15 +265,19 @@ k_cdf(const unsigned long long* __restrict__ w, const unsigned long long* __rest
   }
 }
 
+static __global__ void __launch_bounds__(kNT)
+k_cdf(const unsigned long long* __restrict__ w, const unsigned long long* __restrict__ boff,
+      int raw, int64_t J, unsigned long long* __restrict__ cdf) {
+  cdf_block(w, boff, raw, J, cdf, blockIdx.x);
+}
+
 // One thread per draw t: x = floor((h 2^64 + l) W / 2^128) exactly, then the
 // first j with cdf_j > x, and the rescale sqrt((W / w_j) / T).  Also stores
 // scale^2 (the column weight of C' C'^T).
-static __global__ void __launch_bounds__(kNT)
-k_draw(const unsigned long long* __restrict__ cdf, int64_t J, int64_t T, uint64_t seed,
-       uint64_t mode, int uniform, int64_t* __restrict__ idx, double* __restrict__ scale,
-       double* __restrict__ scale2) {
-  const int64_t t = (int64_t)blockIdx.x * kNT + threadIdx.x;
-  if (t >= T) return;
+__device__ __forceinline__ void draw_one(const unsigned long long* __restrict__ cdf, int64_t J,
+                                         int64_t T, uint64_t seed, uint64_t mode, int uniform,
+                                         int64_t* __restrict__ idx, double* __restrict__ scale,
+                                         double* __restrict__ scale2, int64_t t) {
   const unsigned long long W = uniform ? (unsigned long long)J : cdf[J - 1];
   const U64x4 r = philox4x64_10((uint64_t)(t / 2), mode, kTagSample, 0, seed, 0);
   const uint64_t h = r.w[2 * (t & 1)], l = r.w[2 * (t & 1) + 1];
@@ -289,8 +305,16 @@ k_draw(const unsigned long long* __restrict__ cdf, int64_t J, int64_t T, uint64_
   double sc = 0.0;
   if (wj > 0) sc = sqrt(((double)W / (double)wj) / (double)T);
   idx[t] = j;
-  scale[t] = sc;
+  if (scale) scale[t] = sc;
   if (scale2) scale2[t] = sc * sc;
+}
+
+static __global__ void __launch_bounds__(kNT)
+k_draw(const unsigned long long* __restrict__ cdf, int64_t J, int64_t T, uint64_t seed,
+       uint64_t mode, int uniform, int64_t* __restrict__ idx, double* __restrict__ scale,
+       double* __restrict__ scale2) {
+  const int64_t t = (int64_t)blockIdx.x * kNT + threadIdx.x;
+  if (t < T) draw_one(cdf, J, T, seed, mode, uniform, idx, scale, scale2, t);
 }
 
 // ---------------------------------------------------------------------------

@@ -146,3 +146,44 @@ def test_adaptive_arguments_validated_on_host():
                                              qp, ctypes.c_void_p(1), ctypes.c_void_p(1), 1 << 30,
                                              ranks, ctypes.byref(bound), None, None)
         assert rc == _abi.TR_EINVAL
+
+
+def _breq(ranks, samples, prob="nearly_optimal", oversample=4, power=1, seed=0):
+    return tr.BatchRequest(None, ranks, samples, oversample, power, prob, seed)
+
+
+def test_batch_workspace_and_limits_on_host():
+    a = _breq((4, 4, 3), (300, 200, 100))
+    b = _breq((6, 5, 5), (900, 400, 50), prob="uniform", seed=3)
+    one = tr.tucker_rand_batch_workspace_size([a], dims=[(40, 30, 20)])
+    two = tr.tucker_rand_batch_workspace_size([a, b], dims=[(40, 30, 20), (64, 48, 32)])
+    assert 0 < one < two
+    # T_n > J_n is accepted (the exact product for that mode)
+    assert tr.tucker_rand_batch_workspace_size([_breq((4, 4, 3), (5000, 5000, 5000))],
+                                               dims=[(40, 30, 20)]) > 0
+
+    def code(reqs, dims, dtype=torch.float32):
+        with pytest.raises(_abi.TuckerRandError) as e:
+            tr.tucker_rand_batch_workspace_size(reqs, dtype, dims)
+        return e.value.code
+
+    # mixed orders, prob none, a bad rank: invalid or unsupported, before any launch
+    assert code([a, _breq((2, 2), (10, 10))], [(40, 30, 20), (8, 8)]) == _abi.TR_EINVAL
+    assert code([_breq((4, 4, 3), (300, 200, 100), prob="none")], [(40, 30, 20)]) == \
+        _abi.TR_ENOTSUP
+    assert code([_breq((41, 4, 3), (300, 200, 100))], [(40, 30, 20)]) == _abi.TR_EINVAL
+    # the grouped kernels' limits: I_n <= 512, s_n <= 48, min(T_n, J_n) <= 8192
+    assert code([_breq((4, 4, 3), (300, 200, 100))], [(600, 20, 20)]) == _abi.TR_ENOTSUP
+    assert code([_breq((40, 4, 3), (300, 200, 100), oversample=10)], [(100, 60, 50)]) == \
+        _abi.TR_ENOTSUP
+    assert code([_breq((4, 4, 3), (9000, 200, 100))], [(100, 100, 100)]) == _abi.TR_ENOTSUP
+    L = _abi.lib()
+    out = ctypes.c_size_t()
+    assert L.tucker_rand_batch_workspace_size(0, None, 0, ctypes.byref(out)) == _abi.TR_EINVAL
+    arr, _keep = tr._batch_params([a], [(40, 30, 20)])
+    assert L.tucker_rand_batch_workspace_size(1, arr, 5, ctypes.byref(out)) == _abi.TR_EINVAL
+    # null tensors are rejected before anything is copied or launched
+    nul = (ctypes.c_void_p * 1)(None)
+    qn = (ctypes.POINTER(ctypes.c_void_p) * 1)(None)
+    assert L.tucker_rand_sthosvd_batch(1, arr, 1, nul, qn, nul, None, 0, None, None) == \
+        _abi.TR_EINVAL
