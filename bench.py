@@ -56,6 +56,8 @@ def _parse():
     ap.add_argument("--budget-gb", type=float, default=16.0)
     ap.add_argument("--load", type=float, default=0.7,
                     help="arrival rate as a fraction of the one-at-a-time throughput")
+    ap.add_argument("--max-group", type=int, default=64,
+                    help="largest group of the grouped serving backend")
     ap.add_argument("--source", choices=("device", "host"), default="device")
     ap.add_argument("--oracle-requests", type=int, default=8)
     ap.add_argument("--copy-probe", action="store_true",
@@ -133,7 +135,10 @@ def main():
 
     if args.workload == "serving":
         srv = bench_serving(args)
-        cap = srv["saturated_throughput_rps"]["batched"]
+        caps = srv["saturated_throughput_rps"]
+        best = max(("batched", "grouped"), key=lambda k: caps[k])
+        cap = caps[best]
+        srv["workload"] += f"; value: the {best} server's saturated throughput"
         out = {"metric": METRIC, "value": cap,
                "unit": "requests/s", "n_gpus": 1, "steps": srv["requests"], "warmup": 0,
                "ms_per_step": round(1e3 / cap, 4),
@@ -434,7 +439,10 @@ def bench_serving(args):
     """The request stream: modes U{32..384}, ranks U{4..24}, T_n = 4 mu_n,
     nearly-optimal sampling, q = 1, K = 10, Poisson arrivals at `load` times
     the one-at-a-time throughput; one slot (one request at a time) against
-    `slots` concurrent slots under an HBM budget, on the same arrivals."""
+    `slots` concurrent slots under an HBM budget (one request per stream,
+    "batched") and against `slots` grouped slots (a group of admitted requests
+    per stream, every stage one launch for the group, "grouped"), on the same
+    arrivals, and again at the grouped server's own capacity."""
     import numpy as np
     import torch
     import synth
@@ -455,18 +463,21 @@ def bench_serving(args):
     t_gen = time.perf_counter() - t_gen
     budget = int(args.budget_gb * (1 << 30))
 
-    def serve(slots, arrivals):
+    def serve(slots, arrivals, grouped=False):
         for r, a in zip(reqs, arrivals):
             r.arrival = float(a)
-        server = sv.Server(sv.GpuBackend(slots), slots=slots, hbm_budget=budget)
+        be = sv.GroupedBackend(slots, args.max_group) if grouped else sv.GpuBackend(slots)
+        server = sv.Server(be, slots=slots, hbm_budget=budget)
         res = server.run(reqs)
-        return res, server.peak_used
+        return res, server
 
     # warm-up: kernels loaded and allocator pools filled for every slot
     warm = reqs[:2 * args.slots]
     for r in warm:
         r.arrival = 0.0
     sv.Server(sv.GpuBackend(args.slots), slots=args.slots, hbm_budget=budget).run(warm)
+    sv.Server(sv.GroupedBackend(args.slots, args.max_group), slots=args.slots,
+              hbm_budget=budget).run(reqs[:4 * args.slots])
     torch.cuda.synchronize()
 
     zero = np.zeros(n)
@@ -474,10 +485,19 @@ def bench_serving(args):
     cap1 = sv.summarize(sat1)["throughput_rps"]
     satS, _ = serve(args.slots, zero)
     capS = sv.summarize(satS)["throughput_rps"]
+    satG, srvG = serve(args.slots, zero, grouped=True)
+    capG = sv.summarize(satG)["throughput_rps"]
+    sat_groups = srvG.group_sizes
     rate = args.load * cap1
     arr = sv.poisson_arrivals(n, rate, seed=args.seed + 7)
     one, _ = serve(1, arr)
-    mix, peak = serve(args.slots, arr)
+    mix, srvS = serve(args.slots, arr)
+    peak = srvS.peak_used
+    grp, srvG = serve(args.slots, arr, grouped=True)
+    # a second stream at the grouped server's own saturation point
+    arr_hi = sv.poisson_arrivals(n, args.load * capG, seed=args.seed + 8)
+    grp_hi, srvH = serve(args.slots, arr_hi, grouped=True)
+    mix_hi, _ = serve(args.slots, arr_hi)
 
     # results alone (one slot, no overlap) against results in the mix: bitwise
     same = all(torch.equal(a.core, b.core) and
@@ -486,6 +506,15 @@ def bench_serving(args):
     # relative Tucker error of each request (Eq. (8)), by explicit float64
     # reconstruction from the mix's outputs
     re = [_re_fp64(r.X, m.factors, m.core) for r, m in zip(reqs, mix)]
+    re_g = [_re_fp64(r.X, m.factors, m.core) for r, m in zip(reqs, grp)]
+    # grouped results: bitwise the same in any group (each of the first
+    # requests again, alone)
+    k_alone = min(16, n)
+    alone_g = sv.Server(sv.GroupedBackend(1, 1), slots=1, hbm_budget=budget).run(
+        [sv.Request(r.rid, r.X, r.ranks, r.samples, seed=r.seed) for r in reqs[:k_alone]])
+    same_g = all(torch.equal(a.core, b.core) and
+                 all(torch.equal(x, y) for x, y in zip(a.factors, b.factors))
+                 for a, b in zip(alone_g, grp[:k_alone]))
     out = {
         "workload": f"serving stream, {n} requests, modes U{{32..384}}^3 float32, ranks "
                     f"U{{4..24}}, rand ST-HOSVD + nearly-optimal sampling T_n = 4 mu_n, "
@@ -494,12 +523,24 @@ def bench_serving(args):
         "hbm_budget_bytes": budget, "peak_admitted_bytes": int(peak),
         "mean_tensor_MB": round(sum(r.X.numel() * 4 for r in reqs) / n / 1e6, 2),
         "arrival_rate_rps": round(rate, 2),
-        "saturated_throughput_rps": {"one_at_a_time": cap1, "batched": capS},
+        "saturated_throughput_rps": {"one_at_a_time": cap1, "batched": capS,
+                                     "grouped": capG},
+        "saturated_group_sizes": {"groups": len(sat_groups),
+                                  "mean": round(float(np.mean(sat_groups)), 2),
+                                  "max": int(max(sat_groups))},
         "one_at_a_time": sv.summarize(one),
         "batched": sv.summarize(mix),
-        "all_status_ok": all(m.status == 0 for m in mix),
+        "grouped": sv.summarize(grp),
+        "grouped_mean_group": round(float(np.mean(srvG.group_sizes)), 2),
+        "at_grouped_load": {"arrival_rate_rps": round(args.load * capG, 2),
+                            "grouped": sv.summarize(grp_hi),
+                            "batched": sv.summarize(mix_hi),
+                            "grouped_mean_group": round(float(np.mean(srvH.group_sizes)), 2)},
+        "all_status_ok": all(m.status == 0 for m in mix + grp + grp_hi + mix_hi),
         "mix_equals_alone_bitwise": bool(same),
+        "grouped_equals_alone_bitwise": {"requests": k_alone, "ok": bool(same_g)},
         "rel_error": {"mean": float(np.mean(re)), "max": float(np.max(re))},
+        "grouped_rel_error_max_abs_diff": float(np.max(np.abs(np.array(re_g) - np.array(re)))),
         "generation_s": round(t_gen, 2),
     }
     if args.oracle_requests > 0:

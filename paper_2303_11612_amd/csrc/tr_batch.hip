@@ -116,7 +116,10 @@ int plan_request(const tr_params* p, int N, RPlan* P) {
 
 // Kernels of a mode whose block maps are kept: colnorms, weights / cdf
 // (chunks), draw, gather, shrink.
-enum { kMapNorm = 0, kMapChunk, kMapDraw, kMapGather, kMapShrink, kMaps };
+// kMapM16, kMapM32: the first mode's shrink on the matrix cores, for Q^T rows
+// of stride <= 16 and <= 32.
+enum { kMapNorm = 0, kMapChunk, kMapDraw, kMapGather, kMapPwW, kMapPwY, kMapShrink, kMapM16,
+       kMapM32, kMaps };
 
 struct Layout {
   size_t oMd, oGj, oFj, oSt, oMaps, descBytes, reqBase, total;
@@ -171,15 +174,32 @@ int factor_tab(const std::vector<RPlan>& P, int n, const trk::FactorJob* tab, in
   return launch_factor_tab_kRf48x2(tab, nreq, cast_f32, sttab, st);
 }
 
+template <int SM>
+void power_steps(int nreq, const trk::BMode* md, const int64_t* mw, int64_t bw,
+                 const int64_t* my, int64_t by, int qmax, hipStream_t st) {
+  for (int step = 0; step < qmax; ++step) {
+    hipLaunchKernelGGL(trk::kb_pw_w<SM>, dim3((unsigned)bw), dim3(trk::kNT), 0, st, md, mw,
+                       nreq, step);
+    hipLaunchKernelGGL(trk::kb_pw_y, dim3((unsigned)by), dim3(trk::kNT), 0, st, md, my, nreq,
+                       step);
+  }
+}
+
 template <typename Tin>
 void launch_mode(int n, int nreq, const trk::BMode* md, const int64_t* maps,
-                 const std::vector<int64_t> (&nb)[kMaps], int any_nearly, hipStream_t st) {
+                 const std::vector<int64_t> (&nb)[kMaps], int any_nearly, int smax, int qmax,
+                 hipStream_t st) {
   const int64_t* mp = maps + (size_t)n * kMaps * (nreq + 1);
   auto mapk = [&](int k) { return mp + (size_t)k * (nreq + 1); };
   if (any_nearly) {
-    if (nb[kMapNorm].back() > 0)
-      hipLaunchKernelGGL(trk::kb_colnorms<Tin>, dim3((unsigned)nb[kMapNorm].back()),
-                         dim3(trk::kNT), 0, st, md, mapk(kMapNorm), nreq);
+    if (nb[kMapNorm].back() > 0) {
+      if (n == 0)
+        hipLaunchKernelGGL(trk::kb_colnorms_l1<Tin>, dim3((unsigned)nb[kMapNorm].back()),
+                           dim3(trk::kNT), 0, st, md, mapk(kMapNorm), nreq);
+      else
+        hipLaunchKernelGGL(trk::kb_colnorms<Tin>, dim3((unsigned)nb[kMapNorm].back()),
+                           dim3(trk::kNT), 0, st, md, mapk(kMapNorm), nreq);
+    }
     if (nb[kMapChunk].back() > 0) {
       hipLaunchKernelGGL(trk::kb_weights, dim3((unsigned)nb[kMapChunk].back()), dim3(trk::kNT),
                          0, st, md, mapk(kMapChunk), nreq);
@@ -191,7 +211,13 @@ void launch_mode(int n, int nreq, const trk::BMode* md, const int64_t* maps,
                      md, mapk(kMapDraw), nreq);
   hipLaunchKernelGGL(trk::kb_gather<Tin>, dim3((unsigned)nb[kMapGather].back()), dim3(trk::kNT),
                      0, st, md, mapk(kMapGather), nreq);
-  hipLaunchKernelGGL(trk::kb_power, dim3((unsigned)nreq), dim3(trk::kNT), 0, st, md);
+  const int64_t bw = nb[kMapPwW].back(), by = nb[kMapPwY].back();
+  if (smax <= 16)
+    power_steps<16>(nreq, md, mapk(kMapPwW), bw, mapk(kMapPwY), by, qmax, st);
+  else if (smax <= 32)
+    power_steps<32>(nreq, md, mapk(kMapPwW), bw, mapk(kMapPwY), by, qmax, st);
+  else
+    power_steps<48>(nreq, md, mapk(kMapPwW), bw, mapk(kMapPwY), by, qmax, st);
 }
 
 template <typename Tin, typename Tout, int MU>
@@ -199,6 +225,19 @@ void shrink_k(int nreq, const trk::BMode* md, const int64_t* map, int64_t blocks
               hipStream_t st) {
   hipLaunchKernelGGL((trk::kb_shrink<Tin, Tout, MU>), dim3((unsigned)blocks), dim3(trk::kNT), 0,
                      st, md, map, nreq, last);
+}
+
+// The first mode: one launch per output tile count (16 or 32 rows of Q^T).
+template <typename Tin, typename Tout>
+void shrink_first(int nreq, const trk::BMode* md, const int64_t* maps,
+                  const std::vector<int64_t> (&nb)[kMaps], int last, hipStream_t st) {
+  const dim3 b(trk::kNT);
+  if (nb[kMapM16].back() > 0)
+    hipLaunchKernelGGL((trk::kb_shrink_mfma<Tin, Tout, 1>), dim3((unsigned)nb[kMapM16].back()),
+                       b, 0, st, md, maps + (size_t)kMapM16 * (nreq + 1), nreq, last);
+  if (nb[kMapM32].back() > 0)
+    hipLaunchKernelGGL((trk::kb_shrink_mfma<Tin, Tout, 2>), dim3((unsigned)nb[kMapM32].back()),
+                       b, 0, st, md, maps + (size_t)kMapM32 * (nreq + 1), nreq, last);
 }
 
 template <typename Tin, typename Tout>
@@ -234,7 +273,7 @@ int run_batch(int nreq, const tr_params* const* p, int dtype, const void* const*
   uint32_t** stt = reinterpret_cast<uint32_t**>(hd(Lo.oSt));
   int64_t* maps = reinterpret_cast<int64_t*>(hd(Lo.oMaps));
   int64_t gt = 0;
-  int any_nearly = 0, mumax[TR_MAX_ORDER] = {};
+  int any_nearly = 0, mumax[TR_MAX_ORDER] = {}, smax[TR_MAX_ORDER] = {}, qmax = 0;
   std::vector<int64_t> nb[TR_MAX_ORDER][kMaps];
   for (int r = 0; r < nreq; ++r) stt[r] = status ? status + r : nullptr;
   for (int n = 0; n < N; ++n) {
@@ -246,6 +285,8 @@ int run_batch(int nreq, const tr_params* const* p, int dtype, const void* const*
       const bool nearly = p[r]->prob == TR_PROB_NEARLY_OPTIMAL && M.sampled;
       any_nearly |= nearly ? 1 : 0;
       mumax[n] = std::max(mumax[n], M.mu);
+      smax[n] = std::max(smax[n], M.s);
+      qmax = std::max(qmax, p[r]->power);
       trk::BMode& d = md[(size_t)n * nreq + r];
       d.X = n == 0 ? A[r] : at<double>(base, (n % 2 == 1) ? R.oX0 : R.oX1);
       d.L = M.L;
@@ -290,7 +331,10 @@ int run_batch(int nreq, const tr_params* const* p, int dtype, const void* const*
       nb[n][kMapChunk][r + 1] = nearly ? d.nchunk : 0;
       nb[n][kMapDraw][r + 1] = cdiv(M.Tp, trk::kNT);
       nb[n][kMapGather][r + 1] = M.Tp * rc;
-      nb[n][kMapShrink][r + 1] = cdiv(M.J, trk::kNT);
+      nb[n][kMapPwW][r + 1] = cdiv(M.Tp, trk::kPwCols);
+      nb[n][kMapPwY][r + 1] = cdiv(M.I * M.s, trk::kNT);
+      nb[n][kMapShrink][r + 1] = n == 0 ? 0 : cdiv(M.J, trk::kNT);
+      if (n == 0) nb[n][M.ldq <= 16 ? kMapM16 : kMapM32][r + 1] = cdiv(M.J, trk::kSmCols);
     }
     for (int k = 0; k < kMaps; ++k) {
       int64_t* mp = maps + ((size_t)n * kMaps + k) * (nreq + 1);
@@ -318,18 +362,21 @@ int run_batch(int nreq, const tr_params* const* p, int dtype, const void* const*
   for (int n = 0; n < N; ++n) {
     const trk::BMode* mdn = dmd + (size_t)n * nreq;
     if (n == 0 && f32)
-      launch_mode<float>(n, nreq, mdn, dmaps, nb[n], any_nearly, st);
+      launch_mode<float>(n, nreq, mdn, dmaps, nb[n], any_nearly, smax[n], qmax, st);
     else
-      launch_mode<double>(n, nreq, mdn, dmaps, nb[n], any_nearly, st);
+      launch_mode<double>(n, nreq, mdn, dmaps, nb[n], any_nearly, smax[n], qmax, st);
     TR_TRY(check_launch());
     TR_TRY(factor_tab(P, n, dfj + (size_t)n * nreq, nreq, f32 ? 1 : 0,
                       status ? dst : nullptr, st));
     const int64_t* smap = dmaps + ((size_t)n * kMaps + kMapShrink) * (nreq + 1);
+    const int64_t* fmaps = dmaps + (size_t)n * kMaps * (nreq + 1);
     const int64_t blocks = nb[n][kMapShrink].back();
     const int last = n + 1 == N;
     if (n == 0 && f32) {
-      if (last) shrink_mu<float, float>(mumax[n], nreq, mdn, smap, blocks, 1, st);
-      else shrink_mu<float, double>(mumax[n], nreq, mdn, smap, blocks, 0, st);
+      if (last) shrink_first<float, float>(nreq, mdn, fmaps, nb[n], 1, st);
+      else shrink_first<float, double>(nreq, mdn, fmaps, nb[n], 0, st);
+    } else if (n == 0) {
+      shrink_first<double, double>(nreq, mdn, fmaps, nb[n], last, st);
     } else if (f32) {
       if (last) shrink_mu<double, float>(mumax[n], nreq, mdn, smap, blocks, 1, st);
       else shrink_mu<double, double>(mumax[n], nreq, mdn, smap, blocks, 0, st);

@@ -121,15 +121,16 @@ struct FiberChunkV {
 // VEC: the chunks are loaded 16 bytes at a time (I a multiple of 16/sizeof(T),
 // X 16-byte aligned).
 // ---------------------------------------------------------------------------
+// Columns [256 blk, 256 blk + 256) of the view, by the calling workgroup
+// (tile and scr: its LDS buffers).
 template <typename T, bool VEC>
-__global__ void __launch_bounds__(kNT)
-k_colnorms_l1(const T* __restrict__ X, int64_t I, int64_t J,
-              double* __restrict__ norms, unsigned long long* __restrict__ max_bits) {
+__device__ __forceinline__ void colnorms_l1_block(
+    const T* __restrict__ X, int64_t I, int64_t J, double* __restrict__ norms,
+    unsigned long long* __restrict__ max_bits, int64_t blk,
+    T (*tile)[kNT + 1], unsigned long long* scr) {
   constexpr int TI = RowsPerChunk<T>::value;
-  __shared__ T tile[TI][kNT + 1];
-  __shared__ unsigned long long scr[kNT / kWave];
   const int c = threadIdx.x;
-  const int64_t j0 = (int64_t)blockIdx.x * kNT;
+  const int64_t j0 = blk * kNT;
   const int ncol = (int)min((int64_t)kNT, J - j0);
   const T* base = X + j0 * I;
   double acc = 0.0;
@@ -154,6 +155,15 @@ k_colnorms_l1(const T* __restrict__ X, int64_t I, int64_t J,
   }
   if (c < ncol) norms[j0 + c] = acc;
   if (max_bits) block_max_bits(c < ncol ? acc : 0.0, max_bits, scr);
+}
+
+template <typename T, bool VEC>
+__global__ void __launch_bounds__(kNT)
+k_colnorms_l1(const T* __restrict__ X, int64_t I, int64_t J,
+              double* __restrict__ norms, unsigned long long* __restrict__ max_bits) {
+  __shared__ T tile[RowsPerChunk<T>::value][kNT + 1];
+  __shared__ unsigned long long scr[kNT / kWave];
+  colnorms_l1_block<T, VEC>(X, I, J, norms, max_bits, blockIdx.x, tile, scr);
 }
 
 template <typename T>

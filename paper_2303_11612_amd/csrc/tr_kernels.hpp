@@ -341,14 +341,16 @@ k_gather(const T* __restrict__ X, int64_t L, int64_t I, const int64_t* __restric
 // branches.  Outputs k < kout are written with row stride kout (kout = mu for
 // a mode product; kout = MU keeps the zero padding for the power steps).
 // ---------------------------------------------------------------------------
-template <typename Tin, int MU>
-__global__ void __launch_bounds__(kNT)
-k_ttm_l1(const Tin* __restrict__ X, int64_t I, int64_t R, const double* __restrict__ Qt,
-         int kout, const double* __restrict__ colscale, double* __restrict__ Y) {
+// Columns [256 blk, 256 blk + 256) by the calling workgroup (tile: its LDS).
+template <typename Tin, int MU, typename Tout = double>
+__device__ __forceinline__ void ttm_l1_block(const Tin* __restrict__ X, int64_t I, int64_t R,
+                                             const double* __restrict__ Qt, int kout,
+                                             const double* __restrict__ colscale,
+                                             Tout* __restrict__ Y, int64_t blk,
+                                             Tin (*tile)[kNT + 1]) {
   constexpr int TI = RowsPerChunk<Tin>::value;
-  __shared__ Tin tile[TI][kNT + 1];
   const int c = threadIdx.x;
-  const int64_t j0 = (int64_t)blockIdx.x * kNT;
+  const int64_t j0 = blk * kNT;
   const int ncol = (int)min((int64_t)kNT, R - j0);
   const Tin* base = X + j0 * I;
   double acc[MU];
@@ -371,8 +373,16 @@ k_ttm_l1(const Tin* __restrict__ X, int64_t I, int64_t R, const double* __restri
     const double d = colscale ? colscale[j] : 1.0;
 #pragma unroll
     for (int k = 0; k < MU; ++k)
-      if (k < kout) Y[k + (int64_t)kout * j] = acc[k] * d;
+      if (k < kout) Y[k + (int64_t)kout * j] = (Tout)(acc[k] * d);
   }
+}
+
+template <typename Tin, int MU>
+__global__ void __launch_bounds__(kNT)
+k_ttm_l1(const Tin* __restrict__ X, int64_t I, int64_t R, const double* __restrict__ Qt,
+         int kout, const double* __restrict__ colscale, double* __restrict__ Y) {
+  __shared__ Tin tile[RowsPerChunk<Tin>::value][kNT + 1];
+  ttm_l1_block<Tin, MU>(X, I, R, Qt, kout, colscale, Y, blockIdx.x, tile);
 }
 
 template <typename Tin, int MU>

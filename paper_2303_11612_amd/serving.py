@@ -140,8 +140,84 @@ class GpuBackend:
         res.core = h["core"]
 
 
+class GroupedBackend:
+    """Runs a group of admitted requests through one tucker_rand_sthosvd_batch
+    call on the slot's stream: every stage of every mode is one launch for the
+    whole group.  A request's result is bitwise the same in any group (and
+    differs from GpuBackend's only by float64 rounding: the grouped kernels
+    sum in other orders)."""
+
+    grouped = True
+
+    def __init__(self, slots: int, max_group: int = 64):
+        import torch
+        from . import (BatchRequest, colmajor_empty, tucker_rand_batch_workspace_size,
+                       tucker_rand_sthosvd_batch)
+        self.torch = torch
+        self.max_group = max(1, int(max_group))
+        self._colmajor_empty = colmajor_empty
+        self._breq = BatchRequest
+        self._ws_size = tucker_rand_batch_workspace_size
+        self._batch = tucker_rand_sthosvd_batch
+        self.streams = [torch.cuda.Stream() for _ in range(slots)]
+
+    def _request(self, req: Request, X):
+        return self._breq(X, req.ranks, req.samples, req.oversample, req.power, req.prob,
+                          req.seed)
+
+    def compatible(self, a: Request, b: Request) -> bool:
+        """Requests that can share a group: the same order and dtype."""
+        return a.X.dim() == b.X.dim() and a.X.dtype == b.X.dtype
+
+    def footprint(self, req: Request) -> int:
+        """Device bytes the request holds while its group runs (its workspace
+        alone bounds its share of a group's: the per-request regions are the
+        same and the descriptor area grows linearly)."""
+        X = req.X
+        esz = X.element_size()
+        ws = self._ws_size([self._request(req, None)], X.dtype, dims=[tuple(X.shape)])
+        out = sum(X.shape[n] * req.ranks[n] for n in range(X.dim())) + int(np.prod(req.ranks))
+        staged = 0 if X.is_cuda else X.numel() * esz
+        return int(staged + ws + out * esz + 4)
+
+    def launch_group(self, reqs: List[Request], slot: int):
+        torch = self.torch
+        st = self.streams[slot]
+        with torch.cuda.stream(st):
+            Xs = []
+            for req in reqs:
+                X = req.X
+                if not X.is_cuda:
+                    host = X
+                    X = self._colmajor_empty(tuple(host.shape), host.dtype)
+                    X.copy_(host, non_blocking=True)
+                Xs.append(X)
+            Qs, cores, stat = self._batch([self._request(r, X) for r, X in zip(reqs, Xs)],
+                                          stream=st)
+            done = torch.cuda.Event(enable_timing=True)
+            done.record(st)
+        return {"X": Xs, "Qs": Qs, "cores": cores, "status": stat, "done": done}
+
+    def poll(self, h) -> bool:
+        return h["done"].query()
+
+    reference = GpuBackend.reference
+    completion_time = GpuBackend.completion_time
+
+    def finish_group(self, h, results: List[Result]):
+        stat = h["status"].cpu().tolist()
+        for i, res in enumerate(results):
+            res.status = int(stat[i])
+            res.factors = h["Qs"][i]
+            res.core = h["cores"][i]
+
+
 class Server:
-    """Admission by free slot and HBM footprint, in arrival order."""
+    """Admission by free slot and HBM footprint, in arrival order.
+
+    With a grouped backend (``backend.grouped``) a free slot takes every
+    arrived request that fits -- up to ``backend.max_group``, compatible with
+    the first -- as one group; otherwise one request per slot."""
 
     def __init__(self, backend, slots: int = 8, hbm_budget: int = 16 * GIB,
                  lookahead: int = 8):
@@ -151,6 +227,7 @@ class Server:
         self.slots = slots
         self.budget = int(hbm_budget)
         self.lookahead = max(1, int(lookahead))
+        self.group_sizes = []
 
     def run(self, requests: List[Request], clock: Optional[Callable[[], float]] = None,
             idle: Optional[Callable[[], None]] = None) -> List[Result]:
@@ -171,38 +248,60 @@ class Server:
         if clock is None:
             def clock():
                 return time.perf_counter() - t0
+        grouped = getattr(be, "grouped", False)
+        gmax = be.max_group if grouped else 1
         pending = list(reqs)
-        active = {}                   # slot -> (request, handle, Result)
+        active = {}                   # slot -> (handle, [Result])
         used = 0
         self.peak_used = 0
+        self.group_sizes = []
         results = {}
         while pending or active:
             # completions
             for slot in list(active):
-                r, h, res = active[slot]
+                h, group = active[slot]
                 if be.poll(h):
-                    res.completed = be.completion_time(h, ref) - t0
-                    be.finish(h, res)
-                    results[r.rid] = res
-                    used -= res.footprint
+                    t_done = be.completion_time(h, ref) - t0
+                    if grouped:
+                        be.finish_group(h, group)
+                    else:
+                        be.finish(h, group[0])
+                    for res in group:
+                        res.completed = t_done
+                        results[res.rid] = res
+                        used -= res.footprint
                     del active[slot]
             # admissions: arrived requests in arrival order, bounded look-ahead
+            # (per group member)
             now = clock()
             free = [s for s in range(self.slots) if s not in active]
-            i = 0
-            while free and i < min(len(pending), self.lookahead):
-                r = pending[i]
-                if r.arrival > now:
-                    break
-                if used + fps[r.rid] <= self.budget:
-                    slot = free.pop(0)
-                    res = Result(r.rid, r.arrival, now, footprint=fps[r.rid], slot=slot)
-                    active[slot] = (r, be.launch(r, slot), res)
-                    used += fps[r.rid]
-                    self.peak_used = max(self.peak_used, used)
-                    pending.pop(i)
-                else:
+            while free and pending and pending[0].arrival <= now:
+                take, i = [], 0
+                budget_left = self.budget - used
+                while len(take) < gmax and i < len(pending) and \
+                        i < len(take) + self.lookahead:
+                    r = pending[i]
+                    if r.arrival > now:
+                        break
+                    if fps[r.rid] <= budget_left and \
+                            (not take or be.compatible(pending[take[0]], r)):
+                        take.append(i)
+                        budget_left -= fps[r.rid]
                     i += 1
+                if not take:
+                    break
+                slot = free.pop(0)
+                group_reqs = [pending[i] for i in take]
+                for i in reversed(take):
+                    pending.pop(i)
+                group = [Result(r.rid, r.arrival, now, footprint=fps[r.rid], slot=slot)
+                         for r in group_reqs]
+                h = be.launch_group(group_reqs, slot) if grouped else be.launch(group_reqs[0],
+                                                                                slot)
+                active[slot] = (h, group)
+                used += sum(res.footprint for res in group)
+                self.peak_used = max(self.peak_used, used)
+                self.group_sizes.append(len(group))
             if idle is not None:
                 idle()
             elif not active and pending and pending[0].arrival > clock():

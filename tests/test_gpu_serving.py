@@ -1,5 +1,8 @@
 """Continuous batching on the GPU: every result is bitwise the same alone and
-in the mix, and matches the FP64 oracle (float32 bar 1e-4).
+in the mix, and matches the FP64 oracle (float32 bar 1e-4).  The grouped
+server (GroupedBackend: admitted requests run as one tucker_rand_sthosvd_batch
+call) gives each request bitwise the result of that request alone in a batch,
+whatever the grouping.
 
 Requests are the serving stream's (modes 32..384, ranks 4..24, T_n = 4 mu_n,
 nearly-optimal sampling, q = 1, K = 10).  "Alone" runs each request by itself
@@ -14,7 +17,8 @@ import torch
 import oracle
 import synth
 import paper_2303_11612_amd as tr
-from paper_2303_11612_amd.serving import GpuBackend, Request, Server, pinned_colmajor
+from paper_2303_11612_amd.serving import (GpuBackend, GroupedBackend, Request, Server,
+                                          pinned_colmajor)
 
 pytestmark = pytest.mark.gpu
 
@@ -106,3 +110,46 @@ def test_mix_matches_oracle(stream_requests, alone):
         re_o = oracle.relative_error(A64, co, Qo)
         re_g = oracle.relative_error(A64, cg.astype(np.float64), [Q.astype(np.float64) for Q in Qg])
         assert abs(re_g - re_o) <= 1e-4 * max(re_o, 1e-3), (rid, re_g, re_o)
+
+
+@pytest.fixture(scope="module")
+def alone_grouped(stream_requests):
+    outs = []
+    for req in _requests(stream_requests, "device"):
+        res = Server(GroupedBackend(1, 1), slots=1).run([req])
+        assert res[0].status == 0
+        outs += _outputs(res)
+    return outs
+
+
+@pytest.mark.parametrize("source", ["device", "host"])
+def test_grouped_mix_equals_alone(stream_requests, alone_grouped, source):
+    srv = Server(GroupedBackend(2, 4), slots=2)
+    res = srv.run(_requests(stream_requests, source))
+    assert all(r.status == 0 for r in res)
+    assert max(srv.group_sizes) > 1 and sum(srv.group_sizes) == NREQ
+    _same(_outputs(res), alone_grouped)
+
+
+def test_grouped_budget_and_arrivals(stream_requests, alone_grouped):
+    reqs = _requests(stream_requests, "host", arrivals=np.arange(NREQ) * 2e-4)
+    be = GroupedBackend(3, 3)
+    budget = int(2.5 * max(be.footprint(r) for r in reqs))
+    srv = Server(be, slots=3, hbm_budget=budget)
+    res = srv.run(reqs)
+    assert srv.peak_used <= budget
+    assert all(r.status == 0 and r.admitted >= r.arrival and r.completed > r.admitted
+               for r in res)
+    _same(_outputs(res), alone_grouped)
+
+
+def test_grouped_close_to_per_request_driver(alone, alone_grouped, stream_requests):
+    """The grouped kernels sum in other orders than tucker_rand_sthosvd: the
+    two results agree to float32 output rounding (both are within the float32
+    bar of the oracle)."""
+    for (Qa, ca), (Qb, cb) in zip(alone, alone_grouped):
+        for x, y in zip(Qa, Qb):
+            x64, y64 = x.astype(np.float64), y.astype(np.float64)
+            d = max(np.linalg.norm(x64 - y64 @ (y64.T @ x64), 2),
+                    np.linalg.norm(y64 - x64 @ (x64.T @ y64), 2))
+            assert d <= 1e-4

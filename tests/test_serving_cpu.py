@@ -152,3 +152,70 @@ def test_poisson_arrivals_rate():
     a = poisson_arrivals(20000, 500.0, seed=0)
     assert np.all(np.diff(a) > 0)
     assert abs(20000 / a[-1] - 500.0) < 15.0
+
+
+class FakeGroupedBackend(FakeBackend):
+    """A group costs a fixed launch overhead plus its bytes at the service
+    rate (the grouped kernels pay the per-stage launch cost once per group)."""
+
+    grouped = True
+
+    def __init__(self, max_group=4, overhead=2e-3, **kw):
+        super().__init__(**kw)
+        self.max_group = max_group
+        self.overhead = overhead
+        self.groups = []
+
+    def compatible(self, a, b):
+        return len(a.ranks) == len(b.ranks)
+
+    def launch_group(self, reqs, slot):
+        nbytes = sum(r.X.nbytes for r in reqs)
+        end = self.now + self.overhead + nbytes / self.rate
+        key = tuple(r.rid for r in reqs)
+        self.running[key] = (self.now, end, nbytes)
+        self.groups.append((self.now, key))
+        self.log.append((self.now, "start", key, sum(v[2] for v in self.running.values()),
+                         len(self.running)))
+        return key
+
+    def finish_group(self, h, results):
+        self.running.pop(h)
+        self.log.append((self.now, "end", h, 0, len(self.running)))
+
+
+def test_grouped_admission_rules():
+    rng = np.random.default_rng(5)
+    sizes = rng.integers(1 << 20, 16 << 20, size=80)
+    arr = poisson_arrivals(80, 3000.0, seed=6)
+    reqs = _reqs(sizes, arr)
+    budget = 96 << 20
+    be = FakeGroupedBackend(max_group=5)
+    srv = Server(be, slots=2, hbm_budget=budget)
+    res = srv.run(reqs, clock=be.clock, idle=be.idle)
+    assert [r.rid for r in res] == list(range(80))
+    seen = []
+    for t, key in be.groups:
+        assert 1 <= len(key) <= 5
+        assert all(reqs[rid].arrival <= t for rid in key)
+        seen += list(key)
+    assert sorted(seen) == list(range(80))
+    assert sum(srv.group_sizes) == 80 and max(srv.group_sizes) > 1
+    for t, ev, key, used, n in be.log:
+        if ev == "start":
+            assert used <= budget and n <= 2
+    # members of a group complete together
+    for _, key in be.groups:
+        assert len({res[rid].completed for rid in key}) == 1
+
+
+def test_grouping_amortises_launch_overhead_under_load():
+    sizes = np.full(120, 1 << 20)
+    arr = poisson_arrivals(120, 1500.0, seed=8)      # 1.5x what one-at-a-time sustains
+    def run(gmax):
+        be = FakeGroupedBackend(max_group=gmax, overhead=1e-3, rate=1e12)
+        return summarize(Server(be, slots=1, hbm_budget=1 << 34).run(
+            _reqs(sizes, arr), clock=be.clock, idle=be.idle))
+    one, grouped = run(1), run(32)
+    assert grouped["throughput_rps"] > 1.3 * one["throughput_rps"]
+    assert grouped["p99_ms"] < one["p99_ms"]
