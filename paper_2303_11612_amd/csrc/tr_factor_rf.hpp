@@ -16,6 +16,7 @@
 
 #include "tr_device.hpp"
 #include "tr_factor.hpp"
+#include "tr_power.hpp"
 
 namespace trk {
 
@@ -32,7 +33,12 @@ struct RfShape {
   // one wave (JW values x SEG segments) then spread over all 32 banks, and
   // segments never overlap.
   __host__ __device__ static constexpr int poff(int g) { return g * JW; }
-  static constexpr int kP = NT * PS + SEG * JW;
+  // Q formation: each wave stages 64 rows of V (the Householder vectors) in
+  // its own LDS block of row stride LDV (16 TT columns, zero beyond SM)
+  static constexpr int TT = (SM + 15) / 16;   // 16-wide tiles of V^T V per dimension
+  static constexpr int LDV = 16 * TT + 2;
+  static constexpr int kVB = NT * LDV;
+  static constexpr int kP = NT * PS + SEG * JW > kVB ? NT * PS + SEG * JW : kVB;
   static constexpr int kTotal = kP + 2 * SM * LDX + 6 * SM + 16;  // doubles
   static constexpr size_t lds_bytes() { return 8 * (size_t)kTotal; }
 };
@@ -408,7 +414,107 @@ __device__ __forceinline__ void factor_rf_body(const FactorJob& jb, int cast_f32
   }
   __syncthreads();
 
-  // ---- 5. Z = H_0 ... H_{s-1} [U; 0], reflectors applied last-first ----
+  // ---- 5. Z = H_0 ... H_{s-1} [U; 0] in compact form.  With
+  //         Z_{k+1} = H_{k+1} ... H_{s-1} [U; 0] and w_k = tau_k v_k^T Z_{k+1},
+  //         Z = [U; 0] - sum_k v_k w_k, and since [U; 0] is zero below row s,
+  //         w_k = tau_k (y_k - sum_{m > k} (v_k^T v_m) w_m), y = V(0:s, :)^T U.
+  //         So one product G = V^T V (matrix cores), a short recurrence for
+  //         the rows w_k, and one local update of every row replace the s
+  //         dependent reflector applications. ----
+  {
+    constexpr int TT = S::TT, LDV = S::LDV, NTL = TT * (TT + 1) / 2;
+    double* Vb = P + wid * kWave * LDV;  // this wave's 64 rows of V
+    const int h = lane & 15, g = lane >> 4;
+    f64x4 gacc[NTL];
+#pragma unroll
+    for (int t = 0; t < NTL; ++t) gacc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+    // rows tid + NT r, r descending: the last pass leaves rows 0 .. 63 (with
+    // the top s rows of V) in wave 0's block
+#pragma unroll
+    for (int r = R - 1; r >= 0; --r) {
+      const int i = tid + NT * r;
+      wave_lds_order();
+#pragma unroll
+      for (int j = 0; j < 16 * TT; ++j) {
+        double v = 0.0;
+        if (j < SM) v = j < s ? (i > j ? a[r][j] : (i == j ? 1.0 : 0.0)) : 0.0;
+        Vb[lane * LDV + j] = v;
+      }
+      wave_lds_order();
+#pragma unroll
+      for (int kk = 0; kk < kWave / 4; ++kk) {
+        const double* row = Vb + (4 * kk + g) * LDV + h;
+        int t = 0;
+#pragma unroll
+        for (int ta = 0; ta < TT; ++ta)
+#pragma unroll
+          for (int tb = ta; tb < TT; ++tb, ++t) gacc[t] = mfma_f64(row[16 * ta], row[16 * tb], gacc[t]);
+      }
+    }
+    // the waves' partial tiles in the blocks of waves 1..3, summed in wave
+    // order into G (row-major, stride LDX, in the Jacobi buffer, free now)
+    double* Gp = P + kWave * LDV;
+    double* G = X;
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NTL; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Gp[((wid * NTL + t) * 4 + q) * kWave + lane] = gacc[t][q];
+    __syncthreads();
+    for (int e = tid; e < NTL * 4 * kWave; e += NT) {
+      const int t = e / (4 * kWave), q = (e / kWave) % 4, ln = e % kWave;
+      int ta = 0, tb = 0, c = 0;
+      for (int x = 0; x < TT; ++x)
+        for (int y = x; y < TT; ++y, ++c)
+          if (c == t) {
+            ta = x;
+            tb = y;
+          }
+      const int m = 16 * ta + (ln >> 4) + 4 * q, k = 16 * tb + (ln & 15);
+      double sum = Gp[((0 * NTL + t) * 4 + q) * kWave + ln];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) sum += Gp[((w * NTL + t) * 4 + q) * kWave + ln];
+      if (m < SM && k < SM) G[m * LDX + k] = sum;
+    }
+    __syncthreads();
+    // y(k, c) = sum_i V(i, k) U(i, c) over i < SM (V is zero above its unit
+    // diagonal and U below row s), zero for c >= mu
+    double* Ys = Gp;
+    double* Ws = Gp + SM * MU;
+    for (int e = tid; e < SM * MU; e += NT) {
+      const int k = e / MU, c = e % MU;
+      const int cc = c < mu ? c : 0;
+      double t = 0.0;
+#pragma unroll
+      for (int i = 0; i < SM; ++i) t = fma(P[i * LDV + k], U[cc * LDX + i], t);
+      Ys[e] = c < mu ? t : 0.0;
+    }
+    __syncthreads();
+    // w_k, k = s-1 .. 0, lane c of wave 0; G, y and w are zero past s, so
+    // every step runs unmasked (the dot product in two alternating partial
+    // sums, added at the end)
+    if (wid == 0) {
+      const int c = lane < MU ? lane : MU - 1;
+      double w[SM];
+      auto w_step = [&](auto kc) __attribute__((always_inline)) {
+        constexpr int k = SM - 1 - decltype(kc)::value;
+        double acc0 = Ys[k * MU + c], acc1 = 0.0;
+#pragma unroll
+        for (int m = k + 1; m < SM; ++m) {
+          const double gkm = G[k * LDX + m];
+          if ((m - k) & 1) acc0 = fma(-gkm, w[m], acc0);
+          else acc1 = fma(-gkm, w[m], acc1);
+        }
+        w[k] = k < s ? tau[k] * (acc0 + acc1) : 0.0;
+      };
+      StaticFor<0, SM>::run(w_step);
+      if (lane < MU) {
+#pragma unroll
+        for (int k = 0; k < SM; ++k) Ws[k * MU + lane] = w[k];
+      }
+    }
+    __syncthreads();
+  }
   double z[R][MU];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -419,38 +525,26 @@ __device__ __forceinline__ void factor_rf_body(const FactorJob& jb, int cast_f32
       z[r][c] = (i < s && c < mu) ? u : 0.0;
     }
   }
-  auto q_step = [&](auto kc) __attribute__((always_inline)) {
-    constexpr int k = SM - 1 - decltype(kc)::value;
-    if (k >= s) return;
-    double v[R];
+  {
+    const double* Ws = P + kWave * S::LDV + SM * MU;
+    // (rows k >= s of W are zero, so the loop runs unmasked)
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int i = tid + NT * r;
-      v[r] = i > k ? a[r][k] : (i == k ? 1.0 : 0.0);
-    }
-    double p[MU];
+    for (int k = 0; k < SM; ++k) {
+      double v[R];
 #pragma unroll
-    for (int c = 0; c < MU; ++c) {
-      double t = 0.0;
+      for (int r = 0; r < R; ++r) {
+        const int i = tid + NT * r;
+        v[r] = i > k ? a[r][k] : (i == k ? 1.0 : 0.0);
+      }
 #pragma unroll
-      for (int r = 0; r < R; ++r) t = fma(v[r], z[r][c], t);
-      p[c] = t;
-    }
-    rf_reduce<SM, MU, 0, RfSum>(p, mu, P, vec, tid);
-    const double tk = tau[k];
+      for (int c = 0; c < MU; ++c) {
+        const double wk = Ws[k * MU + c];
 #pragma unroll
-    for (int c0 = 0; c0 < MU; c0 += 8) {
-      if (c0 < mu) {
-#pragma unroll
-        for (int c = c0; c < c0 + 8; ++c) {
-          const double w = tk * vec[c];
-#pragma unroll
-          for (int r = 0; r < R; ++r) z[r][c] = fma(-v[r], w, z[r][c]);
-        }
+        for (int r = 0; r < R; ++r) z[r][c] = fma(-v[r], wk, z[r][c]);
       }
     }
-  };
-  StaticFor<0, SM>::run(q_step);
+  }
+  __syncthreads();  // W (in P) is read until here; the sign step reuses P
 
   // ---- 6. sign: the largest-magnitude entry of each column (lowest row on
   //         ties) becomes positive ----
