@@ -36,6 +36,7 @@ __all__ = [
     "orth", "tucker_signal", "tendiag", "add_noise", "Workload",
     "low_rank_plus_noise", "gaussian_bumps", "config", "CONFIGS",
     "serving_request", "serving_shape", "serving_request_device",
+    "tucker_noise_device", "tendiag_noise_device", "eq9_samples",
 ]
 
 
@@ -246,3 +247,91 @@ def serving_request_device(req_id: int, base_seed: int = 1000, device="cuda"):
     scale = 1e-3 * float(torch.linalg.vector_norm(B)) / math.sqrt(B.numel())
     X = (B + scale * E).to(torch.float32)
     return X.permute(2, 1, 0), ranks, tuple(4 * r for r in ranks)
+
+
+def _colmajor(T):
+    """A C-contiguous torch tensor rearranged in memory to column-major order
+    (same logical shape and values)."""
+    order = tuple(range(T.dim() - 1, -1, -1))
+    return T.permute(order).contiguous().permute(order)
+
+
+def _device_signal(core, factors, device):
+    """B = core x_1 U_1 ... x_N U_N in float64 on the device (C-contiguous)."""
+    import torch
+    f64 = dict(dtype=torch.float64, device=device)
+    B = torch.as_tensor(np.ascontiguousarray(core), **f64)
+    for n, U in enumerate(factors):
+        Ut = torch.as_tensor(np.ascontiguousarray(U), **f64)
+        B = torch.movedim(torch.tensordot(Ut, B.contiguous(), dims=([1], [n])), 0, n)
+    return B.contiguous()
+
+
+def _device_noise(B, gamma, seed, dtype, device):
+    import torch
+    if gamma == 0.0:
+        return _colmajor(B.to(dtype))
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    scale = gamma * float(torch.linalg.vector_norm(B)) / math.sqrt(B.numel())
+    E = torch.randn(B.shape, generator=g, dtype=torch.float64, device=device)
+    return _colmajor((B + scale * E).to(dtype))
+
+
+def tucker_noise_device(dims, core_dims, gamma, seed, core="uniform", device="cuda",
+                        dtype=None):
+    """Eq. (9) tensor assembled on the device: A = B + gamma ||B||_F /
+    sqrt(prod I_n) E, B = C x_1 A_1 ... x_N A_N with C iid U(0,1)
+    (core="uniform", the paper's choice) or N(0,1) (core="gauss"), A_n an
+    orthonormal basis of a standard Gaussian I_n x r_n matrix.  The core and
+    factors are numpy draws (same order as ``low_rank_plus_noise``); the noise
+    is drawn on the device with torch's generator seeded with ``seed``.
+    Returns a column-major float32 (or ``dtype``) device tensor."""
+    import torch
+    rng = np.random.default_rng(seed)
+    N = len(dims)
+    if core == "uniform":
+        C = rng.random(tuple(core_dims)[::-1]).T
+    elif core == "gauss":
+        C = rng.standard_normal(tuple(core_dims)[::-1]).T
+    else:
+        raise ValueError(core)
+    U = [orth(rng.standard_normal((dims[n], core_dims[n]))) for n in range(N)]
+    B = _device_signal(C, U, device)
+    return _device_noise(B, gamma, seed, dtype or torch.float32, device)
+
+
+def tendiag_noise_device(dims, decay, gamma, seed, device="cuda", dtype=None):
+    """Section 6.3 tensor on the device: B = tendiag(v) x_1 A_1 ... x_N A_N
+    (r = len(v) terms sum_i v_i a_i^(1) o ... o a_i^(N), A_n orthonormal
+    I_n x r), plus relative noise gamma as in Eq. (9)."""
+    import torch
+    rng = np.random.default_rng(seed)
+    N = len(dims)
+    r = len(decay)
+    U = [orth(rng.standard_normal((dims[n], r))) for n in range(N)]
+    f64 = dict(dtype=torch.float64, device=device)
+    v = torch.as_tensor(np.asarray(decay, dtype=np.float64), **f64)
+    # B_(1) = A_1 diag(v) (A_N kr ... kr A_2)^T, built as C-ordered (I_1, ..., I_N)
+    K = torch.as_tensor(np.ascontiguousarray(U[N - 1]), **f64)        # (I_N, r)
+    for n in range(N - 2, 0, -1):
+        Un = torch.as_tensor(np.ascontiguousarray(U[n]), **f64)      # (I_n, r)
+        K = (Un[:, None, :] * K[None, :, :]).reshape(-1, r)           # (I_n * ..., r)
+    A1 = torch.as_tensor(np.ascontiguousarray(U[0]), **f64) * v[None, :]
+    B = torch.matmul(A1, K.t().contiguous()).reshape(tuple(dims))
+    return _device_noise(B, gamma, seed, dtype or torch.float32, device)
+
+
+def eq9_samples(alpha, dims, ranks, sthosvd):
+    """T_n = ceil(alpha prod_{m != n} I_m) for Alg. 4 and ceil(alpha mu_1 ...
+    mu_{n-1} I_{n+1} ... I_N) for Alg. 5 (the setting of Section 4.3)."""
+    N = len(dims)
+    out = []
+    for n in range(N):
+        p = 1
+        for m in range(N):
+            if m == n:
+                continue
+            p *= (ranks[m] if (sthosvd and m < n) else dims[m])
+        out.append(int(math.ceil(alpha * p)))
+    return tuple(out)
