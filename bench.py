@@ -153,7 +153,7 @@ def main():
     if args.workload == "paper":
         pw = bench_paper(args)
         f4 = pw["eq9_fig4"]
-        best = f4["alg5"][-1]
+        best = [r for r in f4["alg5"] if r["mu"] == 50][0]
         out = {"metric": METRIC, "value": round(1e3 / best["ms"], 2), "unit": "decomp/s",
                "n_gpus": 1, "steps": pw["repeats"], "warmup": 1, "ms_per_step": best["ms"],
                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -381,15 +381,14 @@ def bench_paper(args):
     (workspace preallocated, inputs in HBM) and its RE (Eq. (8)) from the
     library's norms:
     * Eq. (9) 600^3 (core 100^3 iid U(0,1), gamma 1e-3): Fig. 4's setting
-      (Alg. 1, 4, 2, 5 with q 1, K 10, alpha 0.2) over mu = 5..MAXMU, Fig. 1's
+      (Alg. 1, 4, 2, 5 with q 1, K 10, alpha 0.2) over mu = 5..100, Fig. 1's
       q = 1..4 and Fig. 2's K = 5..30 for Alg. 1 and 2, Fig. 3's alpha sweep
       for Alg. 4 and 5;
     * Section 6.3: tendiag 600^3 (v_i = 1 for i <= 50, (i - 49)^-2 after,
       600 terms), Alg. 2 and 5;
     * a 200^4 Tucker tensor (core 50^4 iid N(0,1), gamma 1e-3), Alg. 2 and 5.
-    The sketch width s = mu + K is limited to 64 (the factor kernels' limit),
-    so mu runs to 50 where the paper goes to 100; RE is cross-checked by a
-    float64 reconstruction for a few decompositions."""
+    mu runs to 100 as in the paper (s = mu + K up to 110); RE is
+    cross-checked by a float64 reconstruction for a few decompositions."""
     import numpy as np
     import torch
     import synth
@@ -433,21 +432,21 @@ def bench_paper(args):
             r["re_fp64_reconstruction"] = _re_fp64(X, Qs, core)
         return r
 
-    out = {"repeats": reps, "note": "s = mu + K <= 64: mu runs to 50 (the paper: 100)"}
+    out = {"repeats": reps}
     t0 = time.perf_counter()
     X = synth.tucker_noise_device((600, 600, 600), (100, 100, 100), 1e-3, args.seed)
     torch.cuda.synchronize()
     out["generation_s"] = round(time.perf_counter() - t0, 2)
-    mus = list(range(5, 55, 5))
+    mus = list(range(5, 105, 5))
     algs = {"alg1": ("thosvd", "none"), "alg4": ("thosvd", "uniform"),
             "alg2": ("sthosvd", "none"), "alg5": ("sthosvd", "uniform")}
     fig4 = {}
     for name, (algo, prob) in algs.items():
-        fig4[name] = [run(X, algo, mu, prob=prob, alpha=0.2, check=(mu == 50))
+        fig4[name] = [run(X, algo, mu, prob=prob, alpha=0.2, check=(mu in (50, 100)))
                       for mu in mus]
     out["eq9_fig4"] = dict(fig4, setting="Eq. (9) 600^3 float32, gamma 1e-3; q 1, K 10, "
                            "alpha 0.2; Alg. 4/5 with uniform probabilities")
-    out["eq9_fig1_q"] = {name: {str(q): [run(X, algo, mu, q=q) for mu in (10, 30, 50)]
+    out["eq9_fig1_q"] = {name: {str(q): [run(X, algo, mu, q=q) for mu in (10, 50, 100)]
                                 for q in (1, 2, 3, 4)}
                          for name, (algo, _) in (("alg1", algs["alg1"]),
                                                  ("alg2", algs["alg2"]))}
@@ -456,7 +455,7 @@ def bench_paper(args):
                          for name, (algo, _) in (("alg1", algs["alg1"]),
                                                  ("alg2", algs["alg2"]))}
     out["eq9_fig3_alpha"] = {name: {str(a): [run(X, algo, mu, prob=prob, alpha=a)
-                                             for mu in (10, 30, 50)]
+                                             for mu in (10, 50, 100)]
                                     for a in (0.01, 0.08, 0.15, 0.22, 0.29, 0.36, 0.43, 0.5)}
                              for name, (algo, prob) in (("alg4", algs["alg4"]),
                                                         ("alg5", algs["alg5"]))}

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 # the batched driver
 SOURCES = [
     # one unit per factor kernel instance (FactorVariant 0 .. 15), the slowest
-    ("tr_factor_inst.hip", (f"-DTR_FACTOR_INST={k}",)) for k in range(16)] + [
+    ("tr_factor_inst.hip", (f"-DTR_FACTOR_INST={k}",)) for k in range(17)] + [
     ("tr_lowp_launch.hip", ()), ("tucker_rand.hip", ()), ("tr_factor_launch.hip", ()),
     ("tr_pw_fused.hip", ()), ("tr_batch.hip", ())]
 SRC = os.path.join(CSRC, "tucker_rand.hip")

@@ -27,14 +27,22 @@ namespace trk {
 // ---------------------------------------------------------------------------
 constexpr int kFactorNT = 256;
 
+// SM > 64 (the wide variant, s <= 128): the s x s matrices M and U live in
+// global scratch (FactorJob::gW, 2 SM LDR doubles) as do the I x s and I x mu
+// working matrices; the second QR is skipped (M = R1, whose left singular
+// vectors are those of C's R factor) and the Jacobi keeps two rows of the
+// s x s matrix per lane.
 template <int SM>
 struct FactorShape {
   static constexpr int NT = kFactorNT, NW = NT / kWave, LDR = SM + 1;
+  static constexpr bool kWide = SM > 64;
   // always-LDS part (doubles): M/X, U, scratch, vec and small vectors
-  static constexpr int kSmall = 2 * SM * LDR + NW * SM + 11 * SM + 16 + SM * SM / 2;
+  static constexpr int kSmall =
+      (kWide ? 0 : 2 * SM * LDR) + NW * SM + 11 * SM + 16 + SM * SM / 2;
   static size_t lds_bytes(int I, int s, int mu, bool global_mats) {
     return 8 * ((global_mats ? 0 : (size_t)I * (s + mu)) + kSmall);
   }
+  static size_t wide_scratch_bytes() { return kWide ? 8 * (size_t)(2 * SM * LDR) : 0; }
 };
 
 __device__ __forceinline__ void lds_fence() {
@@ -62,6 +70,7 @@ struct FactorJob {
   void* Qcast;
   double* gA;
   int I, s, mu, ldqt;
+  double* gW;  // wide variant (s > 64): scratch for the two s x s matrices
 };
 constexpr int kMaxFactorJobs = 8;
 // Independent factorizations launched together, one workgroup each (by value
@@ -87,12 +96,16 @@ k_factor(FactorJobs jobs, int cast_f32, uint32_t* __restrict__ status) {
   constexpr int CH = SM < 16 ? SM : 16;  // columns per register chunk
   extern __shared__ double smem[];
   double* sp = smem;
+  constexpr bool kWide = F::kWide;
+  static_assert(!kWide || kGlobal, "the wide variant keeps its matrices in global memory");
   double* A = kGlobal ? gA : sp;                    // I x s, column-major
   double* Z = kGlobal ? gZ : sp + (size_t)I * s;    // I x mu, column-major
   if (!kGlobal) sp += (size_t)I * (s + mu);
-  double* M = sp;                  // R1^T, then X = R2^T (column c at M[c*LDR])
+  // R1^T, then X = R2^T (column c at M[c*LDR]); wide: R1 itself
+  double* M = kWide ? jb.gW : sp;
   double* U = M + SM * LDR;        // R2^T while it is built, then U_X(:, 1:mu)
-  double* scr = U + SM * LDR;      // NW x SM reduction scratch
+  if (!kWide) sp += 2 * SM * LDR;
+  double* scr = sp;                // NW x SM reduction scratch
   double* vec = scr + NW * SM;     // reduced vector
   double* tau = vec + SM;
   double* rowk = tau + SM;
@@ -191,15 +204,19 @@ k_factor(FactorJobs jobs, int cast_f32, uint32_t* __restrict__ status) {
     }
     for (int i = tid; i < I; i += NT)
       if (i > k) A[(size_t)k * I + i] *= inv;
-    // R1 row k -> column k of M = R1^T
-    if (tid < s) M[k * LDR + tid] = tid == k ? beta
-                                   : (tid > k ? rowk[tid] - tk * (rowk[tid] + inv * vec[tid]) : 0.0);
+    // R1 row k -> column k of M = R1^T (wide: row k of M = R1)
+    if (tid < s) {
+      const double r1 = tid == k ? beta
+                        : (tid > k ? rowk[tid] - tk * (rowk[tid] + inv * vec[tid]) : 0.0);
+      if constexpr (kWide) M[tid * LDR + k] = r1;
+      else M[k * LDR + tid] = r1;
+    }
     if (tid == 0) tau[k] = tk;
     __syncthreads();
   }
 
   // ---- 2. QR of M = R1^T (s x s) by wave 0, lane = row; U = R2^T ----
-  if (wid == 0) {
+  if (!kWide && wid == 0) {
     const int ln = min(lane, s1);
     for (int k = 0; k < s; ++k) {
       const double alpha = M[k * LDR + k];
@@ -299,15 +316,26 @@ k_factor(FactorJobs jobs, int cast_f32, uint32_t* __restrict__ status) {
           ps[h] = pq & 0xff;
           qs[h] = pq >> 8;
         }
+        // wide: the second row of each lane (lane + 64)
+        double xs2[kWide ? HW : 1], ys2[kWide ? HW : 1];
+        const int ln2 = kWide ? min(lane + kWave, s1) : 0;
 #pragma unroll
         for (int h = 0; h < HW; ++h) {
           xs[h] = M[ps[h] * LDR + ln];
           ys[h] = M[qs[h] * LDR + ln];
+          if constexpr (kWide) {
+            xs2[h] = M[ps[h] * LDR + ln2];
+            ys2[h] = M[qs[h] * LDR + ln2];
+          }
           aa[h] = jn[ps[h]];
           bb[h] = jn[qs[h]];
         }
 #pragma unroll
-        for (int h = 0; h < HW; ++h) cc[h] = wave_sum(lane < s ? xs[h] * ys[h] : 0.0);
+        for (int h = 0; h < HW; ++h) {
+          double d = lane < s ? xs[h] * ys[h] : 0.0;
+          if constexpr (kWide) d += lane + kWave < s ? xs2[h] * ys2[h] : 0.0;
+          cc[h] = wave_sum(d);
+        }
 #pragma unroll
         for (int h = 0; h < HW; ++h) {
           const int g = wid + NW * h;
@@ -321,6 +349,12 @@ k_factor(FactorJobs jobs, int cast_f32, uint32_t* __restrict__ status) {
             if (lane < s) {
               M[ps[h] * LDR + lane] = cs * xs[h] - sn * ys[h];
               M[qs[h] * LDR + lane] = sn * xs[h] + cs * ys[h];
+            }
+            if constexpr (kWide) {
+              if (lane + kWave < s) {
+                M[ps[h] * LDR + lane + kWave] = cs * xs2[h] - sn * ys2[h];
+                M[qs[h] * LDR + lane + kWave] = sn * xs2[h] + cs * ys2[h];
+              }
             }
             if (lane == 0) {
               jn[ps[h]] = a - t * c;

@@ -182,5 +182,12 @@ int launch_factor_tab_kRf40x2(const trk::FactorJob* tab, int n, int cast_f32,
   return factor_rf_tab<40, 2, 32>(tab, n, cast_f32, status_tab, st);
 }
 #endif
+#if TR_FACTOR_INST == 16
+static_assert(kGlb128 == 16, "instance numbering");
+int launch_factor_kGlb128(const trk::FactorJobs& jobs, int n, int cast_f32, uint32_t* status,
+                          hipStream_t st) {
+  return factor_k_jobs<128, true>(jobs, n, cast_f32, status, st);
+}
+#endif
 
 }  // namespace trh

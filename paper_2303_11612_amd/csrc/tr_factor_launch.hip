@@ -39,6 +39,9 @@ int launch_factor_kRf40x1(const trk::FactorJobs& jobs, int n, int cast_f32, uint
 int launch_factor_kRf40x2(const trk::FactorJobs& jobs, int n, int cast_f32, uint32_t* status,
                       hipStream_t st);
 
+int launch_factor_kGlb128(const trk::FactorJobs& jobs, int n, int cast_f32, uint32_t* status,
+                          hipStream_t st);
+
 int launch_factor_group(int var, const trk::FactorJobs& jobs, int n, int cast_f32,
                         uint32_t* status, hipStream_t st) {
   switch (var) {
@@ -58,6 +61,7 @@ int launch_factor_group(int var, const trk::FactorJobs& jobs, int n, int cast_f3
     case kRf24x2: return launch_factor_kRf24x2(jobs, n, cast_f32, status, st);
     case kRf40x1: return launch_factor_kRf40x1(jobs, n, cast_f32, status, st);
     case kRf40x2: return launch_factor_kRf40x2(jobs, n, cast_f32, status, st);
+    case kGlb128: return launch_factor_kGlb128(jobs, n, cast_f32, status, st);
     default: return TR_EINVAL;
   }
 }

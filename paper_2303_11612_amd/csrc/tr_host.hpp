@@ -57,7 +57,9 @@ int launch_pw_lp(int prec, int kind, int64_t s, const void* X, int64_t L, int64_
 // else the one with its working matrices in global scratch.
 enum FactorVariant {
   kRf16x1, kRf16x2, kRf32x1, kRf32x2, kRf48x1, kRf48x2,
-  kLds16, kLds32, kLds64, kGlb16, kGlb32, kGlb64, kRf24x1, kRf24x2, kRf40x1, kRf40x2
+  kLds16, kLds32, kLds64, kGlb16, kGlb32, kGlb64, kRf24x1, kRf24x2, kRf40x1, kRf40x2,
+  kGlb128,  // 64 < s <= 128: matrices in global scratch, FactorJob::gW set
+  kNumFactorVariants
 };
 
 // Fused exact power step (k_pw_fused): I <= 128 rows and sketch width

@@ -76,7 +76,7 @@ struct TimeScope {
 // Compile-time widths: a row of Q^T or of the sketch is padded with zeros to
 // the next width in this list, which the kernels are instantiated for.
 // ---------------------------------------------------------------------------
-constexpr int kWidths[] = {4, 8, 12, 16, 20, 24, 32, 40, 48, 64};
+constexpr int kWidths[] = {4, 8, 12, 16, 20, 24, 32, 40, 48, 64, 80, 96, 112, 128};
 inline int pad_width(int64_t m) {
   for (int w : kWidths)
     if (m <= w) return w;
@@ -109,7 +109,13 @@ inline int64_t ttm_splits(int64_t J, int64_t I) {
   return std::max<int64_t>(1, std::min<int64_t>(cdiv(512, bx), I / 16));
 }
 
-inline int factor_sm(int64_t s) { return s <= 16 ? 16 : (s <= 32 ? 32 : 64); }
+inline int factor_sm(int64_t s) {
+  return s <= 16 ? 16 : (s <= 32 ? 32 : (s <= 64 ? 64 : 128));
+}
+// sketch widths above 64 (up to 128): plain power scheme in native precision
+// only, factor kernel kGlb128 with its s x s matrices in global scratch
+constexpr int64_t kMaxSketch = 128;
+inline bool wide_sketch(int64_t s) { return s > 64; }
 constexpr size_t kMaxLds = 163840;
 
 // LDS bytes of the factor kernel; `global_mats` keeps the I x s and I x mu
@@ -118,13 +124,20 @@ inline size_t factor_lds_bytes(int64_t I, int64_t s, int64_t mu, bool global_mat
   switch (factor_sm(s)) {
     case 16: return trk::FactorShape<16>::lds_bytes((int)I, (int)s, (int)mu, global_mats);
     case 32: return trk::FactorShape<32>::lds_bytes((int)I, (int)s, (int)mu, global_mats);
-    default: return trk::FactorShape<64>::lds_bytes((int)I, (int)s, (int)mu, global_mats);
+    case 64: return trk::FactorShape<64>::lds_bytes((int)I, (int)s, (int)mu, global_mats);
+    default: return trk::FactorShape<128>::lds_bytes((int)I, (int)s, (int)mu, true);
   }
 }
 inline bool factor_in_lds(int64_t I, int64_t s, int64_t mu) {
-  return factor_lds_bytes(I, s, mu, false) <= kMaxLds;
+  return !wide_sketch(s) && factor_lds_bytes(I, s, mu, false) <= kMaxLds;
 }
-inline bool factor_supported(int64_t I, int64_t s) { return s >= 1 && s <= 64 && I <= (1 << 24); }
+inline bool factor_supported(int64_t I, int64_t s) {
+  return s >= 1 && s <= kMaxSketch && I <= (1 << 24);
+}
+// global scratch of the wide factor variant (its two s x s matrices)
+inline size_t factor_wide_bytes(int64_t s) {
+  return wide_sketch(s) ? trk::FactorShape<128>::wide_scratch_bytes() : 0;
+}
 
 inline size_t lp_esz(int prec) { return prec == TR_PREC_FP8E4M3 ? 1 : 2; }
 
@@ -135,6 +148,7 @@ struct ModePlan {
   int64_t L, I, R, J;   // 3-D view of the tensor the mode is computed from
   int64_t s, mu, T;     // sketch width, rank, samples (T = 0: exact)
   int sw, muw;          // padded widths of the sketch rows and of Q^T rows
+  size_t oFw = 0;       // wide factor scratch (s > 64)
   bool sampled;
   bool src_f64;         // the tensor of this mode is float64
   bool intermediate;    // ... and the library's own shrunk tensor (ST-HOSVD, n > 0)
@@ -244,6 +258,7 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
       }
     }
     if (!factor_supported(M.I, M.s)) return TR_ENOTSUP;
+    if (wide_sketch(M.s) && (lp || P->racc || P->related)) return TR_ENOTSUP;
     // low precision rounds the caller's data only: an ST-HOSVD intermediate
     // (float64, at most mu_1/I_1 of the input) keeps its energy in few
     // columns, so rounding it would turn the format's roundoff directly into
@@ -342,6 +357,8 @@ int make_plan(const tr_params* p, int dtype, bool sthosvd, Plan* P) {
       P->oYn[n] = take(8 * (size_t)(P->m[n].I * P->m[n].s));
       P->oSign[n] = take(8 * (size_t)P->m[n].s);
     }
+  for (int n = 0; n < N; ++n)
+    if (wide_sketch(P->m[n].s)) P->m[n].oFw = take(factor_wide_bytes(P->m[n].s));
   if (P->racc || P->related)
     for (int n = 0; n < N; ++n) {
       const size_t Is = (size_t)(P->m[n].I * P->m[n].s), ss = (size_t)(P->m[n].s * P->m[n].s);
@@ -569,20 +586,22 @@ void ttm_w(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Qt, int 
   const int64_t J = L * R;
   const dim3 grid((unsigned)cdiv(J, kNT));
   const int64_t ns = ttm_splits(J, I);
-  if (ns > 1 && MU <= 24) {
-    // segments combined inside the workgroup: one launch, no partials; the
-    // fewer the columns, the more (and shorter) segments per column, so that
-    // a view of a few hundred columns still spreads over the chip
-    if (J < 1024 && I >= 256)
-      hipLaunchKernelGGL((trk::k_ttm_seg<Tin, MU, 64>), dim3((unsigned)cdiv(J, kNT / 64)),
-                         dim3(kNT), 0, st, X, L, I, R, Qt, kout, colscale, Y);
-    else if (J < 8192 && I >= 128)
-      hipLaunchKernelGGL((trk::k_ttm_seg<Tin, MU, 32>), dim3((unsigned)cdiv(J, kNT / 32)),
-                         dim3(kNT), 0, st, X, L, I, R, Qt, kout, colscale, Y);
-    else
-      hipLaunchKernelGGL((trk::k_ttm_seg<Tin, MU, 16>), dim3((unsigned)cdiv(J, kNT / 16)),
-                         dim3(kNT), 0, st, X, L, I, R, Qt, kout, colscale, Y);
-    return;
+  if constexpr (MU <= 24) {
+    if (ns > 1) {
+      // segments combined inside the workgroup: one launch, no partials; the
+      // fewer the columns, the more (and shorter) segments per column, so that
+      // a view of a few hundred columns still spreads over the chip
+      if (J < 1024 && I >= 256)
+        hipLaunchKernelGGL((trk::k_ttm_seg<Tin, MU, 64>), dim3((unsigned)cdiv(J, kNT / 64)),
+                           dim3(kNT), 0, st, X, L, I, R, Qt, kout, colscale, Y);
+      else if (J < 8192 && I >= 128)
+        hipLaunchKernelGGL((trk::k_ttm_seg<Tin, MU, 32>), dim3((unsigned)cdiv(J, kNT / 32)),
+                           dim3(kNT), 0, st, X, L, I, R, Qt, kout, colscale, Y);
+      else
+        hipLaunchKernelGGL((trk::k_ttm_seg<Tin, MU, 16>), dim3((unsigned)cdiv(J, kNT / 16)),
+                           dim3(kNT), 0, st, X, L, I, R, Qt, kout, colscale, Y);
+      return;
+    }
   }
   if (ns > 1 && split) {
     const int64_t ich = cdiv(I, ns);
@@ -617,6 +636,10 @@ int ttm_t(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Qt, int w
     case 40: ttm_w<Tin, 40>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
     case 48: ttm_w<Tin, 48>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
     case 64: ttm_w<Tin, 64>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
+    case 80: ttm_w<Tin, 80>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
+    case 96: ttm_w<Tin, 96>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
+    case 112: ttm_w<Tin, 112>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
+    case 128: ttm_w<Tin, 128>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
     default: return TR_ENOTSUP;
   }
   return check_launch();
@@ -679,6 +702,10 @@ int pw_step_t(const Tin* X, int64_t L, int64_t I, int64_t R, const double* colw,
     case 2: return pw_step<Tin, 2>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st);
     case 3: return pw_step<Tin, 3>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st);
     case 4: return pw_step<Tin, 4>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st);
+    case 5: return pw_step<Tin, 5>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st);
+    case 6: return pw_step<Tin, 6>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st);
+    case 7: return pw_step<Tin, 7>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st);
+    case 8: return pw_step<Tin, 8>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st);
     default: return TR_ENOTSUP;
   }
 }
@@ -868,8 +895,14 @@ inline int factor_rf_variant(int64_t I, int64_t s, int64_t mu) {
   return mu <= 32 ? kRf48x2 : -1;
 }
 
-int factor_variant(int64_t I, int64_t s, int64_t mu, bool has_scratch, int* var) {
+int factor_variant(int64_t I, int64_t s, int64_t mu, bool has_scratch, bool has_wide,
+                   int* var) {
   if (!factor_supported(I, s) || mu < 1 || mu > s) return TR_ENOTSUP;
+  if (wide_sketch(s)) {
+    if (!has_scratch || !has_wide) return TR_ENOMEM;
+    *var = kGlb128;
+    return TR_OK;
+  }
   const int rf = factor_rf_variant(I, s, mu);
   if (rf >= 0 && !force_lds_factor()) {
     *var = rf;
@@ -912,7 +945,8 @@ int launch_factor_jobs(const trk::FactorJob* job, int n, int cast_f32, uint32_t*
   if (n < 1 || n > trk::kMaxFactorJobs) return TR_EINVAL;
   int var[trk::kMaxFactorJobs];
   for (int b = 0; b < n; ++b)
-    TR_TRY(factor_variant(job[b].I, job[b].s, job[b].mu, job[b].gA != nullptr, &var[b]));
+    TR_TRY(factor_variant(job[b].I, job[b].s, job[b].mu, job[b].gA != nullptr,
+                          job[b].gW != nullptr, &var[b]));
   // Jobs of different register-resident instances would run one launch after
   // another; when one instance covers them all (the narrowest such), a single
   // launch runs them side by side and takes about as long as its widest job.
@@ -1124,7 +1158,8 @@ int range_sketch(const Plan& P, int n, const void* X, void* ws, const tr_diag* d
 trk::FactorJob factor_job(const Plan& P, int n, double* Y, double* sig, void* ws, void* Qout) {
   const ModePlan& M = P.m[n];
   return trk::FactorJob{Y, at<double>(ws, P.oQ[n]), at<double>(ws, P.oQt[n]), sig, Qout, Y,
-                        (int)M.I, (int)M.s, (int)M.mu, M.muw};
+                        (int)M.I, (int)M.s, (int)M.mu, M.muw,
+                        wide_sketch(M.s) ? at<double>(ws, M.oFw) : nullptr};
 }
 
 double* mode_sigma(const Plan& P, int n, const tr_diag* diag, void* ws, size_t off) {
@@ -1738,7 +1773,7 @@ int tucker_rand_gather(int dtype, const void* X, int64_t L, int64_t I, int64_t R
 
 size_t tucker_rand_power_workspace_size(int dtype, int64_t L, int64_t I, int64_t R,
                                         int64_t s) {
-  if (L < 1 || I < 1 || R < 1 || s < 1 || s > 64) return 0;
+  if (L < 1 || I < 1 || R < 1 || s < 1 || s > kMaxSketch) return 0;
   return power_ws_bytes(L, I, R, s, dtype == TR_F64);
 }
 
@@ -1748,7 +1783,7 @@ int tucker_rand_power(int dtype, const void* X, int64_t L, int64_t I, int64_t R,
   if ((dtype != TR_F64 && dtype != TR_F32) || !X || !G || !C || L < 1 || I < 1 || R < 1 ||
       s < 1 || q < 1)
     return TR_EINVAL;
-  if (s > 64) return TR_ENOTSUP;
+  if (s > kMaxSketch) return TR_ENOTSUP;
   const bool f64 = dtype == TR_F64;
   if (!workspace || workspace_bytes < power_ws_bytes(L, I, R, s, f64)) return TR_ENOMEM;
   hipStream_t st = (hipStream_t)stream;
@@ -1766,22 +1801,26 @@ int tucker_rand_power(int dtype, const void* X, int64_t L, int64_t I, int64_t R,
 }
 
 size_t tucker_rand_factor_workspace_size(int64_t I, int64_t s, int64_t mu) {
-  if (I < 1 || s < 1 || s > 64 || mu < 1 || mu > s) return 0;
-  return factor_in_lds(I, s, mu) ? 0 : 8 * (size_t)(I * s);
+  if (I < 1 || s < 1 || s > kMaxSketch || mu < 1 || mu > s) return 0;
+  if (factor_in_lds(I, s, mu)) return 0;
+  return align_up(8 * (size_t)(I * s)) + factor_wide_bytes(s);
 }
 
 int tucker_rand_factor(const double* C, int64_t I, int64_t s, int64_t mu, double* Q,
                        double* sigma, void* workspace, size_t workspace_bytes, void* stream) {
   if (!C || !Q || I < 1 || s < 1 || s > I || mu < 1 || mu > s) return TR_EINVAL;
-  if (s > 64) return TR_ENOTSUP;
+  if (s > kMaxSketch) return TR_ENOTSUP;
   const size_t need = tucker_rand_factor_workspace_size(I, s, mu);
   if (need > 0 && (!workspace || workspace_bytes < need)) return TR_ENOMEM;
-  return launch_factor(C, I, s, mu, Q, nullptr, (int)mu, sigma, nullptr, 0, nullptr,
-                       (double*)workspace, (hipStream_t)stream);
+  trk::FactorJob jb{C, Q, nullptr, sigma, nullptr, (double*)workspace, (int)I, (int)s, (int)mu,
+                    (int)mu, nullptr};
+  if (wide_sketch(s))
+    jb.gW = (double*)((char*)workspace + align_up(8 * (size_t)(I * s)));
+  return launch_factor_jobs(&jb, 1, 0, nullptr, (hipStream_t)stream);
 }
 
 size_t tucker_rand_ttm_workspace_size(int64_t L, int64_t I, int64_t R, int64_t mu) {
-  if (L < 1 || I < 1 || R < 1 || mu < 1 || mu > 64) return 0;
+  if (L < 1 || I < 1 || R < 1 || mu < 1 || mu > kMaxSketch) return 0;
   return align_up(8 * (size_t)(I * pad_width(mu))) + align_up(8 * (size_t)(L * mu * R));
 }
 
@@ -1791,7 +1830,7 @@ int tucker_rand_ttm(int in_dtype, const void* X, int64_t L, int64_t I, int64_t R
   if ((in_dtype != TR_F64 && in_dtype != TR_F32) || (out_dtype != TR_F64 && out_dtype != TR_F32))
     return TR_EINVAL;
   if (!X || !Q || !Y || L < 1 || I < 1 || R < 1 || mu < 1) return TR_EINVAL;
-  if (mu > 64) return TR_ENOTSUP;
+  if (mu > kMaxSketch) return TR_ENOTSUP;
   if (!workspace || workspace_bytes < tucker_rand_ttm_workspace_size(L, I, R, mu)) return TR_ENOMEM;
   hipStream_t st = (hipStream_t)stream;
   const int w = pad_width(mu);

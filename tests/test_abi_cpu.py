@@ -69,8 +69,15 @@ def test_sthosvd_rank_checked_against_shrunk_unfolding():
 
 def test_unsupported_requests():
     with pytest.raises(_abi.TuckerRandError) as e:
-        _ws((200, 200, 200), (60, 10, 10), 10, 1)        # s = 70 > 64
+        _ws((200, 200, 200), (130, 10, 10), 10, 1)       # s = 140 > 128
     assert e.value.code == _abi.TR_ENOTSUP
+    # 64 < s <= 128: the plain power scheme only
+    assert _ws((200, 200, 200), (100, 10, 10), 10, 1) > _ws((200, 200, 200), (50, 10, 10), 10, 1)
+    for flags in (["stabilized_power"], ["related_form"]):
+        with pytest.raises(_abi.TuckerRandError) as e:
+            tr.tucker_rand_workspace_size((200, 200, 200), (100, 10, 10), 10, 2, "none",
+                                          flags=flags)
+        assert e.value.code == _abi.TR_ENOTSUP
     # low-precision power products: I_n <= 512 and s_n <= 48
     with pytest.raises(_abi.TuckerRandError) as e:
         _ws((600, 20, 20), (4, 4, 4), 4, 1, precision="bf16")

@@ -301,3 +301,63 @@ def test_ttm_matches_mode_product(in_dt, out_dt, mu, shape):
         want = oracle.mode_product(A.astype(np.float64), Q.T, n).ravel(order="F")
         tol = 1e-13 if out_dt == torch.float64 else 2e-7
         assert np.linalg.norm(Y - want) <= tol * np.linalg.norm(want), (n, m)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("s", [65, 100, 128])
+def test_power_products_sketch_past_64(dtype, s):
+    """Sketch widths above 64 (five to eight 16-column groups)."""
+    shape = (200, 45, 150)
+    A = _rand_tensor(shape, dtype, 15)
+    X = tr.to_device(A)
+    for n, L, I, R in _views(shape):
+        if s > I:
+            continue
+        G = oracle.gaussian_matrix(I, s, n, 8)
+        M = oracle.unfold(A.astype(np.float64), n)
+        C = _np(tr.tucker_rand_power(X, L, I, R, tr.to_device(G), 1))
+        want = oracle.power_sketch(M, G, 1)
+        assert np.linalg.norm(C - want) <= 1e-12 * np.linalg.norm(want), n
+    I, T = 150, 1001
+    Cp = _rand_tensor((I, T), dtype, 16)
+    d = np.random.default_rng(4).random(T) + 0.5
+    G = oracle.gaussian_matrix(I, s, 0, 9)
+    C = _np(tr.tucker_rand_power(tr.to_device(Cp), 1, I, T, tr.to_device(G), 2,
+                                 torch.tensor(d, device=DEV)))
+    Ms = Cp.astype(np.float64) * np.sqrt(d)[None, :]
+    want = oracle.power_sketch(Ms, G, 2)
+    assert np.linalg.norm(C - want) <= 1e-12 * np.linalg.norm(want)
+
+
+@pytest.mark.parametrize("I,s,mu", [(200, 65, 50), (600, 110, 100), (128, 128, 128),
+                                    (300, 100, 60), (1000, 90, 90), (129, 72, 1)])
+def test_factor_wide_sketch(I, s, mu):
+    """Sketches of 65..128 columns (the kernel with its s x s matrices in
+    global scratch, Jacobi on R1 with two rows per lane)."""
+    C = _graded(I, s, I + s, decay=0.9)
+    Q, sig = tr.tucker_rand_factor(tr.to_device(C), mu)
+    Q, sig = _np(Q), _np(sig)
+    Qo, so = oracle.leading_left_singular_vectors(C, mu)
+    assert np.allclose(sig, so, rtol=1e-12, atol=1e-14)
+    assert np.max(np.abs(Q.T @ Q - np.eye(mu))) < 1e-13
+    for c in range(mu):
+        gap = min(so[c - 1] - so[c] if c else np.inf,
+                  so[c] - so[c + 1] if c + 1 < len(so) else so[c])
+        bound = max(1e-10, 20 * 2.2e-16 * so[0] / gap)
+        assert np.linalg.norm(Q[:, c] - Qo[:, c]) <= bound, (c, bound)
+
+
+@pytest.mark.parametrize("in_dt", [np.float32, np.float64])
+@pytest.mark.parametrize("mu", [65, 100, 128])
+def test_ttm_rank_past_64(in_dt, mu):
+    shape = (200, 140, 30)
+    A = _rand_tensor(shape, in_dt, 5)
+    X = tr.to_device(A)
+    rng = np.random.default_rng(mu)
+    for n, L, I, R in _views(shape):
+        if mu > I:
+            continue
+        Q = np.linalg.qr(rng.standard_normal((I, mu)))[0]
+        Y = _np(tr.tucker_rand_ttm(X, L, I, R, tr.to_device(Q), out_dtype=torch.float64))
+        want = oracle.mode_product(A.astype(np.float64), Q.T, n).ravel(order="F")
+        assert np.linalg.norm(Y - want) <= 1e-13 * np.linalg.norm(want), (n, mu)
