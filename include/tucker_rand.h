@@ -100,7 +100,9 @@ typedef struct tr_params {
                                is the column count of the unfolding that mode n is
                                computed from (original tensor for T-HOSVD, shrunk
                                tensor mu_1..mu_{n-1} I_{n+1}..I_N for ST-HOSVD)    */
-  int32_t oversample;       /* K >= 0; sketch width s_n = min(mu_n + K, I_n)       */
+  int32_t oversample;       /* K >= 0; sketch width s_n = min(mu_n + K, I_n) <= 128
+                               (<= 64 with TR_FLAG_STABILIZED_POWER, TR_FLAG_RELATED_FORM
+                               or a low precision; else TR_ENOTSUP)                */
   int32_t power;            /* q >= 1 power steps                                  */
   int32_t prob;             /* tr_prob                                             */
   const int64_t *samples;   /* host [N]: T_n >= 1 sampled columns (prob != NONE);
@@ -363,7 +365,7 @@ size_t tucker_rand_power_workspace_size(int dtype, int64_t L, int64_t I,
  * the L x I x R view of X (device, dtype) and D = diag(colweight) (device
  * float64 [L*R], or NULL for the identity).  With X a gathered I x T matrix
  * (L = 1, R = T) and colweight = scale^2 this is (C'_n C'_n^T)^q G_n.
- * G, C: device float64 I x s (may alias).  Float64 accumulation.
+ * G, C: device float64 I x s (may alias), s <= 128.  Float64 accumulation.
  */
 int tucker_rand_power(int dtype, const void *X, int64_t L, int64_t I,
                       int64_t R, const double *colweight, int32_t q,
@@ -376,12 +378,13 @@ size_t tucker_rand_factor_workspace_size(int64_t I, int64_t s, int64_t mu);
 
 /*
  * Factor of a sketch (Remark after Alg. 5): Q = the mu leading left singular
- * vectors of C (device float64 I x s, 1 <= mu <= s <= I, s <= 64), each
+ * vectors of C (device float64 I x s, 1 <= mu <= s <= I, s <= 128), each
  * column's largest-magnitude entry made positive (lowest row on ties).
  * Computed on one workgroup in float64: Householder QR C = Q1 R1, a QR of
  * R1^T = Q2 R2, one-sided Jacobi on the columns of R2^T (whose rotated,
  * normalised columns are the left singular vectors U of R1), and
- * Q = Q1 U(:, 1:mu).  Q: device float64 I x mu; sigma: device float64 [s]
+ * Q = Q1 U(:, 1:mu).  For s > 64 the second QR is skipped (the Jacobi runs
+ * on the columns of R1) and the workspace holds the s x s matrices too.  Q: device float64 I x mu; sigma: device float64 [s]
  * singular values in descending order (may be NULL).
  */
 int tucker_rand_factor(const double *C, int64_t I, int64_t s, int64_t mu,
@@ -394,7 +397,7 @@ size_t tucker_rand_ttm_workspace_size(int64_t L, int64_t I, int64_t R,
 
 /*
  * Mode-n product Y = X x_n Q^T (Section 2): for the L x I x R view of X
- * (device, in_dtype) and Q (device float64 I x mu, mu <= 64), Y is
+ * (device, in_dtype) and Q (device float64 I x mu, mu <= 128), Y is
  * L x mu x R (device, out_dtype) with Y(l, k, r) = sum_i Q(i, k) X(l, i, r),
  * float64 accumulation.  This is the ST-HOSVD shrink (Alg. 2 step 6) and each
  * link of the T-HOSVD core chain.  workspace: device scratch of
