@@ -386,7 +386,9 @@ def bench_paper(args):
       for Alg. 4 and 5;
     * Section 6.3: tendiag 600^3 (v_i = 1 for i <= 50, (i - 49)^-2 after,
       600 terms), Alg. 2 and 5;
-    * a 200^4 Tucker tensor (core 50^4 iid N(0,1), gamma 1e-3), Alg. 2 and 5.
+    * a 200^4 Tucker tensor (core 50^4 iid N(0,1), gamma 1e-3), Alg. 2 and 5;
+    * Section 6.1's sparse 600^3 tensor: Alg. 5 with the first mode read from
+      compressed sparse columns, against the dense path.
     mu runs to 100 as in the paper (s = mu + K up to 110); RE is
     cross-checked by a float64 reconstruction for a few decompositions."""
     import numpy as np
@@ -468,6 +470,47 @@ def bench_paper(args):
                          for name in ("alg2", "alg5")}
     del X
     torch.cuda.empty_cache()
+    # Section 6.1's sparse tensor: the first mode from compressed sparse
+    # columns against the dense path on the same tensor (Alg. 5, alpha 0.01,
+    # uniform probabilities as in the paper)
+    X = synth.sparse_cp_device((600, 600, 600), 600, 0.05, 1000.0, args.seed + 3)
+    csc = synth.csc_mode1(X)
+    sp = {"nnz": int(csc[2].numel()), "density": round(csc[2].numel() / X.numel(), 4),
+          "csc_bytes": int(8 * csc[0].numel() + 4 * csc[1].numel() + 4 * csc[2].numel()),
+          "dense_bytes": int(4 * X.numel()), "csc": [], "dense": []}
+    for mu in (10, 30, 50):
+        ranks = (mu,) * 3
+        samples = synth.eq9_samples(0.01, X.shape, ranks, True)
+        need = tr.tucker_rand_workspace_size(X.shape, ranks, 10, 1, "uniform", samples, 0,
+                                             X.dtype, sthosvd=True)
+        if ws is None or ws.numel() < need:
+            ws = None
+            torch.cuda.empty_cache()
+            ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        for kind in ("csc", "dense"):
+            def call():
+                if kind == "csc":
+                    return tr.tucker_rand_sthosvd_csc(*csc, X.shape, ranks, 10, 1, "uniform",
+                                                      samples, 0, diag=True, workspace=ws)
+                return tr.tucker_rand_sthosvd(X, ranks, 10, 1, "uniform", samples, 0,
+                                              diag="norms", workspace=ws)
+            call()
+            times = []
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                _, _, info = call()
+                e1.record()
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1))
+            print(f"paper: sparse600 {kind} mu {mu}: {np.median(times):.3f} ms", file=sys.stderr,
+                  flush=True)
+            sp[kind].append({"mu": mu, "ms": round(float(np.median(times)), 3),
+                             "re": float(info["norms"][2]), "status": int(info["status"][0])})
+    out["sparse600"] = dict(sp, setting="Section 6.1: 600 rank-one terms, 5 % dense factor "
+                                        "vectors, gamma 1000; Alg. 5, K 10, q 1, alpha 0.01")
+    del X, csc
+    torch.cuda.empty_cache()
     X = synth.tucker_noise_device((200,) * 4, (50,) * 4, 1e-3, args.seed + 2, core="gauss")
     out["tucker200pow4"] = {name: [run(X, algs[name][0], mu, prob=algs[name][1], alpha=0.01,
                                        check=(mu == 30)) for mu in (10, 30, 50)]
@@ -477,7 +520,7 @@ def bench_paper(args):
     torch.cuda.empty_cache()
     out["all_status_ok"] = all(
         r["status"] == 0
-        for blk in (out["eq9_fig4"], out["tendiag600"], out["tucker200pow4"])
+        for blk in (out["eq9_fig4"], out["tendiag600"], out["tucker200pow4"], out["sparse600"])
         for k, lst in blk.items() if isinstance(lst, list) for r in lst)
     return out
 

@@ -92,6 +92,8 @@ typedef enum { TR_PREC_NATIVE = 0, TR_PREC_BF16 = 1, TR_PREC_FP8E4M3 = 2 } tr_pr
 /* Device status bits (OR-ed into tr_diag.status). */
 #define TR_DEV_NONFINITE 0x1u  /* a column norm or sketch entry was NaN/Inf   */
 #define TR_DEV_ZERO_DIST 0x2u  /* every column norm was zero: nothing to draw */
+#define TR_DEV_BAD_INDEX 0x4u  /* sparse input: a row index outside [0, I_1)
+                                  (the entry was skipped)                     */
 
 typedef struct tr_params {
   int32_t order;            /* N, 1 <= N <= TR_MAX_ORDER                          */
@@ -275,6 +277,34 @@ int tucker_rand_sthosvd_batch(int nreq, const tr_params *const *p, int dtype,
                               void *const *core, void *workspace,
                               size_t workspace_bytes, uint32_t *status,
                               void *stream);
+
+/*
+ * Randomized ST-HOSVD with sampled products (Alg. 5) of a sparse tensor (the
+ * sparse examples of Sections 6.1 and 6.5): the mode-1 unfolding A_(1)
+ * (I_1 x J_1, J_1 = I_2 ... I_N, column j = i_2 + I_2 (i_3 + I_3 (...)) as
+ * in the dense layout) in compressed sparse columns.  Only the first mode
+ * reads the sparse tensor -- its column norms, the gather of its sampled
+ * columns and the shrink Q_1^T A_(1); the shrunk tensor is dense and the
+ * later modes run as in tucker_rand_sthosvd.  The norms sum each column's
+ * nonzeros in row order, so they, the draws, the gathered columns and Q_1
+ * are those of tucker_rand_sthosvd on the dense tensor.
+ *   p        as for tucker_rand_sthosvd; prob TR_PROB_NEARLY_OPTIMAL or
+ *            TR_PROB_UNIFORM with T_1 <= J_1 (the first mode sampled),
+ *            native precision, no flags (else TR_ENOTSUP).
+ *   colptr   device int64 [J_1 + 1]: colptr[0] = 0, nondecreasing,
+ *            colptr[J_1] = nnz.
+ *   rowidx   device int32 [nnz]: rows in [0, I_1), increasing within each
+ *            column (an index outside [0, I_1) is skipped and sets
+ *            TR_DEV_BAD_INDEX; an unsorted column changes the rounding).
+ *   vals     device [nnz] in dtype.
+ *   workspace  >= tucker_rand_workspace_size(p, dtype, 1, ...) bytes.
+ * Outputs, diagnostics and stream as for tucker_rand_sthosvd.
+ */
+int tucker_rand_sthosvd_csc(const tr_params *p, int dtype, int64_t nnz,
+                            const int64_t *colptr, const int32_t *rowidx,
+                            const void *vals, void *const *Q, void *core,
+                            void *workspace, size_t workspace_bytes,
+                            const tr_diag *diag, void *stream);
 
 /*
  * For callers that cannot allocate device memory (code under HIP graph

@@ -26,6 +26,7 @@ __all__ = [
     "tucker_rand_workspace_size", "tucker_rand_thosvd", "tucker_rand_sthosvd",
     "tucker_rand_sthosvd_noalloc", "tucker_rand_adaptive",
     "BatchRequest", "tucker_rand_batch_workspace_size", "tucker_rand_sthosvd_batch",
+    "tucker_rand_sthosvd_csc",
     "tucker_rand_gaussian", "tucker_rand_colnorms", "tucker_rand_sample",
     "tucker_rand_gather", "tucker_rand_power", "tucker_rand_factor",
     "tucker_rand_ttm", "tucker_rand_status_string",
@@ -286,6 +287,57 @@ def tucker_rand_sthosvd_noalloc(A: torch.Tensor, ranks, oversample=10, power=1, 
     ``diag``) for a call with no allocation on the Python side either."""
     return _decompose("tucker_rand_sthosvd_noalloc", A, ranks, oversample, power, prob,
                       samples, seed, precision, diag, timer, None, stream, out, flags)
+
+
+def tucker_rand_sthosvd_csc(colptr: torch.Tensor, rowidx: torch.Tensor, vals: torch.Tensor,
+                            dims, ranks, oversample=10, power=1, prob="nearly_optimal",
+                            samples=None, seed=0, diag=False, workspace=None, stream=None,
+                            out=None):
+    """Randomized ST-HOSVD with sampled products (Alg. 5) of a sparse tensor of
+    shape ``dims`` given as the compressed sparse columns of its mode-1
+    unfolding: ``colptr`` int64 [J_1 + 1], ``rowidx`` int32 [nnz] (rows
+    increasing within a column), ``vals`` [nnz] float32 or float64, all on
+    the device.  Returns (Q list, core, diag dict) as tucker_rand_sthosvd."""
+    for t, dt in ((colptr, torch.int64), (rowidx, torch.int32)):
+        if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+            raise ValueError("colptr must be contiguous device int64, rowidx device int32")
+    if not vals.is_cuda or not vals.is_contiguous():
+        raise ValueError("vals must be a contiguous device tensor")
+    dims = tuple(int(d) for d in dims)
+    N = len(dims)
+    if colptr.numel() != math.prod(dims[1:]) + 1 or rowidx.numel() != vals.numel():
+        raise ValueError("colptr needs J_1 + 1 entries and rowidx one per value")
+    dt = _dtype_code(vals)
+    st = stream if stream is not None else torch.cuda.current_stream(vals.device)
+    p, keep = _params(dims, ranks, oversample, power, prob, samples, seed, "native")
+    need = c_size_t(0)
+    check("tucker_rand_workspace_size",
+          lib().tucker_rand_workspace_size(byref(p), dt, 1, byref(need)))
+    with torch.cuda.stream(st):
+        if workspace is None:
+            workspace = torch.empty(max(need.value, 1), dtype=torch.uint8, device=vals.device)
+        if out is None:
+            Qs = [colmajor_empty((dims[n], ranks[n]), vals.dtype, vals.device) for n in range(N)]
+            core = colmajor_empty(tuple(ranks), vals.dtype, vals.device)
+        else:
+            Qs, core = out
+        info, dstruct = {}, None
+        if diag:
+            dstruct = _abi.TrDiag()
+            info["status"] = torch.zeros(1, dtype=torch.int32, device=vals.device)
+            dstruct.status = info["status"].data_ptr()
+            info["norms"] = torch.zeros(3, dtype=torch.float64, device=vals.device)
+            dstruct.norms = info["norms"].data_ptr()
+    qptrs = (c_void_p * N)(*[q.data_ptr() for q in Qs])
+    rc = lib().tucker_rand_sthosvd_csc(byref(p), dt, vals.numel(), c_void_p(colptr.data_ptr()),
+                                       c_void_p(rowidx.data_ptr()), c_void_p(vals.data_ptr()),
+                                       qptrs, c_void_p(core.data_ptr()),
+                                       c_void_p(workspace.data_ptr()), c_size_t(workspace.numel()),
+                                       byref(dstruct) if dstruct is not None else None,
+                                       _stream(st))
+    check("tucker_rand_sthosvd_csc", rc)
+    del keep
+    return Qs, core, info
 
 
 class BatchRequest:

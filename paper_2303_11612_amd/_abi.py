@@ -16,7 +16,7 @@ TR_OK, TR_EINVAL, TR_ENOMEM, TR_EDEVICE, TR_ENOTSUP, TR_ENUMERIC = range(6)
 TR_F64, TR_F32 = 0, 1
 PROB = {"none": 0, "nearly_optimal": 1, "uniform": 2}
 PREC = {"native": 0, "bf16": 1, "fp8e4m3": 2}
-TR_DEV_NONFINITE, TR_DEV_ZERO_DIST = 0x1, 0x2
+TR_DEV_NONFINITE, TR_DEV_ZERO_DIST, TR_DEV_BAD_INDEX = 0x1, 0x2, 0x4
 # tr_params.flags bits
 FLAGS = {"stabilized_power": 0x1, "unfused_power": 0x2, "related_form": 0x4}
 KC = {"colnorms": 0, "sample": 1, "gather": 2, "power": 3, "factor": 4, "ttm": 5,
@@ -57,6 +57,9 @@ _SIGS = {
                                      POINTER(c_void_p), c_void_p, c_void_p, c_size_t,
                                      POINTER(c_int64), POINTER(c_double), POINTER(TrDiag),
                                      c_void_p]),
+    "tucker_rand_sthosvd_csc": (c_int, [POINTER(TrParams), c_int, c_int64, c_void_p, c_void_p,
+                                        c_void_p, POINTER(c_void_p), c_void_p, c_void_p,
+                                        c_size_t, POINTER(TrDiag), c_void_p]),
     "tucker_rand_batch_workspace_size": (c_int, [c_int, POINTER(POINTER(TrParams)), c_int,
                                                  POINTER(c_size_t)]),
     "tucker_rand_sthosvd_batch": (c_int, [c_int, POINTER(POINTER(TrParams)), c_int,

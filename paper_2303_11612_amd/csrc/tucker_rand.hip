@@ -21,6 +21,7 @@
 #include "tr_factor_rf.hpp"
 #include "tr_power.hpp"
 #include "tr_lowp.hpp"
+#include "tr_sparse.hpp"
 #include "tr_stab.hpp"
 #include "tr_norms.hpp"
 #include "tr_host.hpp"
@@ -1038,18 +1039,82 @@ int launch_partial_sum(const void* x, bool f32, bool sq, int64_t n, double* part
   return check_launch();
 }
 
+// The first mode's unfolding in compressed sparse columns (tr_sparse.hpp).
+struct CscView {
+  const int64_t* colptr;  // [J_1 + 1]
+  const int32_t* rowidx;  // [nnz]
+  const void* vals;       // [nnz], the decomposition's dtype
+  int64_t nnz;
+};
+
+int launch_colnorms_csc(bool f64, const CscView& sp, int64_t J, double* norms,
+                        unsigned long long* maxb, hipStream_t st) {
+  const dim3 grid((unsigned)cdiv(J, kNT));
+  if (f64)
+    hipLaunchKernelGGL(trk::k_colnorms_csc<double>, grid, dim3(kNT), 0, st, sp.colptr,
+                       (const double*)sp.vals, J, norms, maxb);
+  else
+    hipLaunchKernelGGL(trk::k_colnorms_csc<float>, grid, dim3(kNT), 0, st, sp.colptr,
+                       (const float*)sp.vals, J, norms, maxb);
+  return check_launch();
+}
+
+int launch_gather_csc(bool f64, const CscView& sp, int64_t I, const int64_t* idx, int64_t T,
+                      void* Cp, uint32_t* status, hipStream_t st) {
+  if (f64)
+    hipLaunchKernelGGL(trk::k_gather_csc<double>, dim3((unsigned)T), dim3(kNT), 0, st, sp.colptr,
+                       sp.rowidx, (const double*)sp.vals, I, idx, (double*)Cp, status);
+  else
+    hipLaunchKernelGGL(trk::k_gather_csc<float>, dim3((unsigned)T), dim3(kNT), 0, st, sp.colptr,
+                       sp.rowidx, (const float*)sp.vals, I, idx, (float*)Cp, status);
+  return check_launch();
+}
+
+template <typename T, int MU>
+void ttm_csc_w(const CscView& sp, int64_t I, int64_t J, const double* Qt, int kout, double* Y,
+               uint32_t* status, hipStream_t st) {
+  hipLaunchKernelGGL((trk::k_ttm_csc<T, MU>), dim3((unsigned)cdiv(J, kNT)), dim3(kNT), 0, st,
+                     sp.colptr, sp.rowidx, (const T*)sp.vals, I, J, Qt, kout, Y, status);
+}
+
+template <typename T>
+int ttm_csc_t(const CscView& sp, int64_t I, int64_t J, const double* Qt, int width, int kout,
+              double* Y, uint32_t* status, hipStream_t st) {
+  switch (width) {
+    case 4: ttm_csc_w<T, 4>(sp, I, J, Qt, kout, Y, status, st); break;
+    case 8: ttm_csc_w<T, 8>(sp, I, J, Qt, kout, Y, status, st); break;
+    case 12: ttm_csc_w<T, 12>(sp, I, J, Qt, kout, Y, status, st); break;
+    case 16: ttm_csc_w<T, 16>(sp, I, J, Qt, kout, Y, status, st); break;
+    case 20: ttm_csc_w<T, 20>(sp, I, J, Qt, kout, Y, status, st); break;
+    case 24: ttm_csc_w<T, 24>(sp, I, J, Qt, kout, Y, status, st); break;
+    case 32: ttm_csc_w<T, 32>(sp, I, J, Qt, kout, Y, status, st); break;
+    case 40: ttm_csc_w<T, 40>(sp, I, J, Qt, kout, Y, status, st); break;
+    case 48: ttm_csc_w<T, 48>(sp, I, J, Qt, kout, Y, status, st); break;
+    case 64: ttm_csc_w<T, 64>(sp, I, J, Qt, kout, Y, status, st); break;
+    case 80: ttm_csc_w<T, 80>(sp, I, J, Qt, kout, Y, status, st); break;
+    case 96: ttm_csc_w<T, 96>(sp, I, J, Qt, kout, Y, status, st); break;
+    case 112: ttm_csc_w<T, 112>(sp, I, J, Qt, kout, Y, status, st); break;
+    case 128: ttm_csc_w<T, 128>(sp, I, J, Qt, kout, Y, status, st); break;
+    default: return TR_ENOTSUP;
+  }
+  return check_launch();
+}
+
 // ||A||^2, ||G||^2 and RE (Eq. (8)) into diag->norms after a decomposition:
 // ||A||^2 from the partials of mode 1's column norms when they were taken,
-// else from one sum-of-squares sweep of A; ||G||^2 from the float64 core.
+// else from one sum-of-squares sweep of A (of a sparse A's stored values);
+// ||G||^2 from the float64 core.
 int launch_norms_re(const Plan& P, const void* A, void* ws, const tr_diag* diag,
-                    hipStream_t st) {
+                    hipStream_t st, const CscView* sp = nullptr) {
   if (!diag || !diag->norms) return TR_OK;
   const ModePlan& M0 = P.m[0];
-  const int64_t numel = M0.L * M0.I * M0.R;
+  // a sparse tensor's squares are those of its stored values
+  const int64_t numel = sp ? sp->nnz : M0.L * M0.I * M0.R;
   double* parts = at<double>(ws, P.oNparts);
   const bool have = M0.sampled && P.prob == TR_PROB_NEARLY_OPTIMAL;
   const int np = norm_parts(have ? M0.J : numel);
-  if (!have) TR_TRY(launch_partial_sum(A, P.dtype == TR_F32, true, numel, parts, st));
+  if (!have)
+    TR_TRY(launch_partial_sum(sp ? sp->vals : A, P.dtype == TR_F32, true, numel, parts, st));
   int64_t ncore = 1;
   for (int n = 0; n < P.N; ++n) ncore *= P.m[n].mu;
   hipLaunchKernelGGL(trk::k_norms_re, dim3(1), dim3(trk::kNormNT), 0, st, parts, np,
@@ -1062,7 +1127,7 @@ int launch_norms_re(const Plan& P, const void* A, void* ws, const tr_diag* diag,
 // Sketch of mode n of tensor X (3-D view from the plan): C_n = (M M^T)^q G_n
 // into Y (I x s, float64).
 int range_sketch(const Plan& P, int n, const void* X, void* ws, const tr_diag* diag,
-                 bool need_xmax, double* Y, hipStream_t st) {
+                 bool need_xmax, double* Y, hipStream_t st, const CscView* sp = nullptr) {
   const ModePlan& M = P.m[n];
   tr_timer* tm = diag ? diag->timer : nullptr;
   uint32_t* status = diag ? diag->status : nullptr;
@@ -1086,7 +1151,10 @@ int range_sketch(const Plan& P, int n, const void* X, void* ws, const tr_diag* d
     double* scale2 = at<double>(ws, P.oScale2);
     if (norms_needed) {
       TimeScope ts(tm, TR_KC_COLNORMS, n, st);
-      TR_TRY(launch_colnorms(M.src_f64, X, M.L, M.I, M.R, norms, maxb, st, M.intermediate));
+      if (sp)
+        TR_TRY(launch_colnorms_csc(M.src_f64, *sp, M.J, norms, maxb, st));
+      else
+        TR_TRY(launch_colnorms(M.src_f64, X, M.L, M.I, M.R, norms, maxb, st, M.intermediate));
     }
     // ||A||^2 for the diagnostics: the column norms of mode 1 add up to it
     if (norms_needed && n == 0 && diag && diag->norms)
@@ -1099,7 +1167,10 @@ int range_sketch(const Plan& P, int n, const void* X, void* ws, const tr_diag* d
     }
     {
       TimeScope ts(tm, TR_KC_GATHER, n, st);
-      if (lp)
+      if (sp)
+        TR_TRY(launch_gather_csc(M.src_f64, *sp, M.I, idx, M.T, at<void>(ws, P.oCp), status,
+                                 st));
+      else if (lp)
         TR_TRY(launch_gather_lp(P.prec, M.src_f64, X, M.L, M.I, idx, M.T, scale2,
                                 at<void>(ws, P.oCq), at<float>(ws, P.oOmega), st));
       else
@@ -1262,9 +1333,10 @@ int related_finish(const Plan& P, const int* modes, int k, void* ws, void* const
 
 // Range finder of mode n (ST-HOSVD: sketch, then factor).
 int range_finder(const Plan& P, int n, const void* X, void* ws, void* Qout,
-                 const tr_diag* diag, bool need_xmax, hipStream_t st) {
+                 const tr_diag* diag, bool need_xmax, hipStream_t st,
+                 const CscView* sp = nullptr) {
   double* Y = at<double>(ws, P.oY);
-  TR_TRY(range_sketch(P, n, X, ws, diag, need_xmax, Y, st));
+  TR_TRY(range_sketch(P, n, X, ws, diag, need_xmax, Y, st, sp));
   tr_timer* tm = diag ? diag->timer : nullptr;
   uint32_t* status = diag ? diag->status : nullptr;
   TimeScope ts(tm, TR_KC_FACTOR, n, st);
@@ -1300,7 +1372,7 @@ int check_buffers(const Plan& P, const void* A, void* const* Q, const void* core
 // core buffer and is cast into the caller's core.
 int shrink(const Plan& P, int n, int step, const void* cur, bool cur_f64, int64_t L,
            int64_t I, int64_t R, void* ws, void* core, tr_timer* tm, void** out,
-           hipStream_t st) {
+           hipStream_t st, const CscView* sp = nullptr, uint32_t* status = nullptr) {
   const ModePlan& M = P.m[n];
   const bool last = n == P.N - 1;
   double* dst = at<double>(ws, last ? P.oCore : ((step % 2 == 0) ? P.oX0 : P.oX1));
@@ -1310,8 +1382,15 @@ int shrink(const Plan& P, int n, int step, const void* cur, bool cur_f64, int64_
     // split-rows scratch for; those run the one-pass kernels)
     const size_t need = 8 * (size_t)(ttm_splits(L * R, I) * L * R * M.muw);
     double* split = need <= P.splitBytes ? at<double>(ws, P.oSplit) : nullptr;
-    TR_TRY(launch_ttm(cur_f64, cur, L, I, R, at<double>(ws, P.oQt[n]), M.muw, (int)M.mu,
-                      nullptr, dst, split, st));
+    if (sp && cur_f64)
+      TR_TRY(ttm_csc_t<double>(*sp, I, L * R, at<double>(ws, P.oQt[n]), M.muw, (int)M.mu, dst,
+                               status, st));
+    else if (sp)
+      TR_TRY(ttm_csc_t<float>(*sp, I, L * R, at<double>(ws, P.oQt[n]), M.muw, (int)M.mu, dst,
+                              status, st));
+    else
+      TR_TRY(launch_ttm(cur_f64, cur, L, I, R, at<double>(ws, P.oQt[n]), M.muw, (int)M.mu,
+                        nullptr, dst, split, st));
   }
   if (last) TR_TRY(launch_cast(dst, L * M.mu * R, P.dtype == TR_F32, core, st));
   *out = dst;
@@ -1639,10 +1718,18 @@ int scratch_address(hipStream_t st, void** out) {
   return TR_OK;
 }
 
+// sp: the first mode's unfolding in compressed sparse columns (A unused then;
+// the first mode must be sampled, in native precision, without flags).
 int run_sthosvd(const tr_params* p, int dtype, const void* A, void* const* Q, void* core,
-                void* ws, size_t ws_bytes, const tr_diag* diag, hipStream_t st) {
+                void* ws, size_t ws_bytes, const tr_diag* diag, hipStream_t st,
+                const CscView* sp = nullptr) {
   Plan P;
   TR_TRY(make_plan(p, dtype, true, &P));
+  if (sp) {
+    if (!P.m[0].sampled || P.prec != TR_PREC_NATIVE || P.racc || P.related) return TR_ENOTSUP;
+    if (P.m[0].I > 2147483647LL) return TR_ENOTSUP;
+    A = sp->vals;
+  }
   TR_TRY(check_buffers(P, A, Q, core, ws, ws_bytes));
   const void* cur = A;
   bool cur_f64 = dtype == TR_F64;
@@ -1652,14 +1739,16 @@ int run_sthosvd(const tr_params* p, int dtype, const void* A, void* const* Q, vo
     TR_TRY(launch_gaussian_modes(P, ws, st));
   }
   for (int n = 0; n < P.N; ++n) {
-    TR_TRY(range_finder(P, n, cur, ws, Q[n], diag, true, st));
+    const CscView* spn = n == 0 ? sp : nullptr;
+    TR_TRY(range_finder(P, n, cur, ws, Q[n], diag, true, st, spn));
     const ModePlan& M = P.m[n];
     void* out = nullptr;
-    TR_TRY(shrink(P, n, n, cur, cur_f64, M.L, M.I, M.R, ws, core, tm, &out, st));
+    TR_TRY(shrink(P, n, n, cur, cur_f64, M.L, M.I, M.R, ws, core, tm, &out, st, spn,
+                  diag ? diag->status : nullptr));
     cur = out;
     cur_f64 = true;
   }
-  return launch_norms_re(P, A, ws, diag, st);
+  return launch_norms_re(P, A, ws, diag, st, sp);
 }
 
 }  // namespace
@@ -1701,6 +1790,17 @@ int tucker_rand_sthosvd(const tr_params* p, int dtype, const void* A, void* cons
                         void* stream) {
   return run_sthosvd(p, dtype, A, Q, core, workspace, workspace_bytes, diag,
                      (hipStream_t)stream);
+}
+
+int tucker_rand_sthosvd_csc(const tr_params* p, int dtype, int64_t nnz, const int64_t* colptr,
+                            const int32_t* rowidx, const void* vals, void* const* Q, void* core,
+                            void* workspace, size_t workspace_bytes, const tr_diag* diag,
+                            void* stream) {
+  if (nnz < 0 || !colptr || (nnz > 0 && (!rowidx || !vals))) return TR_EINVAL;
+  static const double kNoValues = 0.0;  // a host stand-in when nnz == 0 (never read)
+  const CscView sp{colptr, rowidx, nnz > 0 ? vals : (const void*)&kNoValues, nnz};
+  return run_sthosvd(p, dtype, nullptr, Q, core, workspace, workspace_bytes, diag,
+                     (hipStream_t)stream, &sp);
 }
 
 int tucker_rand_sthosvd_noalloc(const tr_params* p, int dtype, const void* A, void* const* Q,

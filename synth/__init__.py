@@ -37,6 +37,7 @@ __all__ = [
     "low_rank_plus_noise", "gaussian_bumps", "config", "CONFIGS",
     "serving_request", "serving_shape", "serving_request_device",
     "tucker_noise_device", "tendiag_noise_device", "eq9_samples",
+    "sparse_cp_device", "csc_mode1",
 ]
 
 
@@ -335,3 +336,48 @@ def eq9_samples(alpha, dims, ranks, sthosvd):
             p *= (ranks[m] if (sthosvd and m < n) else dims[m])
         out.append(int(math.ceil(alpha * p)))
     return tuple(out)
+
+
+def sparse_cp_device(dims, n_terms, density, gamma, seed, device="cuda", dtype=None):
+    """Sparse tensor of Sections 6.1 / 6.5: sum_i c_i x_i o y_i o z_i (o ...)
+    with c_i = gamma / i^2 for i <= 50 and 1 / i^2 after, every factor vector
+    sparse -- ceil(density I_n) nonzero entries at distinct uniformly drawn
+    positions, N(0,1) values (the paper fixes only the density).  Built on the
+    device in float64, returned column-major in float32 (or ``dtype``)."""
+    import torch
+    rng = np.random.default_rng(seed)
+    N = len(dims)
+    c = np.array([(gamma if i <= 50 else 1.0) / float(i) ** 2 for i in range(1, n_terms + 1)])
+    U = []
+    for n in range(N):
+        F = np.zeros((dims[n], n_terms))
+        k = int(math.ceil(density * dims[n]))
+        for i in range(n_terms):
+            pos = rng.choice(dims[n], size=k, replace=False)
+            F[pos, i] = rng.standard_normal(k)
+        U.append(F)
+    f64 = dict(dtype=torch.float64, device=device)
+    K = torch.as_tensor(np.ascontiguousarray(U[N - 1]), **f64)
+    for n in range(N - 2, 0, -1):
+        Un = torch.as_tensor(np.ascontiguousarray(U[n]), **f64)
+        K = (Un[:, None, :] * K[None, :, :]).reshape(-1, n_terms)
+    A1 = torch.as_tensor(np.ascontiguousarray(U[0]), **f64) * torch.as_tensor(c, **f64)[None, :]
+    B = torch.matmul(A1, K.t().contiguous()).reshape(tuple(dims))
+    return _colmajor(B.to(dtype or torch.float32))
+
+
+def csc_mode1(X):
+    """Compressed sparse columns of the mode-1 unfolding of a column-major
+    tensor X (torch, any device): (colptr int64 [J_1 + 1], rowidx int32
+    [nnz], vals [nnz]), rows increasing within each column."""
+    import torch
+    I1 = X.shape[0]
+    J1 = X.numel() // I1
+    order = tuple(range(X.dim() - 1, -1, -1))
+    M = X.permute(order).reshape(J1, I1)      # row j = column j of A_(1)
+    nz = torch.nonzero(M)                     # (j, i) in row-major order
+    vals = M[nz[:, 0], nz[:, 1]].contiguous()
+    counts = torch.bincount(nz[:, 0], minlength=J1)
+    colptr = torch.zeros(J1 + 1, dtype=torch.int64, device=X.device)
+    colptr[1:] = torch.cumsum(counts, 0)
+    return colptr, nz[:, 1].to(torch.int32).contiguous(), vals

@@ -194,3 +194,27 @@ def test_batch_workspace_and_limits_on_host():
     qn = (ctypes.POINTER(ctypes.c_void_p) * 1)(None)
     assert L.tucker_rand_sthosvd_batch(1, arr, 1, nul, qn, nul, None, 0, None, None) == \
         _abi.TR_EINVAL
+
+
+def test_sparse_entry_validated_on_host():
+    L = _abi.lib()
+    p, _keep = tr._params((20, 16, 12), (4, 4, 4), 4, 1, "nearly_optimal", (50, 40, 30), 0,
+                          "native")
+    q = (ctypes.c_void_p * 3)(1, 1, 1)
+    one = ctypes.c_void_p(1)
+    # missing colptr / negative nnz / missing values with nnz > 0
+    assert L.tucker_rand_sthosvd_csc(ctypes.byref(p), 0, 10, None, one, one, q, one, one,
+                                     1 << 30, None, None) == _abi.TR_EINVAL
+    assert L.tucker_rand_sthosvd_csc(ctypes.byref(p), 0, -1, one, one, one, q, one, one,
+                                     1 << 30, None, None) == _abi.TR_EINVAL
+    assert L.tucker_rand_sthosvd_csc(ctypes.byref(p), 0, 10, one, None, one, q, one, one,
+                                     1 << 30, None, None) == _abi.TR_EINVAL
+    # the first mode must be sampled (exact products on the sparse tensor are not built)
+    for prob, samples in (("none", None), ("nearly_optimal", (500, 40, 30))):
+        p2, _k2 = tr._params((20, 16, 12), (4, 4, 4), 4, 1, prob, samples, 0, "native")
+        assert L.tucker_rand_sthosvd_csc(ctypes.byref(p2), 0, 10, one, one, one, q, one, one,
+                                         1 << 30, None, None) == _abi.TR_ENOTSUP
+    p3, _k3 = tr._params((20, 16, 12), (4, 4, 4), 4, 1, "nearly_optimal", (50, 40, 30), 0,
+                         "bf16")
+    assert L.tucker_rand_sthosvd_csc(ctypes.byref(p3), 0, 10, one, one, one, q, one, one,
+                                     1 << 30, None, None) == _abi.TR_ENOTSUP

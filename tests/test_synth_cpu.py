@@ -50,3 +50,19 @@ def test_eq9_samples_rule():
     assert synth.eq9_samples(0.01, (200,) * 4, (20,) * 4, True) == (
         80000, math.ceil(0.01 * 20 * 200 * 200), math.ceil(0.01 * 20 * 20 * 200),
         math.ceil(0.01 * 20 ** 3))
+
+
+def test_csc_mode1_round_trip_and_sparse_generator():
+    X = synth.sparse_cp_device((30, 20, 10), 30, 0.2, 1000, 3, device="cpu", dtype=torch.float64)
+    A = X.numpy()
+    # each factor vector has ceil(0.2 I_n) nonzeros, so the tensor is sparse
+    assert 0.0 < np.mean(A != 0) < 0.5
+    colptr, rowidx, vals = synth.csc_mode1(X)
+    assert colptr[0] == 0 and colptr[-1] == vals.numel() == int(np.count_nonzero(A))
+    D = np.zeros((30, 200))
+    cp, ri, v = colptr.numpy(), rowidx.numpy(), vals.numpy()
+    for j in range(200):
+        rows = ri[cp[j]:cp[j + 1]]
+        assert np.all(np.diff(rows) > 0)
+        D[rows, j] = v[cp[j]:cp[j + 1]]
+    assert np.array_equal(D, A.reshape(30, 200, order="F"))
