@@ -27,22 +27,22 @@ namespace trk {
 // ---------------------------------------------------------------------------
 constexpr int kFactorNT = 256;
 
-// SM > 64 (the wide variant, s <= 128): the s x s matrices M and U live in
-// global scratch (FactorJob::gW, 2 SM LDR doubles) as do the I x s and I x mu
-// working matrices; the second QR is skipped (M = R1, whose left singular
-// vectors are those of C's R factor) and the Jacobi keeps two rows of the
-// s x s matrix per lane.
+// SM > 64 (the wide variant, s <= 128): M = R1 (the second QR is skipped;
+// R1's left singular vectors are those C's Q1 rotates) stays in LDS, U lives
+// in global scratch (FactorJob::gW, SM LDR doubles) as do the I x s and
+// I x mu working matrices, and the Jacobi gives each column pair four lanes
+// (all pairs of a step at once; the pair of a step is computed, not tabled).
 template <int SM>
 struct FactorShape {
   static constexpr int NT = kFactorNT, NW = NT / kWave, LDR = SM + 1;
   static constexpr bool kWide = SM > 64;
   // always-LDS part (doubles): M/X, U, scratch, vec and small vectors
   static constexpr int kSmall =
-      (kWide ? 0 : 2 * SM * LDR) + NW * SM + 11 * SM + 16 + SM * SM / 2;
+      (kWide ? 1 : 2) * SM * LDR + NW * SM + 11 * SM + 16 + (kWide ? 0 : SM * SM / 2);
   static size_t lds_bytes(int I, int s, int mu, bool global_mats) {
     return 8 * ((global_mats ? 0 : (size_t)I * (s + mu)) + kSmall);
   }
-  static size_t wide_scratch_bytes() { return kWide ? 8 * (size_t)(2 * SM * LDR) : 0; }
+  static size_t wide_scratch_bytes() { return kWide ? 8 * (size_t)(SM * LDR) : 0; }
 };
 
 __device__ __forceinline__ void lds_fence() {
@@ -102,9 +102,10 @@ k_factor(FactorJobs jobs, int cast_f32, uint32_t* __restrict__ status) {
   double* Z = kGlobal ? gZ : sp + (size_t)I * s;    // I x mu, column-major
   if (!kGlobal) sp += (size_t)I * (s + mu);
   // R1^T, then X = R2^T (column c at M[c*LDR]); wide: R1 itself
-  double* M = kWide ? jb.gW : sp;
-  double* U = M + SM * LDR;        // R2^T while it is built, then U_X(:, 1:mu)
-  if (!kWide) sp += 2 * SM * LDR;
+  double* M = sp;
+  // R2^T while it is built, then U_X(:, 1:mu); wide: in global scratch
+  double* U = kWide ? jb.gW : M + SM * LDR;
+  sp += (kWide ? 1 : 2) * SM * LDR;
   double* scr = sp;                // NW x SM reduction scratch
   double* vec = scr + NW * SM;     // reduced vector
   double* tau = vec + SM;
@@ -283,7 +284,63 @@ k_factor(FactorJobs jobs, int cast_f32, uint32_t* __restrict__ status) {
   __syncthreads();
 
   // ---- 3. one-sided Jacobi on the columns of X; pair g on wave g % NW ----
-  {
+  if constexpr (kWide) {
+    // wide: pair g on lanes 4g .. 4g + 3, lane lq holding rows lq + 4u of the
+    // pair's two columns (rows past s are zero and stay zero); every pair of
+    // a step rotates at once, one barrier per step
+    constexpr int LP = NT / (SM / 2), RU = SM / LP;
+    static_assert(LP == 4, "four lanes per pair");
+    const int se = s + (s & 1), np = se / 2;
+    const int g = tid / LP, lq = tid % LP;
+    const bool gact = g < np;
+    const double tol = 2.0 * s * 2.220446049250313e-16;
+    const double tol_big = 0.1 * sqrt(tol);
+    for (int sweep = 0; sweep < 40 && se > 1; ++sweep) {
+      if (tid < se) {
+        double a = 0.0;
+        for (int i = 0; i < s; ++i) a += M[tid * LDR + i] * M[tid * LDR + i];
+        jn[tid] = a;
+      }
+      __syncthreads();
+      int rot = 0;
+      for (int step = 0; step < se - 1; ++step) {
+        int p = 0, q = 1;
+        if (gact) jacobi_pair(g, step, se, &p, &q);
+        double* xp = M + p * LDR;
+        double* xq = M + q * LDR;
+        double xv[RU], yv[RU];
+        double c = 0.0;
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+          xv[u] = xp[lq + LP * u];
+          yv[u] = xq[lq + LP * u];
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u) c = fma(xv[u], yv[u], c);
+        c += dpp_f64<kDppQuadXor1>(c);
+        c += dpp_f64<kDppQuadXor2>(c);
+        const double a = jn[p], b = jn[q];
+        if (gact && c != 0.0 && fabs(c) > tol * sqrt(a) * sqrt(b)) {
+          const double zeta = (b - a) / (2.0 * c);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + t * t);
+          const double sn = cs * t;
+#pragma unroll
+          for (int u = 0; u < RU; ++u) {
+            xp[lq + LP * u] = cs * xv[u] - sn * yv[u];
+            xq[lq + LP * u] = sn * xv[u] + cs * yv[u];
+          }
+          if (lq == 0) {
+            jn[p] = a - t * c;
+            jn[q] = b + t * c;
+          }
+          rot |= fabs(c) > tol_big * sqrt(a) * sqrt(b) ? 1 : 0;
+        }
+        __syncthreads();
+      }
+      if (!__syncthreads_or(rot)) break;
+    }
+  } else {
     const int se = s + (s & 1);
     const int np = se / 2;
     const int np1 = np - 1;
@@ -316,26 +373,15 @@ k_factor(FactorJobs jobs, int cast_f32, uint32_t* __restrict__ status) {
           ps[h] = pq & 0xff;
           qs[h] = pq >> 8;
         }
-        // wide: the second row of each lane (lane + 64)
-        double xs2[kWide ? HW : 1], ys2[kWide ? HW : 1];
-        const int ln2 = kWide ? min(lane + kWave, s1) : 0;
 #pragma unroll
         for (int h = 0; h < HW; ++h) {
           xs[h] = M[ps[h] * LDR + ln];
           ys[h] = M[qs[h] * LDR + ln];
-          if constexpr (kWide) {
-            xs2[h] = M[ps[h] * LDR + ln2];
-            ys2[h] = M[qs[h] * LDR + ln2];
-          }
           aa[h] = jn[ps[h]];
           bb[h] = jn[qs[h]];
         }
 #pragma unroll
-        for (int h = 0; h < HW; ++h) {
-          double d = lane < s ? xs[h] * ys[h] : 0.0;
-          if constexpr (kWide) d += lane + kWave < s ? xs2[h] * ys2[h] : 0.0;
-          cc[h] = wave_sum(d);
-        }
+        for (int h = 0; h < HW; ++h) cc[h] = wave_sum(lane < s ? xs[h] * ys[h] : 0.0);
 #pragma unroll
         for (int h = 0; h < HW; ++h) {
           const int g = wid + NW * h;
@@ -349,12 +395,6 @@ k_factor(FactorJobs jobs, int cast_f32, uint32_t* __restrict__ status) {
             if (lane < s) {
               M[ps[h] * LDR + lane] = cs * xs[h] - sn * ys[h];
               M[qs[h] * LDR + lane] = sn * xs[h] + cs * ys[h];
-            }
-            if constexpr (kWide) {
-              if (lane + kWave < s) {
-                M[ps[h] * LDR + lane + kWave] = cs * xs2[h] - sn * ys2[h];
-                M[qs[h] * LDR + lane + kWave] = sn * xs2[h] + cs * ys2[h];
-              }
             }
             if (lane == 0) {
               jn[ps[h]] = a - t * c;
