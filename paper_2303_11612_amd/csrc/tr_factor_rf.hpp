@@ -148,10 +148,41 @@ __device__ __forceinline__ void householder(double alpha, double sum2, double* b
   }
 }
 
+// The kernel is straight-line code of 60-430 KB, run once per call, and the
+// tensor sweeps before a call evict it from the caches, so each 64-byte
+// instruction line would otherwise be fetched from HBM on demand.  A launch
+// touches every 128-byte line of its own code once, with ordinary loads from
+// all threads at the start: [this instruction's line, the end recorded by an
+// earlier launch of the same kernel).  Returns the folded words (the caller
+// consumes them so that the loads stay); no range recorded yet: no loads.
+template <int NT, int M>
+__device__ __forceinline__ unsigned touch_code(unsigned long long end) {
+  const unsigned long long pc = __builtin_amdgcn_s_getpc() & ~127ull;
+  unsigned acc = 0;
+  if (end > pc && end - pc <= 128ull * NT * M) {
+    const unsigned n = (unsigned)((end - pc) >> 7);
+    unsigned v[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const unsigned l = threadIdx.x + NT * m;
+      v[m] = l < n ? *reinterpret_cast<const unsigned*>(pc + 128ull * l) : 0u;
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) acc ^= v[m];
+  }
+  return acc;
+}
+
+// Where each factor kernel's code ends (written by its launches, read by the
+// next ones); KIND tells the job-list and the job-table kernels apart.
+template <int SM, int R, int MU, int KIND>
+__device__ unsigned long long g_rf_code_end = 0;
+
 // One factorization by the calling workgroup.
 template <int SM, int R, int MU>
 __device__ __forceinline__ void factor_rf_body(const FactorJob& jb, int cast_f32,
-                                               uint32_t* __restrict__ status) {
+                                               uint32_t* __restrict__ status,
+                                               unsigned long long code_end) {
   const double* __restrict__ C = jb.C;
   const int I = jb.I, s = jb.s, mu = jb.mu, ldqt = jb.ldqt;
   double* __restrict__ Q = jb.Q;
@@ -183,6 +214,10 @@ __device__ __forceinline__ void factor_rf_body(const FactorJob& jb, int cast_f32
     for (int j = 0; j < SM; ++j) a[r][j] = C[(size_t)min(j, s1) * I + ic];
   }
   __builtin_amdgcn_sched_barrier(0);
+  // the code lines' loads go out behind the sketch's, and both are waited
+  // for together (vec[0] is cleared below in any case)
+  const unsigned touched = touch_code<NT, 16>(code_end);
+  if (touched == 0x5bd1e995u) vec[0] = 0.0;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int i = tid + NT * r;
@@ -606,7 +641,8 @@ __device__ __forceinline__ void factor_rf_body(const FactorJob& jb, int cast_f32
 template <int SM, int R, int MU>
 __global__ void __launch_bounds__(256)
 k_factor_rf(FactorJobs jobs, int cast_f32, uint32_t* __restrict__ status) {
-  factor_rf_body<SM, R, MU>(jobs.j[blockIdx.x], cast_f32, status);
+  factor_rf_body<SM, R, MU>(jobs.j[blockIdx.x], cast_f32, status, g_rf_code_end<SM, R, MU, 0>);
+  if (threadIdx.x == 0 && blockIdx.x == 0) g_rf_code_end<SM, R, MU, 0> = __builtin_amdgcn_s_getpc();
 }
 
 // Jobs from a device table (the batched driver, whose batches outnumber the
@@ -616,7 +652,9 @@ template <int SM, int R, int MU>
 __global__ void __launch_bounds__(256)
 k_factor_rf_tab(const FactorJob* __restrict__ tab, int cast_f32, uint32_t* const* status_tab) {
   factor_rf_body<SM, R, MU>(tab[blockIdx.x], cast_f32,
-                            status_tab ? status_tab[blockIdx.x] : nullptr);
+                            status_tab ? status_tab[blockIdx.x] : nullptr,
+                            g_rf_code_end<SM, R, MU, 1>);
+  if (threadIdx.x == 0 && blockIdx.x == 0) g_rf_code_end<SM, R, MU, 1> = __builtin_amdgcn_s_getpc();
 }
 
 }  // namespace trk
