@@ -514,15 +514,18 @@ inline int ttm1_batch(int64_t I) {
   return best;
 }
 
-constexpr int kTtm1Waves = 8;
+// bytes of the Q^T tile a block of the mode-1 MFMA shrink stages in LDS
+inline size_t ttm1_lds(int64_t I, int B, int NKT) {
+  return 8 * (size_t)(cdiv(cdiv(I, 16), B) * B * 16) * 16 * NKT;
+}
 
-template <typename Tin, int NKT, int B, bool STR>
+template <typename Tin, int NKT, int B, bool STR, int kW>
 void ttm1_mfma_k(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Qt, int width,
                  int kout, double* Y, hipStream_t st) {
-  // eight waves share one Q^T tile: the LDS allows at most three tiles per
-  // compute unit, and twice the waves keep twice the loads in flight
-  constexpr int kW = kTtm1Waves;
-  const size_t lds = 8 * (size_t)(cdiv(cdiv(I, 16), B) * B * 16) * 16 * NKT;
+  // kW waves share one Q^T tile: the LDS allows at most three tiles per
+  // compute unit, and twice the waves keep twice the loads in flight (16
+  // where a tile leaves room for one block per compute unit)
+  const size_t lds = ttm1_lds(I, B, NKT);
   if (lds > 65536)
     (void)hipFuncSetAttribute((const void*)&trk::k_ttm1_mfma<Tin, NKT, B, STR, kW>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -546,15 +549,30 @@ void ttm1_mfma_k(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Qt
                      dim3(kW * trk::kWave), lds, st, X, L, I, R, Qt, width, kout, Y);
 }
 
+template <typename Tin, int NKT, bool STR, int kW>
+void ttm1_mfma_w(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Qt, int width,
+                 int kout, double* Y, hipStream_t st) {
+  switch (ttm1_batch(I)) {
+    case 4: ttm1_mfma_k<Tin, NKT, 4, STR, kW>(X, L, I, R, Qt, width, kout, Y, st); break;
+    case 5: ttm1_mfma_k<Tin, NKT, 5, STR, kW>(X, L, I, R, Qt, width, kout, Y, st); break;
+    case 6: ttm1_mfma_k<Tin, NKT, 6, STR, kW>(X, L, I, R, Qt, width, kout, Y, st); break;
+    default: ttm1_mfma_k<Tin, NKT, 8, STR, kW>(X, L, I, R, Qt, width, kout, Y, st); break;
+  }
+}
+
 template <typename Tin, int NKT, bool STR>
 void ttm1_mfma_b(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Qt, int width,
                  int kout, double* Y, hipStream_t st) {
-  switch (ttm1_batch(I)) {
-    case 4: ttm1_mfma_k<Tin, NKT, 4, STR>(X, L, I, R, Qt, width, kout, Y, st); break;
-    case 5: ttm1_mfma_k<Tin, NKT, 5, STR>(X, L, I, R, Qt, width, kout, Y, st); break;
-    case 6: ttm1_mfma_k<Tin, NKT, 6, STR>(X, L, I, R, Qt, width, kout, Y, st); break;
-    default: ttm1_mfma_k<Tin, NKT, 8, STR>(X, L, I, R, Qt, width, kout, Y, st); break;
+  // a 32-wide tile of more than 80 KB fits once per compute unit: sixteen
+  // waves then share it (four per SIMD rather than two, for the matrix
+  // instructions' latency; measured on 512 x 131072 float32, mu = 30)
+  if constexpr (NKT == 2) {
+    if (ttm1_lds(I, ttm1_batch(I), NKT) > 81920) {
+      ttm1_mfma_w<Tin, NKT, STR, 16>(X, L, I, R, Qt, width, kout, Y, st);
+      return;
+    }
   }
+  ttm1_mfma_w<Tin, NKT, STR, 8>(X, L, I, R, Qt, width, kout, Y, st);
 }
 
 // Y[k + kout j] = sum_i Qt[i width + k] X_(n)(i, j) on the matrix cores, for
@@ -570,7 +588,7 @@ bool ttm1_mfma(const Tin* X, int64_t L, int64_t I, int64_t J, const double* Qt, 
   if (I < 4) return false;
   const int nkt = (int)cdiv(kout, 16);
   const int b = ttm1_batch(I);
-  if (8 * (size_t)(cdiv(cdiv(I, 16), b) * b * 16) * 16 * nkt > 131072) return false;
+  if (ttm1_lds(I, b, nkt) > 131072) return false;
   if (str) {
     if (nkt == 1) ttm1_mfma_b<Tin, 1, true>(X, L, I, J, Qt, width, kout, Y, st);
     else ttm1_mfma_b<Tin, 2, true>(X, L, I, J, Qt, width, kout, Y, st);
