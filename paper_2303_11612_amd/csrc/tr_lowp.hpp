@@ -236,7 +236,7 @@ __device__ __forceinline__ void lds_barrier() {
 // 4 waves; wave w owns rows [32 MI w, 32 MI (w + 1)) of both products.  The
 // waves' partial slabs of W are added in LDS in wave order, so the result
 // does not depend on timing.
-template <typename Tin, typename OP, int MI, int NKT>
+template <typename Tin, typename OP, int MI, int NKT, bool V4 = false>
 __global__ void __launch_bounds__(kPwWaves * kWave, 1)
 k_pw_lp(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R, int64_t ldi,
         const typename OP::stor* __restrict__ Cq, const float* __restrict__ tau,
@@ -294,6 +294,23 @@ k_pw_lp(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R, int64_t ldi,
         const auto* colp = X + jc * ldi + rw0 + 8 * g;
 #pragma unroll
         for (int m = 0; m < MI; ++m) B.v[jt][m] = OP::load8(colp + 32 * m);
+      } else if constexpr (V4) {
+        // L == 1, float, I and ldi multiples of 4, X 16-byte aligned: a
+        // lane's 8 rows as two 16-byte loads; a group of 4 rows at or past I
+        // reads rows I - 4 .. I - 1 instead (those rows of M meet zero rows
+        // of C in the first product, and the second product's rows past I
+        // are not used)
+        static_assert(sizeof(Tin) == 4, "16-byte loads of four rows");
+        const Tin* colp = X + jc * ldi;
+#pragma unroll
+        for (int m = 0; m < MI; ++m)
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const int64_t r0 = rw0 + 32 * m + 8 * g + 4 * q;
+            const f32x4 v = *reinterpret_cast<const f32x4*>(colp + (r0 + 4 <= I ? r0 : I - 4));
+#pragma unroll
+            for (int t = 0; t < 4; ++t) B.v[jt][m][4 * q + t] = v[t];
+          }
       } else {
         // 32-bit division (the host guarantees J < 2^32): no divergent
         // 64-bit path, whose branches would make every wait conservative
@@ -400,28 +417,57 @@ k_pw_lp(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R, int64_t ldi,
     }
     buf ^= 1;
   };
-  // Column blocks blockIdx.x, + gridDim.x, ...: counted pairs, each item
-  // prefetching the next one's columns into the other register buffer while
-  // it multiplies out its own (a counted loop keeps every prefetch in the
-  // loop body; an early exit between the items would let the compiler sink
-  // them behind the products).
+  // Column blocks blockIdx.x, + gridDim.x, ...: counted triples over three
+  // register buffers (pairs over two with MI = 4), each item prefetching the
+  // columns two items ahead (one) while it multiplies out its own, so that
+  // two column blocks' loads are in flight behind the products (one was not
+  // enough to cover the load latency with two workgroups per compute unit).
+  // A counted loop keeps every
+  // prefetch in the loop body (an early exit between the items would let the
+  // compiler sink them behind the products); prefetches past the last block
+  // read clamped, valid addresses and go unused.
+  // With 512 rows (MI = 4) the third buffer would spill: two buffers there.
   const int64_t G = gridDim.x;
   const int64_t nit = cb < ncb ? (ncb - cb + G - 1) / G : 0;
-  Buf xa, xb;
-  if (nit > 0) load(cb, xa);
-  int64_t k = 0;
-  for (; k + 2 <= nit; k += 2) {
-    load(cb + G, xb);
-    __builtin_amdgcn_sched_barrier(0);
-    process(cb, xa);
-    cb += G;
-    const int64_t nb = cb + G;
-    load(nb < ncb ? nb : cb, xa);  // the last one reloads (unused)
-    __builtin_amdgcn_sched_barrier(0);
-    process(cb, xb);
-    cb = nb;
+  if constexpr (MI <= 2) {
+    Buf xa, xb, xc;
+    if (nit > 0) {
+      load(cb, xa);
+      load(cb + G, xb);
+    }
+    int64_t k = 0;
+    for (; k + 3 <= nit; k += 3) {
+      load(cb + 2 * G, xc);
+      __builtin_amdgcn_sched_barrier(0);
+      process(cb, xa);
+      cb += G;
+      load(cb + 2 * G, xa);
+      __builtin_amdgcn_sched_barrier(0);
+      process(cb, xb);
+      cb += G;
+      load(cb + 2 * G, xb);
+      __builtin_amdgcn_sched_barrier(0);
+      process(cb, xc);
+      cb += G;
+    }
+    if (k < nit) process(cb, xa);
+    if (k + 1 < nit) process(cb + G, xb);
+  } else {
+    Buf xa, xb;
+    if (nit > 0) load(cb, xa);
+    int64_t k = 0;
+    for (; k + 2 <= nit; k += 2) {
+      load(cb + G, xb);
+      __builtin_amdgcn_sched_barrier(0);
+      process(cb, xa);
+      cb += G;
+      load(cb + G, xa);
+      __builtin_amdgcn_sched_barrier(0);
+      process(cb, xb);
+      cb += G;
+    }
+    if (k < nit) process(cb, xa);
   }
-  if (k < nit) process(cb, xa);
   float* out = part + (int64_t)blockIdx.x * SP * Ip;
 #pragma unroll
   for (int it = 0; it < 2 * MI; ++it)

@@ -2,6 +2,9 @@
 // source type, operand format, row tiling (MI) and sketch width (NKT).
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+#include <type_traits>
+
 #include "tr_host.hpp"
 #include "tr_lowp.hpp"
 
@@ -13,7 +16,11 @@ int pw_lp_k(const void* X, int64_t L, int64_t I, int64_t R, int64_t ldi, const v
             const float* tau, const float* omega, const unsigned* xmax, float* part,
             int64_t nblk, hipStream_t st) {
   const size_t lds = lp_lds_bytes(MI, NKT);
-  auto* fn = &trk::k_pw_lp<Tin, OP, MI, NKT>;
+  // float tensor form with contiguous columns: 16-byte row loads
+  const bool v4 = std::is_same<Tin, float>::value && L == 1 && I % 4 == 0 && ldi % 4 == 0 &&
+                  reinterpret_cast<uintptr_t>(X) % 16 == 0;
+  auto* fn = v4 ? &trk::k_pw_lp<Tin, OP, MI, NKT, std::is_same<Tin, float>::value>
+                : &trk::k_pw_lp<Tin, OP, MI, NKT>;
   if (lds > 65536)
     (void)hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
