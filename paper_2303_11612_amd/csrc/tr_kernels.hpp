@@ -294,7 +294,23 @@ __device__ __forceinline__ void draw_one(const unsigned long long* __restrict__ 
     j = 0;
     wj = 0;
   } else {
+    // the first j with cdf_j > x lies in [lo, hi] (cdf_{J-1} = W > x).  An
+    // 8-ary step probes seven positions with independent loads (one round
+    // trip instead of three dependent ones of a binary step): if c probes
+    // have cdf <= x, j lies between probe c and probe c + 1.
     int64_t lo = 0, hi = J - 1;
+    while (hi - lo >= 8) {
+      const int64_t len = hi - lo + 1;
+      unsigned long long v[7];
+#pragma unroll
+      for (int k = 0; k < 7; ++k) v[k] = cdf[lo + len * (k + 1) / 8];
+      int c = 0;
+#pragma unroll
+      for (int k = 0; k < 7; ++k) c += v[k] <= x ? 1 : 0;
+      const int64_t nlo = c == 0 ? lo : lo + len * c / 8 + 1;
+      hi = c == 7 ? hi : lo + len * (c + 1) / 8;
+      lo = nlo;
+    }
     while (lo < hi) {
       const int64_t mid = lo + ((hi - lo) >> 1);
       if (cdf[mid] > x) hi = mid; else lo = mid + 1;
