@@ -333,6 +333,55 @@ k_draw(const unsigned long long* __restrict__ cdf, int64_t J, int64_t T, uint64_
   if (t < T) draw_one(cdf, J, T, seed, mode, uniform, idx, scale, scale2, t);
 }
 
+// The nearly-optimal sampler of a mode with J <= kSmallSampleJ columns in one
+// launch: every workgroup computes the integer weights of k_weights and their
+// inclusive prefix sums (thread t sums a contiguous chunk, then one block
+// scan) into LDS -- workgroup 0 also writes them to w and cdf -- and then
+// draws t = 256 b + thread as k_draw does, searching the LDS copy.  The same
+// integers, hence the same indices and scales, as the three launches it
+// replaces (grid: ceil(T / 256)).
+constexpr int kSmallSampleJ = 6144;
+static __global__ void __launch_bounds__(kNT)
+k_sample_small(const double* __restrict__ norms, int64_t J,
+               const unsigned long long* __restrict__ max_bits, int kexp, int64_t T,
+               uint64_t seed, uint64_t mode, unsigned long long* __restrict__ w,
+               unsigned long long* __restrict__ cdf, int64_t* __restrict__ idx,
+               double* __restrict__ scale, double* __restrict__ scale2,
+               uint32_t* __restrict__ status) {
+  __shared__ unsigned long long cl[kSmallSampleJ];
+  __shared__ unsigned long long scr[kNT / kWave];
+  const double M = __longlong_as_double((long long)*max_bits);
+  const bool bad = !(M > 0.0) || !isfinite(M);
+  const double sc = ldexp(1.0, kexp);
+  const int Ji = (int)J;
+  const int E = (Ji + kNT - 1) / kNT;
+  const int a = min(Ji, (int)threadIdx.x * E), b = min(Ji, a + E);
+  unsigned long long local = 0;
+  for (int j = a; j < b; ++j) {
+    unsigned long long wj = 0;
+    const double n = norms[j];
+    if (!bad && n != 0.0) {
+      wj = (unsigned long long)floor((n / M) * sc);
+      if (wj < 1) wj = 1;
+    }
+    if (blockIdx.x == 0) w[j] = wj;
+    cl[j] = wj;
+    local += wj;
+  }
+  unsigned long long total;
+  unsigned long long run = block_exscan_u64(local, scr, &total);
+  for (int j = a; j < b; ++j) {
+    run += cl[j];
+    cl[j] = run;
+    if (blockIdx.x == 0) cdf[j] = run;
+  }
+  if (bad && status && blockIdx.x == 0 && threadIdx.x == 0)
+    atomicOr(status, isfinite(M) ? kDevZeroDist : (kDevNonFinite | kDevZeroDist));
+  __syncthreads();
+  const int64_t t = (int64_t)blockIdx.x * kNT + threadIdx.x;
+  if (t < T) draw_one(cl, J, T, seed, mode, 0, idx, scale, scale2, t);
+}
+
 // ---------------------------------------------------------------------------
 // K5  Gather C'(:, t) = A_(n)(:, idx[t]) (unscaled; the rescale enters the
 // products as the column weight scale^2).  grid = (T, ceil(I / 256)).

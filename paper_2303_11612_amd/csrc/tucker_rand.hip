@@ -465,6 +465,12 @@ int launch_sample(const double* norms, const unsigned long long* maxb, int64_t J
     int cl2 = 0;
     while (((int64_t)1 << cl2) < J) ++cl2;
     const int kexp = 60 - cl2;
+    if (J <= trk::kSmallSampleJ) {
+      hipLaunchKernelGGL(trk::k_sample_small, dim3((unsigned)cdiv(T, kNT)), dim3(kNT), 0, st,
+                         norms, J, maxb, kexp, T, seed, (uint64_t)mode, w, cdf, idx, scale,
+                         scale2, status);
+      return check_launch();
+    }
     const int64_t nb = cdiv(J, trk::kScanChunk);
     hipLaunchKernelGGL(trk::k_weights, dim3((unsigned)nb), dim3(kNT), 0, st, norms, J, maxb,
                        kexp, 0, w, bsum, status);
