@@ -73,6 +73,12 @@ def _norm_vectors():
     yield "zeros", 5000, n
     yield "tiny", 3, np.array([1.0, 2.0, 0.5])
     yield "one", 1, np.array([4.0])
+    # the largest mode sampled in one launch (every workgroup scans the
+    # weights in LDS) and the smallest one sampled by the three launches
+    for J in (6144, 6145):
+        n = rng.random(J) ** 3
+        n[::5] = 0.0
+        yield f"one_launch_edge_{J}", J, n
     # more than 1024 scan blocks of 1024 columns: the block offsets are
     # scanned by their own launch instead of inside the prefix-sum kernel
     J = 1200000
