@@ -491,12 +491,13 @@ k_ttm_ln(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
 // column each take a contiguous segment of ceil(I/S) rows (MU accumulators,
 // rows in increasing order), and the segment sums are added in segment order
 // in LDS; colscale (optional) multiplies column j's outputs.  Qt is row-major
-// with row stride MU.
+// with row stride MU.  Yc (optional): a second copy of Y in float32 (yc_f32)
+// or float64 (the caller's core, written by the last shrink).
 template <typename Tin, int MU, int S>
 __global__ void __launch_bounds__(kNT)
 k_ttm_seg(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
           const double* __restrict__ Qt, int kout, const double* __restrict__ colscale,
-          double* __restrict__ Y) {
+          double* __restrict__ Y, void* __restrict__ Yc, int yc_f32) {
   constexpr int CPB = kNT / S;  // columns per workgroup
   __shared__ double part[S][CPB][MU];
   const int cl = threadIdx.x % CPB, sg = threadIdx.x / CPB;
@@ -538,7 +539,12 @@ k_ttm_seg(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
       for (int g = 1; g < S; ++g) t += part[g][c][k];
       if (colscale) t *= colscale[jc];
       const int64_t rc = jc / L, lc = jc - rc * L;
-      Y[lc + L * (k + (int64_t)kout * rc)] = t;
+      const int64_t o = lc + L * (k + (int64_t)kout * rc);
+      Y[o] = t;
+      if (Yc) {
+        if (yc_f32) static_cast<float*>(Yc)[o] = (float)t;
+        else static_cast<double*>(Yc)[o] = t;
+      }
     }
   }
 }

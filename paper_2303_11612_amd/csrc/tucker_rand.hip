@@ -605,9 +605,11 @@ bool ttm1_mfma(const Tin* X, int64_t L, int64_t I, int64_t J, const double* Qt, 
   return true;
 }
 
+// Returns true when the kernel it ran also wrote the copy yc (k_ttm_seg).
 template <typename Tin, int MU>
-void ttm_w(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Qt, int kout,
-           const double* colscale, double* Y, double* split, hipStream_t st) {
+bool ttm_w(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Qt, int kout,
+           const double* colscale, double* Y, double* split, void* yc, int yc_f32,
+           hipStream_t st) {
   const int64_t J = L * R;
   const dim3 grid((unsigned)cdiv(J, kNT));
   const int64_t ns = ttm_splits(J, I);
@@ -618,14 +620,14 @@ void ttm_w(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Qt, int 
       // a view of a few hundred columns still spreads over the chip
       if (J < 1024 && I >= 256)
         hipLaunchKernelGGL((trk::k_ttm_seg<Tin, MU, 64>), dim3((unsigned)cdiv(J, kNT / 64)),
-                           dim3(kNT), 0, st, X, L, I, R, Qt, kout, colscale, Y);
+                           dim3(kNT), 0, st, X, L, I, R, Qt, kout, colscale, Y, yc, yc_f32);
       else if (J < 8192 && I >= 128)
         hipLaunchKernelGGL((trk::k_ttm_seg<Tin, MU, 32>), dim3((unsigned)cdiv(J, kNT / 32)),
-                           dim3(kNT), 0, st, X, L, I, R, Qt, kout, colscale, Y);
+                           dim3(kNT), 0, st, X, L, I, R, Qt, kout, colscale, Y, yc, yc_f32);
       else
         hipLaunchKernelGGL((trk::k_ttm_seg<Tin, MU, 16>), dim3((unsigned)cdiv(J, kNT / 16)),
-                           dim3(kNT), 0, st, X, L, I, R, Qt, kout, colscale, Y);
-      return;
+                           dim3(kNT), 0, st, X, L, I, R, Qt, kout, colscale, Y, yc, yc_f32);
+      return yc != nullptr;
     }
   }
   if (ns > 1 && split) {
@@ -635,38 +637,44 @@ void ttm_w(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Qt, int 
                        dim3(kNT), 0, st, X, L, I, R, Qt, ich, split);
     hipLaunchKernelGGL(trk::k_sum_splits, dim3((unsigned)cdiv(J * kout, kNT)), dim3(kNT), 0, st,
                        split, nsu, L, R, MU, kout, colscale, Y);
-    return;
+    return false;
   }
-  if (L == 1 && !colscale && ttm1_mfma(X, 1, I, R, Qt, MU, kout, Y, st)) return;
+  if (L == 1 && !colscale && ttm1_mfma(X, 1, I, R, Qt, MU, kout, Y, st)) return false;
   if (L == 1)
     hipLaunchKernelGGL((trk::k_ttm_l1<Tin, MU>), grid, dim3(kNT), 0, st, X, I, R, Qt, kout,
                        colscale, Y);
   else
     hipLaunchKernelGGL((trk::k_ttm_ln<Tin, MU>), grid, dim3(kNT), 0, st, X, L, I, R, Qt, kout,
                        colscale, Y);
+  return false;
 }
 
 // Y = X x_n Q^T with Qt of row stride `width` (zero-padded); outputs k < kout.
+// yc (optional): where a copy of Y is wanted (float32 if yc_f32); *yc_done
+// tells whether the kernel wrote it (else the caller casts Y).
 template <typename Tin>
 int ttm_t(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Qt, int width, int kout,
-          const double* colscale, double* Y, double* split, hipStream_t st) {
+          const double* colscale, double* Y, double* split, hipStream_t st,
+          void* yc = nullptr, int yc_f32 = 0, bool* yc_done = nullptr) {
+  bool done = false;
   switch (width) {
-    case 4: ttm_w<Tin, 4>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
-    case 8: ttm_w<Tin, 8>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
-    case 12: ttm_w<Tin, 12>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
-    case 16: ttm_w<Tin, 16>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
-    case 20: ttm_w<Tin, 20>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
-    case 24: ttm_w<Tin, 24>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
-    case 32: ttm_w<Tin, 32>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
-    case 40: ttm_w<Tin, 40>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
-    case 48: ttm_w<Tin, 48>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
-    case 64: ttm_w<Tin, 64>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
-    case 80: ttm_w<Tin, 80>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
-    case 96: ttm_w<Tin, 96>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
-    case 112: ttm_w<Tin, 112>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
-    case 128: ttm_w<Tin, 128>(X, L, I, R, Qt, kout, colscale, Y, split, st); break;
+    case 4: done = ttm_w<Tin, 4>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32, st); break;
+    case 8: done = ttm_w<Tin, 8>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32, st); break;
+    case 12: done = ttm_w<Tin, 12>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32, st); break;
+    case 16: done = ttm_w<Tin, 16>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32, st); break;
+    case 20: done = ttm_w<Tin, 20>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32, st); break;
+    case 24: done = ttm_w<Tin, 24>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32, st); break;
+    case 32: done = ttm_w<Tin, 32>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32, st); break;
+    case 40: done = ttm_w<Tin, 40>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32, st); break;
+    case 48: done = ttm_w<Tin, 48>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32, st); break;
+    case 64: done = ttm_w<Tin, 64>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32, st); break;
+    case 80: done = ttm_w<Tin, 80>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32, st); break;
+    case 96: done = ttm_w<Tin, 96>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32, st); break;
+    case 112: done = ttm_w<Tin, 112>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32, st); break;
+    case 128: done = ttm_w<Tin, 128>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32, st); break;
     default: return TR_ENOTSUP;
   }
+  if (yc_done) *yc_done = done;
   return check_launch();
 }
 
@@ -674,9 +682,12 @@ int ttm_t(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Qt, int w
 // doubles), or NULL to always use the one-pass kernels.
 int launch_ttm(bool in_f64, const void* X, int64_t L, int64_t I, int64_t R, const double* Qt,
                int width, int kout, const double* colscale, double* Y, double* split,
-               hipStream_t st) {
-  if (in_f64) return ttm_t((const double*)X, L, I, R, Qt, width, kout, colscale, Y, split, st);
-  return ttm_t((const float*)X, L, I, R, Qt, width, kout, colscale, Y, split, st);
+               hipStream_t st, void* yc = nullptr, int yc_f32 = 0, bool* yc_done = nullptr) {
+  if (in_f64)
+    return ttm_t((const double*)X, L, I, R, Qt, width, kout, colscale, Y, split, st, yc, yc_f32,
+                 yc_done);
+  return ttm_t((const float*)X, L, I, R, Qt, width, kout, colscale, Y, split, st, yc, yc_f32,
+               yc_done);
 }
 
 int launch_cast(const double* src, int64_t n, bool to_f32, void* dst, hipStream_t st) {
@@ -1400,6 +1411,7 @@ int shrink(const Plan& P, int n, int step, const void* cur, bool cur_f64, int64_
   const ModePlan& M = P.m[n];
   const bool last = n == P.N - 1;
   double* dst = at<double>(ws, last ? P.oCore : ((step % 2 == 0) ? P.oX0 : P.oX1));
+  bool cast_done = false;  // the last shrink's kernel wrote the caller's core too
   {
     TimeScope ts(tm, TR_KC_TTM, n, st);
     // (the fixed-precision driver shrinks views its plan did not size the
@@ -1414,9 +1426,10 @@ int shrink(const Plan& P, int n, int step, const void* cur, bool cur_f64, int64_
                               status, st));
     else
       TR_TRY(launch_ttm(cur_f64, cur, L, I, R, at<double>(ws, P.oQt[n]), M.muw, (int)M.mu,
-                        nullptr, dst, split, st));
+                        nullptr, dst, split, st, last ? core : nullptr, P.dtype == TR_F32,
+                        &cast_done));
   }
-  if (last) TR_TRY(launch_cast(dst, L * M.mu * R, P.dtype == TR_F32, core, st));
+  if (last && !cast_done) TR_TRY(launch_cast(dst, L * M.mu * R, P.dtype == TR_F32, core, st));
   *out = dst;
   return TR_OK;
 }
