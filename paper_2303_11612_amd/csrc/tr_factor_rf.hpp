@@ -642,7 +642,8 @@ template <int SM, int R, int MU>
 __global__ void __launch_bounds__(256)
 k_factor_rf(FactorJobs jobs, int cast_f32, uint32_t* __restrict__ status) {
   factor_rf_body<SM, R, MU>(jobs.j[blockIdx.x], cast_f32, status, g_rf_code_end<SM, R, MU, 0>);
-  if (threadIdx.x == 0 && blockIdx.x == 0) g_rf_code_end<SM, R, MU, 0> = __builtin_amdgcn_s_getpc();
+  if (threadIdx.x == 0 && blockIdx.x == 0)
+    g_rf_code_end<SM, R, MU, 0> = __builtin_amdgcn_s_getpc();
 }
 
 // Jobs from a device table (the batched driver, whose batches outnumber the
@@ -654,7 +655,8 @@ k_factor_rf_tab(const FactorJob* __restrict__ tab, int cast_f32, uint32_t* const
   factor_rf_body<SM, R, MU>(tab[blockIdx.x], cast_f32,
                             status_tab ? status_tab[blockIdx.x] : nullptr,
                             g_rf_code_end<SM, R, MU, 1>);
-  if (threadIdx.x == 0 && blockIdx.x == 0) g_rf_code_end<SM, R, MU, 1> = __builtin_amdgcn_s_getpc();
+  if (threadIdx.x == 0 && blockIdx.x == 0)
+    g_rf_code_end<SM, R, MU, 1> = __builtin_amdgcn_s_getpc();
 }
 
 }  // namespace trk

@@ -14,6 +14,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "tr_factor.hpp"
@@ -657,21 +658,26 @@ int ttm_t(const Tin* X, int64_t L, int64_t I, int64_t R, const double* Qt, int w
           const double* colscale, double* Y, double* split, hipStream_t st,
           void* yc = nullptr, int yc_f32 = 0, bool* yc_done = nullptr) {
   bool done = false;
+  // one instance per padded row width
+  auto run = [&](auto w) -> bool {
+    return ttm_w<Tin, decltype(w)::value>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32,
+                                          st);
+  };
   switch (width) {
-    case 4: done = ttm_w<Tin, 4>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32, st); break;
-    case 8: done = ttm_w<Tin, 8>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32, st); break;
-    case 12: done = ttm_w<Tin, 12>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32, st); break;
-    case 16: done = ttm_w<Tin, 16>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32, st); break;
-    case 20: done = ttm_w<Tin, 20>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32, st); break;
-    case 24: done = ttm_w<Tin, 24>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32, st); break;
-    case 32: done = ttm_w<Tin, 32>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32, st); break;
-    case 40: done = ttm_w<Tin, 40>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32, st); break;
-    case 48: done = ttm_w<Tin, 48>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32, st); break;
-    case 64: done = ttm_w<Tin, 64>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32, st); break;
-    case 80: done = ttm_w<Tin, 80>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32, st); break;
-    case 96: done = ttm_w<Tin, 96>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32, st); break;
-    case 112: done = ttm_w<Tin, 112>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32, st); break;
-    case 128: done = ttm_w<Tin, 128>(X, L, I, R, Qt, kout, colscale, Y, split, yc, yc_f32, st); break;
+    case 4: done = run(std::integral_constant<int, 4>{}); break;
+    case 8: done = run(std::integral_constant<int, 8>{}); break;
+    case 12: done = run(std::integral_constant<int, 12>{}); break;
+    case 16: done = run(std::integral_constant<int, 16>{}); break;
+    case 20: done = run(std::integral_constant<int, 20>{}); break;
+    case 24: done = run(std::integral_constant<int, 24>{}); break;
+    case 32: done = run(std::integral_constant<int, 32>{}); break;
+    case 40: done = run(std::integral_constant<int, 40>{}); break;
+    case 48: done = run(std::integral_constant<int, 48>{}); break;
+    case 64: done = run(std::integral_constant<int, 64>{}); break;
+    case 80: done = run(std::integral_constant<int, 80>{}); break;
+    case 96: done = run(std::integral_constant<int, 96>{}); break;
+    case 112: done = run(std::integral_constant<int, 112>{}); break;
+    case 128: done = run(std::integral_constant<int, 128>{}); break;
     default: return TR_ENOTSUP;
   }
   if (yc_done) *yc_done = done;
