@@ -134,6 +134,26 @@ def test_gather_bit_exact(dtype):
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("shape", [(12, 40, 100), (7, 300, 70)])
+def test_gather_many_slabs_bit_exact(dtype, shape):
+    """Inner-mode views with many slabs (R >= 64): uniform samples with
+    repeats, every sample in one slab, and 8192 / 8193 samples."""
+    A = _rand_tensor(shape, dtype, 6)
+    X = tr.to_device(A)
+    rng = np.random.default_rng(1)
+    L, I, R = shape[0], shape[1], shape[2]
+    want_all = oracle.unfold(A, 1)
+    cases = [rng.integers(0, L * R, size=333),
+             5 * L + rng.integers(0, L, size=500),
+             rng.integers(0, L * R, size=8192),
+             rng.integers(0, L * R, size=8193)]
+    for idx in cases:
+        idx[:2] = [0, L * R - 1]
+        Cp = _np(tr.tucker_rand_gather(X, L, I, R, torch.tensor(idx, device=DEV)))
+        assert Cp.dtype == A.dtype and np.array_equal(Cp, want_all[:, idx]), (shape, len(idx))
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
 @pytest.mark.parametrize("q", [1, 2])
 def test_power_products_match_oracle(dtype, q):
     shape = (70, 90, 33)
