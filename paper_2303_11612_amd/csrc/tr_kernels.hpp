@@ -386,16 +386,61 @@ k_sample_small(const double* __restrict__ norms, int64_t J,
 // K5  Gather C'(:, t) = A_(n)(:, idx[t]) (unscaled; the rescale enters the
 // products as the column weight scale^2).  grid = (T, ceil(I / 256)).
 // ---------------------------------------------------------------------------
+// perm (optional): the samples in slab order (k_bucket_samples); workgroup b
+// then copies sample perm[(b mod 8) ceil(T/8) + b / 8], so that the samples
+// of a slab, whose elements share lines, run on one XCD (workgroups go to the
+// eight XCDs in turn) and meet those lines in its L2 (grid: 8 ceil(T/8)).
+__device__ __forceinline__ int64_t gather_sample(const int* __restrict__ perm, int64_t Tn) {
+  if (!perm) return blockIdx.x;
+  const int64_t pos = (int64_t)(blockIdx.x % 8) * ((Tn + 7) / 8) + blockIdx.x / 8;
+  return pos < Tn ? perm[pos] : -1;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kNT)
 k_gather(const T* __restrict__ X, int64_t L, int64_t I, const int64_t* __restrict__ idx,
-         T* __restrict__ Cp) {
-  const int64_t t = blockIdx.x;
+         T* __restrict__ Cp, const int* __restrict__ perm, int64_t Tn) {
+  const int64_t t = gather_sample(perm, Tn);
+  if (t < 0) return;
   const int64_t i = (int64_t)blockIdx.y * kNT + threadIdx.x;
   if (i >= I) return;
   const int64_t j = idx[t];
   const int64_t r = j / L, l = j - r * L;
   Cp[i + I * t] = X[l + L * (i + I * r)];
+}
+
+// The samples of an L x I x R view in slab order (slab r = columns
+// l + L r): perm lists the sample indices t slab by slab, in any order within
+// a slab (a counting sort: bin counts, their exclusive scan, then each sample
+// takes the next place of its bin).  One workgroup of 1024 threads; R <=
+// kBucketR; every idx in [0, L R).
+constexpr int kBucketR = 8192;
+static __global__ void __launch_bounds__(1024)
+k_bucket_samples(const int64_t* __restrict__ idx, int64_t Tn, int64_t L, int64_t R,
+                 int* __restrict__ perm) {
+  __shared__ int cnt[kBucketR];
+  __shared__ unsigned long long scr[1024 / kWave];
+  const int Ri = (int)R;
+  for (int b = threadIdx.x; b < Ri; b += 1024) cnt[b] = 0;
+  __syncthreads();
+  for (int64_t t = threadIdx.x; t < Tn; t += 1024) atomicAdd(&cnt[(int)(idx[t] / L)], 1);
+  __syncthreads();
+  const int per = (Ri + 1023) / 1024;
+  const int a = min(Ri, (int)threadIdx.x * per), b = min(Ri, a + per);
+  unsigned long long local = 0;
+  for (int k = a; k < b; ++k) local += (unsigned)cnt[k];
+  unsigned long long total;
+  unsigned long long run = block_exscan_u64(local, scr, &total);
+  for (int k = a; k < b; ++k) {
+    const int c = cnt[k];
+    cnt[k] = (int)run;
+    run += (unsigned)c;
+  }
+  __syncthreads();
+  for (int64_t t = threadIdx.x; t < Tn; t += 1024) {
+    const int pos = atomicAdd(&cnt[(int)(idx[t] / L)], 1);
+    perm[pos] = (int)t;
+  }
 }
 
 // ---------------------------------------------------------------------------

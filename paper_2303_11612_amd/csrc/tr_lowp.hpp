@@ -160,9 +160,12 @@ template <typename Tin, typename OP>
 __global__ void __launch_bounds__(kNT)
 k_gather_lp(const Tin* __restrict__ X, int64_t L, int64_t I, const int64_t* __restrict__ idx,
             int Ip, const double* __restrict__ scale2, typename OP::stor* __restrict__ Cq,
-            float* __restrict__ omega) {
+            float* __restrict__ omega, const int* __restrict__ perm, int64_t Tn) {
   __shared__ float red[kNT / kWave];
-  const int64_t t = blockIdx.x;
+  // perm: the samples in slab order, as for k_gather (the whole workgroup
+  // leaves together when its place is past T)
+  const int64_t t = gather_sample(perm, Tn);
+  if (t < 0) return;
   const int64_t j = idx[t];
   const int64_t r = j / L, l = j - r * L;
   const Tin* col = X + l + L * I * r;
