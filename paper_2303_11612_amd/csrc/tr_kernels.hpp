@@ -413,17 +413,27 @@ k_gather(const T* __restrict__ X, int64_t L, int64_t I, const int64_t* __restric
 // l + L r): perm lists the sample indices t slab by slab, in any order within
 // a slab (a counting sort: bin counts, their exclusive scan, then each sample
 // takes the next place of its bin).  One workgroup of 1024 threads; R <=
-// kBucketR; every idx in [0, L R).
-constexpr int kBucketR = 8192;
+// kBucketR, T <= kBucketT, L R < 2^32; every idx in [0, L R).
+constexpr int kBucketR = 8192, kBucketT = 16384;
 static __global__ void __launch_bounds__(1024)
 k_bucket_samples(const int64_t* __restrict__ idx, int64_t Tn, int64_t L, int64_t R,
                  int* __restrict__ perm) {
+  constexpr int PT = kBucketT / 1024;  // samples per thread, their slabs kept in registers
   __shared__ int cnt[kBucketR];
   __shared__ unsigned long long scr[1024 / kWave];
   const int Ri = (int)R;
   for (int b = threadIdx.x; b < Ri; b += 1024) cnt[b] = 0;
+  int rs[PT];
+#pragma unroll
+  for (int m = 0; m < PT; ++m) {
+    const int64_t t = threadIdx.x + 1024 * m;
+    // L R < 2^32 (host): a 32-bit division
+    rs[m] = t < Tn ? (int)((uint32_t)idx[t] / (uint32_t)L) : -1;
+  }
   __syncthreads();
-  for (int64_t t = threadIdx.x; t < Tn; t += 1024) atomicAdd(&cnt[(int)(idx[t] / L)], 1);
+#pragma unroll
+  for (int m = 0; m < PT; ++m)
+    if (rs[m] >= 0) atomicAdd(&cnt[rs[m]], 1);
   __syncthreads();
   const int per = (Ri + 1023) / 1024;
   const int a = min(Ri, (int)threadIdx.x * per), b = min(Ri, a + per);
@@ -437,10 +447,9 @@ k_bucket_samples(const int64_t* __restrict__ idx, int64_t Tn, int64_t L, int64_t
     run += (unsigned)c;
   }
   __syncthreads();
-  for (int64_t t = threadIdx.x; t < Tn; t += 1024) {
-    const int pos = atomicAdd(&cnt[(int)(idx[t] / L)], 1);
-    perm[pos] = (int)t;
-  }
+#pragma unroll
+  for (int m = 0; m < PT; ++m)
+    if (rs[m] >= 0) perm[atomicAdd(&cnt[rs[m]], 1)] = (int)threadIdx.x + 1024 * m;
 }
 
 // ---------------------------------------------------------------------------

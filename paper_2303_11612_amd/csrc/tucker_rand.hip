@@ -501,8 +501,8 @@ int slab_order(bool f64, int64_t L, int64_t R, const int64_t* idx, int64_t T, in
                int** perm, hipStream_t st) {
   *perm = nullptr;
   const int64_t row_bytes = L * (f64 ? 8 : 4);
-  if (perm_ws && row_bytes >= 512 && R >= 64 && R <= trk::kBucketR &&
-      T < ((int64_t)1 << 31)) {
+  if (perm_ws && row_bytes >= 512 && R >= 64 && R <= trk::kBucketR && T <= trk::kBucketT &&
+      L * R < ((int64_t)1 << 32)) {
     hipLaunchKernelGGL(trk::k_bucket_samples, dim3(1), dim3(1024), 0, st, idx, T, L, R, perm_ws);
     TR_TRY(check_launch());
     *perm = perm_ws;
