@@ -40,7 +40,7 @@ template <typename Tin, int NKT, bool WPT = false>
 __global__ void __launch_bounds__(kPwWaves * kWave)
 k_pw_w(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
        const double* __restrict__ colw, const double* __restrict__ Yt, int sw,
-       double* __restrict__ W) {
+       double* __restrict__ W, const int64_t* __restrict__ gidx = nullptr) {
   constexpr int SP = 16 * NKT;
   constexpr int kSplit = WPT ? 1 : kPwWaves;  // waves sharing a tile's rows
   __shared__ f64x4 red[WPT ? 1 : kPwWaves - 1][NKT][kWave];
@@ -52,8 +52,9 @@ k_pw_w(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
   const int64_t j = tile * 16 + h;
   const bool jok = j < J;
   const int64_t jc = jok ? j : J - 1;
-  const int64_t r = jc / L;
-  const Tin* xc = X + (jc - r * L) + L * I * r;  // X_(n)(i, jc) = xc[L i]
+  const int64_t js = gidx ? gidx[jc] : jc;  // gathered through the index (L == 1)
+  const int64_t r = js / L;
+  const Tin* xc = X + (js - r * L) + L * I * r;  // X_(n)(i, js) = xc[L i]
   const int64_t nch = (I + 15) / 16;             // chunks of 16 rows
   f64x4 acc[NKT];
 #pragma unroll
@@ -124,7 +125,8 @@ k_pw_w(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
 template <typename Tin, int NKT, int MT>
 __global__ void __launch_bounds__(kPwWaves * kWave)
 k_pw_y(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
-       const double* __restrict__ W, int s, int64_t jper, double* __restrict__ part) {
+       const double* __restrict__ W, int s, int64_t jper, double* __restrict__ part,
+       const int64_t* __restrict__ gidx = nullptr) {
   constexpr int SP = 16 * NKT;
   __shared__ f64x4 red[kPwWaves - 1][MT][NKT][kWave];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -158,13 +160,15 @@ k_pw_y(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
 #pragma unroll
       for (int u = 0; u < kPwBatch; ++u) {
         const int64_t j = j0 + 4 * u + g;
-        const int64_t base = l + LI * r;
+        const int64_t jw = j < jz ? j : jz - 1;
+        // through the index (L == 1): column gidx[j] of the source, whose
+        // rows are all in range
+        const int64_t base = gidx ? I * gidx[jw] : l + LI * r;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
           const int64_t e = base + roff[mt];
-          xr[u][mt] = X[e < nX ? e : nX - 1];
+          xr[u][mt] = X[gidx ? e : (e < nX ? e : nX - 1)];
         }
-        const int64_t jw = j < jz ? j : jz - 1;
 #pragma unroll
         for (int kt = 0; kt < NKT; ++kt) wr[u][kt] = W[jw * SP + 16 * kt + h];
         l += 4;

@@ -727,30 +727,36 @@ int launch_cast(const double* src, int64_t n, bool to_f32, void* dst, hipStream_
   return check_launch();
 }
 
+// gidx (optional, L == 1): column j of the product is column gidx[j] of X,
+// which then has at least max gidx + 1 columns (the sampled C' read in place).
 template <typename Tin, int NKT>
 int pw_step(const Tin* X, int64_t L, int64_t I, int64_t R, const double* colw, const double* Yt,
-            int sw, int s, double* W, double* part, int64_t* nparts, hipStream_t st) {
+            int sw, int s, double* W, double* part, int64_t* nparts, hipStream_t st,
+            const int64_t* gidx) {
   const int64_t J = L * R;
   // W = X^T Y has the shape of the mode-1 shrink with Q^T = Yt: the
   // persistent MFMA kernel (Yt staged in LDS, next tile in flight) when there
   // are no column weights and enough columns to occupy it (with few columns
   // k_pw_w's one-tile blocks, rows split over four waves, are faster)
   const bool many = cdiv(J, 16 * trk::kPwWaves) >= 1024;
-  if (!colw && many && ttm1_mfma(X, L, I, J, Yt, sw, 16 * NKT, W, st)) {
+  if (!gidx && !colw && many && ttm1_mfma(X, L, I, J, Yt, sw, 16 * NKT, W, st)) {
     TR_TRY(check_launch());
   } else if (many)
     // many columns: a tile per wave (no reduction across waves) still gives
     // at least four workgroups per compute unit
     hipLaunchKernelGGL((trk::k_pw_w<Tin, NKT, true>), dim3((unsigned)cdiv(J, 16 * trk::kPwWaves)),
-                       dim3(trk::kPwWaves * trk::kWave), 0, st, X, L, I, R, colw, Yt, sw, W);
+                       dim3(trk::kPwWaves * trk::kWave), 0, st, X, L, I, R, colw, Yt, sw, W,
+                       gidx);
   else
     hipLaunchKernelGGL((trk::k_pw_w<Tin, NKT>), dim3((unsigned)cdiv(J, 16)),
-                       dim3(trk::kPwWaves * trk::kWave), 0, st, X, L, I, R, colw, Yt, sw, W);
+                       dim3(trk::kPwWaves * trk::kWave), 0, st, X, L, I, R, colw, Yt, sw, W,
+                       gidx);
   TR_TRY(check_launch());
   const int64_t jper = cdiv(J, pw_splits(I, J));
   const int64_t ny = cdiv(J, jper);
   hipLaunchKernelGGL((trk::k_pw_y<Tin, NKT, kPwMT>), dim3((unsigned)pw_itiles(I), (unsigned)ny),
-                     dim3(trk::kPwWaves * trk::kWave), 0, st, X, L, I, R, W, s, jper, part);
+                     dim3(trk::kPwWaves * trk::kWave), 0, st, X, L, I, R, W, s, jper, part,
+                     gidx);
   *nparts = ny;
   return check_launch();
 }
@@ -758,17 +764,17 @@ int pw_step(const Tin* X, int64_t L, int64_t I, int64_t R, const double* colw, c
 template <typename Tin>
 int pw_step_t(const Tin* X, int64_t L, int64_t I, int64_t R, const double* colw,
               const double* Yt, int sw, int64_t s, double* W, double* part, int64_t* nparts,
-              hipStream_t st) {
+              hipStream_t st, const int64_t* gidx = nullptr) {
   const int si = (int)s;
   switch (pw_nkt(s)) {
-    case 1: return pw_step<Tin, 1>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st);
-    case 2: return pw_step<Tin, 2>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st);
-    case 3: return pw_step<Tin, 3>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st);
-    case 4: return pw_step<Tin, 4>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st);
-    case 5: return pw_step<Tin, 5>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st);
-    case 6: return pw_step<Tin, 6>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st);
-    case 7: return pw_step<Tin, 7>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st);
-    case 8: return pw_step<Tin, 8>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st);
+    case 1: return pw_step<Tin, 1>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st, gidx);
+    case 2: return pw_step<Tin, 2>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st, gidx);
+    case 3: return pw_step<Tin, 3>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st, gidx);
+    case 4: return pw_step<Tin, 4>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st, gidx);
+    case 5: return pw_step<Tin, 5>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st, gidx);
+    case 6: return pw_step<Tin, 6>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st, gidx);
+    case 7: return pw_step<Tin, 7>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st, gidx);
+    case 8: return pw_step<Tin, 8>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st, gidx);
     default: return TR_ENOTSUP;
   }
 }
@@ -783,18 +789,24 @@ size_t power_ws_bytes(int64_t L, int64_t I, int64_t R, int64_t s, bool f64) {
 
 // C = (X_(n) D X_(n)^T)^q G by the two halves of Strategy A, starting from
 // Yt = G^T (row stride sw, zero-padded).  Z, part: scratch.
+// gidx (optional, L == 1): the product's column j is column gidx[j] of X
+// (sampled columns read in place; not with the one-sweep kernel).
 int run_power(bool f64, const void* X, int64_t L, int64_t I, int64_t R, const double* colw,
               int q, int64_t s, int sw, double* Y, double* Yt, double* Z, double* part,
-              uint32_t* status, hipStream_t st, bool fused = true) {
+              uint32_t* status, hipStream_t st, bool fused = true,
+              const int64_t* gidx = nullptr) {
   for (int step = 0; step < q; ++step) {
     int64_t nused = 0;
     // one sweep with W kept on chip when the rows and the sketch are narrow
-    const int rc = fused ? launch_pw_fused(f64, X, L, I, R, colw, Yt, sw, s, part, &nused, st)
-                         : TR_ENOTSUP;
+    const int rc = fused && !gidx
+                       ? launch_pw_fused(f64, X, L, I, R, colw, Yt, sw, s, part, &nused, st)
+                       : TR_ENOTSUP;
     if (rc != TR_OK && rc != TR_ENOTSUP) return rc;
     if (rc == TR_ENOTSUP) {
-      if (f64) TR_TRY(pw_step_t((const double*)X, L, I, R, colw, Yt, sw, s, Z, part, &nused, st));
-      else TR_TRY(pw_step_t((const float*)X, L, I, R, colw, Yt, sw, s, Z, part, &nused, st));
+      if (f64)
+        TR_TRY(pw_step_t((const double*)X, L, I, R, colw, Yt, sw, s, Z, part, &nused, st, gidx));
+      else
+        TR_TRY(pw_step_t((const float*)X, L, I, R, colw, Yt, sw, s, Z, part, &nused, st, gidx));
     }
     hipLaunchKernelGGL(trk::k_reduce_parts, dim3((unsigned)cdiv(I * s, kNT)), dim3(kNT), 0, st,
                        part, nused, I, (int)s, sw, Y, Yt, status);
@@ -1208,6 +1220,7 @@ int range_sketch(const Plan& P, int n, const void* X, void* ws, const tr_diag* d
   bool src_f64 = M.src_f64;
   int64_t L = M.L, R = M.R;
   const double* colw = nullptr;
+  const int64_t* gidx = nullptr;  // sampled columns read in place (contiguous fibers)
   const bool lp = M.lp;
   if (M.sampled) {
     double* norms = at<double>(ws, P.oNorms);
@@ -1240,6 +1253,10 @@ int range_sketch(const Plan& P, int n, const void* X, void* ws, const tr_diag* d
         TR_TRY(launch_gather_lp(P.prec, M.src_f64, X, M.L, M.I, idx, M.T, scale2,
                                 at<void>(ws, P.oCq), at<float>(ws, P.oOmega), st, M.R,
                                 at<int>(ws, P.oW)));
+      else if (M.L == 1 && !(P.fused && pw_fused_ok(M.I, M.T, M.s)))
+        // contiguous columns, and the products are the two-kernel ones:
+        // they read C' = X(:, idx) in place, without the gathered copy
+        gidx = idx;
       else
         TR_TRY(launch_gather(M.src_f64, X, M.L, M.I, idx, M.T, at<void>(ws, P.oCp), st, M.R,
                              at<int>(ws, P.oW)));  // the weights are spent by now
@@ -1248,7 +1265,7 @@ int range_sketch(const Plan& P, int n, const void* X, void* ws, const tr_diag* d
       TR_TRY(copy_d2d(diag->indices[n], idx, 8 * (size_t)M.T, st));
     if (diag && diag->scales && diag->scales[n])
       TR_TRY(copy_d2d(diag->scales[n], scale, 8 * (size_t)M.T, st));
-    src = at<void>(ws, P.oCp);
+    if (!gidx) src = at<void>(ws, P.oCp);
     L = 1;
     R = M.T;
     colw = scale2;
@@ -1277,13 +1294,13 @@ int range_sketch(const Plan& P, int n, const void* X, void* ws, const tr_diag* d
     double* Ys[1] = {Y};
     for (int step = 0; step < P.q; ++step) {
       TR_TRY(run_power(src_f64, src, L, M.I, R, colw, 1, M.s, M.sw, Y, Yt, Z, part, status, st,
-                       P.fused));
+                       P.fused, gidx));
       TR_TRY(stab_orth(P, &n, 1, Ys, Zts, false, ws, status, st));
     }
   } else {
     TimeScope ts(tm, TR_KC_POWER, n, st);
     TR_TRY(run_power(src_f64, src, L, M.I, R, colw, P.q, M.s, M.sw, Y, Yt, Z, part, status, st,
-                     P.fused));
+                     P.fused, gidx));
   }
   // (with R-accumulation the sketch Z_q Rbar is written by the final factor step)
   if (!P.racc && diag && diag->sketch && diag->sketch[n])
