@@ -35,8 +35,8 @@ sample matrix C' with D = diag(scale_t^2)):
   holds every bfloat16 and every e4m3 value exactly.
 
 For q > 1 the power scheme runs in its R-accumulated form: Z_0 R_0 = G and
-Z_i R_i = M D M^T Z_{i-1} (i = 1..q), where Z_i is the iterate's s left
-singular vectors with the canonical signs and R_i = Z_i^T (M D M^T Z_{i-1}),
+Z_i R_i = M D M^T Z_{i-1} (i = 1..q), where Z_i is the orthonormal QR factor
+of the iterate with the canonical signs and R_i = Z_i^T (M D M^T Z_{i-1}),
 and C_n = Z_q Rbar with Rbar = R_q ... R_0, equal to (M D M^T)^q G in exact
 arithmetic.  Only orthonormal iterates are rounded to the operand format, so
 directions far below the leading one survive the rounding.
@@ -49,7 +49,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .tucker import gaussian_matrix, leading_left_singular_vectors, unfold
+from .tucker import canonical_signs, gaussian_matrix, leading_left_singular_vectors, unfold
 
 FP8_MAX = 448.0
 BLOCK = 32
@@ -177,9 +177,10 @@ def power_sketch_lp(X: np.ndarray, n: int, s: int, q: int, prec: str, seed: int,
 
 
 def _orth(Y: np.ndarray):
-    """(Z, R) with Z the s left singular vectors of Y (canonical signs) and
-    R = Z^T Y, so that Y = Z R."""
-    Z, _ = leading_left_singular_vectors(Y, Y.shape[1])
+    """(Z, R) with Z the orthonormal factor of the QR factorization of Y
+    (canonical signs) and R = Z^T Y, so that Y = Z R."""
+    Q, _ = np.linalg.qr(np.asarray(Y, dtype=np.float64))
+    Z = canonical_signs(Q)
     return Z, Z.T @ Y
 
 

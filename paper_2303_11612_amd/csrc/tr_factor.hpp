@@ -71,6 +71,10 @@ struct FactorJob {
   double* gA;
   int I, s, mu, ldqt;
   double* gW;  // wide variant (s > 64): scratch for the two s x s matrices
+  // orthonormal basis only (the register-resident kernel): Q = the first mu
+  // columns of the Householder QR's Q1 with canonical signs, no SVD (the
+  // power scheme's orthonormalisation between steps); sig is not written
+  int qr_only;
 };
 constexpr int kMaxFactorJobs = 8;
 // Independent factorizations launched together, one workgroup each (by value

@@ -185,6 +185,7 @@ __device__ __forceinline__ void factor_rf_body(const FactorJob& jb, int cast_f32
                                                unsigned long long code_end) {
   const double* __restrict__ C = jb.C;
   const int I = jb.I, s = jb.s, mu = jb.mu, ldqt = jb.ldqt;
+  const bool qr_only = jb.qr_only != 0;  // Q1's leading columns, no SVD
   double* __restrict__ Q = jb.Q;
   double* __restrict__ Qt = jb.Qt;
   double* __restrict__ sig_out = jb.sig;
@@ -282,7 +283,7 @@ __device__ __forceinline__ void factor_rf_body(const FactorJob& jb, int cast_f32
 
   // ---- 2. QR of M = R1^T by wave 0: lane j holds column j of M (row j of
   //         R1, in thread j's registers); column k is broadcast by readlane ----
-  if (wid == 0) {
+  if (wid == 0 && !qr_only) {
     double m[SM];
 #pragma unroll
     for (int i = 0; i < SM; ++i) m[i] = (i >= lane && i < s) ? a[0][i] : 0.0;
@@ -336,7 +337,7 @@ __device__ __forceinline__ void factor_rf_body(const FactorJob& jb, int cast_f32
   //         recomputed at the start of each sweep and then updated with each
   //         rotation (a' = a - t c, b' = b + t c).  The sweeps end after one
   //         without a rotation larger than tol_big (see below). ----
-  {
+  if (!qr_only) {
     // one wave up to 32 columns (no barrier between steps: measured 12 %
     // faster at SM = 24 than four waves with one); two lanes per pair would
     // be needed to fit 40 or 48 columns in one wave, which is slower
@@ -422,15 +423,16 @@ __device__ __forceinline__ void factor_rf_body(const FactorJob& jb, int cast_f32
   }
   __syncthreads();
 
-  // ---- 4. singular values, descending (ties: lower column first) ----
-  if (tid < s) {
+  // ---- 4. singular values, descending (ties: lower column first); for an
+  //         orthonormal basis only, U = I (Q1's columns in their order) ----
+  if (tid < s && !qr_only) {
     double t = 0.0;
 #pragma unroll
     for (int i = 0; i < SM; ++i) t = fma(X[tid * LDX + i], X[tid * LDX + i], t);
     sig[tid] = sqrt(t);
   }
   __syncthreads();
-  if (tid < s) {
+  if (tid < s && !qr_only) {
     const double me = sig[tid];
     int rank = 0;
     for (int q = 0; q < s; ++q) {
@@ -445,6 +447,10 @@ __device__ __forceinline__ void factor_rf_body(const FactorJob& jb, int cast_f32
   __syncthreads();
   for (int e = tid; e < mu * SM; e += NT) {
     const int c = e / SM, i = e % SM;
+    if (qr_only) {
+      U[c * LDX + i] = (i < s && i == c) ? 1.0 : 0.0;
+      continue;
+    }
     const int pc = perm[c];
     const double sg = sig[pc];
     const double xv = X[pc * LDX + i];

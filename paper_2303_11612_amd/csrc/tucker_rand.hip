@@ -909,9 +909,12 @@ int stab_orth(const Plan& P, const int* modes, int k, double* const* C, double* 
   for (int b = 0; b < k; ++b) {
     const int n = modes[b];
     const ModePlan& M = P.m[n];
+    // an orthonormal basis of C only: the Householder QR's Q1 (no SVD) where
+    // the register-resident kernel runs; the wider kernels' SVD basis spans
+    // the same space
     jobs[b] = trk::FactorJob{C[b], at<double>(ws, P.oZn[n]), Zt[b], at<double>(ws, P.oSgs[n]),
                              nullptr, at<double>(ws, P.oGA[n]), (int)M.I, (int)M.s, (int)M.s,
-                             Zt[b] ? M.sw : 0};
+                             Zt[b] ? M.sw : 0, nullptr, 1};
   }
   TR_TRY(launch_factor_jobs(jobs, k, 0, status, st));
   for (int b = 0; b < k; ++b) {
