@@ -121,12 +121,15 @@ k_pw_w(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
 // 16 MT x .. 16 MT (x + 1), column range [y jper, (y + 1) jper); its four
 // waves take consecutive quarters of the range (multiples of 4 columns) and
 // their tiles are added in LDS (wave order 0..3).  The partial sums of the
-// ranges are added by k_reduce_parts in increasing b.
+// ranges are added by k_reduce_parts in increasing b.  With one range and Y
+// set, the block writes what k_reduce_parts would instead: Y (column-major
+// I x s), its row-major copy Yt (row stride ldyt) and the non-finite flag.
 template <typename Tin, int NKT, int MT>
 __global__ void __launch_bounds__(kPwWaves * kWave)
 k_pw_y(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
        const double* __restrict__ W, int s, int64_t jper, double* __restrict__ part,
-       const int64_t* __restrict__ gidx = nullptr) {
+       const int64_t* __restrict__ gidx = nullptr, double* __restrict__ Y = nullptr,
+       double* __restrict__ Yt = nullptr, int ldyt = 0, uint32_t* __restrict__ status = nullptr) {
   constexpr int SP = 16 * NKT;
   __shared__ f64x4 red[kPwWaves - 1][MT][NKT][kWave];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -213,7 +216,15 @@ k_pw_y(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R,
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int64_t i = ib + 16 * mt + g + 4 * q;
-          if (i < I && k < s) out[i + I * k] = v[q];
+          if (i < I && k < s) {
+            if (Y) {
+              Y[i + I * k] = v[q];
+              Yt[i * ldyt + k] = v[q];
+              if (!isfinite(v[q]) && status) atomicOr(status, kDevNonFinite);
+            } else {
+              out[i + I * k] = v[q];
+            }
+          }
         }
       }
   }

@@ -93,7 +93,10 @@ inline int64_t pw_width(int64_t s) { return 16 * cdiv(s, 16); }
 constexpr int kPwMT = 2;
 inline int64_t pw_itiles(int64_t I) { return cdiv(I, 16 * kPwMT); }
 inline int64_t pw_splits(int64_t I, int64_t J) {
-  // about four blocks per compute unit, at least 64 columns per range
+  // about four blocks per compute unit, at least 64 columns per range; one
+  // range up to 128 columns (the product then writes the sketch itself and
+  // the step needs no reduction launch)
+  if (J <= 128) return 1;
   return std::max<int64_t>(1, std::min<int64_t>(cdiv(1024, pw_itiles(I)), cdiv(J, 64)));
 }
 // Number of partial sketches a power step on this source produces (at most).
@@ -729,10 +732,12 @@ int launch_cast(const double* src, int64_t n, bool to_f32, void* dst, hipStream_
 
 // gidx (optional, L == 1): column j of the product is column gidx[j] of X,
 // which then has at least max gidx + 1 columns (the sampled C' read in place).
+// With one column range the product writes Y, Yt (row stride sw; Yt's reads
+// are done by then) and the status itself and *nparts is 0: no reduction.
 template <typename Tin, int NKT>
-int pw_step(const Tin* X, int64_t L, int64_t I, int64_t R, const double* colw, const double* Yt,
+int pw_step(const Tin* X, int64_t L, int64_t I, int64_t R, const double* colw, double* Yt,
             int sw, int s, double* W, double* part, int64_t* nparts, hipStream_t st,
-            const int64_t* gidx) {
+            const int64_t* gidx, double* Y, uint32_t* status) {
   const int64_t J = L * R;
   // W = X^T Y has the shape of the mode-1 shrink with Q^T = Yt: the
   // persistent MFMA kernel (Yt staged in LDS, next tile in flight) when there
@@ -754,29 +759,36 @@ int pw_step(const Tin* X, int64_t L, int64_t I, int64_t R, const double* colw, c
   TR_TRY(check_launch());
   const int64_t jper = cdiv(J, pw_splits(I, J));
   const int64_t ny = cdiv(J, jper);
+  const bool direct = ny == 1;
   hipLaunchKernelGGL((trk::k_pw_y<Tin, NKT, kPwMT>), dim3((unsigned)pw_itiles(I), (unsigned)ny),
                      dim3(trk::kPwWaves * trk::kWave), 0, st, X, L, I, R, W, s, jper, part,
-                     gidx);
-  *nparts = ny;
+                     gidx, direct ? Y : nullptr, direct ? Yt : nullptr, sw,
+                     direct ? status : nullptr);
+  *nparts = direct ? 0 : ny;
   return check_launch();
 }
 
 template <typename Tin>
-int pw_step_t(const Tin* X, int64_t L, int64_t I, int64_t R, const double* colw,
-              const double* Yt, int sw, int64_t s, double* W, double* part, int64_t* nparts,
-              hipStream_t st, const int64_t* gidx = nullptr) {
+int pw_step_t(const Tin* X, int64_t L, int64_t I, int64_t R, const double* colw, double* Yt,
+              int sw, int64_t s, double* W, double* part, int64_t* nparts, hipStream_t st,
+              const int64_t* gidx, double* Y, uint32_t* status) {
   const int si = (int)s;
+#define TR_PW_CASE(n)                                                                    \
+  case n:                                                                                \
+    return pw_step<Tin, n>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st, gidx, Y, \
+                           status);
   switch (pw_nkt(s)) {
-    case 1: return pw_step<Tin, 1>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st, gidx);
-    case 2: return pw_step<Tin, 2>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st, gidx);
-    case 3: return pw_step<Tin, 3>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st, gidx);
-    case 4: return pw_step<Tin, 4>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st, gidx);
-    case 5: return pw_step<Tin, 5>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st, gidx);
-    case 6: return pw_step<Tin, 6>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st, gidx);
-    case 7: return pw_step<Tin, 7>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st, gidx);
-    case 8: return pw_step<Tin, 8>(X, L, I, R, colw, Yt, sw, si, W, part, nparts, st, gidx);
+    TR_PW_CASE(1)
+    TR_PW_CASE(2)
+    TR_PW_CASE(3)
+    TR_PW_CASE(4)
+    TR_PW_CASE(5)
+    TR_PW_CASE(6)
+    TR_PW_CASE(7)
+    TR_PW_CASE(8)
     default: return TR_ENOTSUP;
   }
+#undef TR_PW_CASE
 }
 
 size_t power_ws_bytes(int64_t L, int64_t I, int64_t R, int64_t s, bool f64) {
@@ -804,9 +816,12 @@ int run_power(bool f64, const void* X, int64_t L, int64_t I, int64_t R, const do
     if (rc != TR_OK && rc != TR_ENOTSUP) return rc;
     if (rc == TR_ENOTSUP) {
       if (f64)
-        TR_TRY(pw_step_t((const double*)X, L, I, R, colw, Yt, sw, s, Z, part, &nused, st, gidx));
+        TR_TRY(pw_step_t((const double*)X, L, I, R, colw, Yt, sw, s, Z, part, &nused, st, gidx,
+                         Y, status));
       else
-        TR_TRY(pw_step_t((const float*)X, L, I, R, colw, Yt, sw, s, Z, part, &nused, st, gidx));
+        TR_TRY(pw_step_t((const float*)X, L, I, R, colw, Yt, sw, s, Z, part, &nused, st, gidx,
+                         Y, status));
+      if (nused == 0) continue;  // the product wrote Y and Yt
     }
     hipLaunchKernelGGL(trk::k_reduce_parts, dim3((unsigned)cdiv(I * s, kNT)), dim3(kNT), 0, st,
                        part, nused, I, (int)s, sw, Y, Yt, status);
