@@ -11,6 +11,10 @@
   same sums in another order, 1e-12 relative.
 * A NaN planted in the input reaches the status word (TR_DEV_NONFINITE) for
   exact and nearly-optimal sampled products; the call still completes.
+* A mode with more than 128 rows and at most 128 columns takes the two-product
+  power step with a single column range, whose product kernel writes the
+  sketch (and the status) itself: parity with the oracle at 1e-10 for q = 1,
+  2 in both power-scheme forms, and a NaN still reaches the status word.
 """
 import numpy as np
 import pytest
@@ -128,3 +132,32 @@ def test_finite_input_leaves_status_clear():
     for prob, samples in (("none", None), ("nearly_optimal", (200, 150, 100))):
         _, _, info = _gpu(A, "sthosvd", (3, 3, 3), 3, 1, prob, samples, 1)
         assert int(_np(info["status"])[0]) == 0
+
+
+# mode 1 has I = 300 > 128 rows (no one-sweep kernel) and J = 10 * 12 = 120
+# columns (one column range): the step's product writes the sketch itself
+SINGLE_RANGE_SHAPE = (300, 10, 12)
+
+
+@pytest.mark.parametrize("flags", [0, ["stabilized_power"]])
+@pytest.mark.parametrize("q", [1, 2])
+@pytest.mark.parametrize("algo", ["thosvd", "sthosvd"])
+def test_single_range_power_step_matches_oracle(algo, q, flags):
+    A = synth.low_rank_plus_noise(SINGLE_RANGE_SHAPE, (5, 4, 4), 1e-2, 21)
+    ranks, K = (4, 3, 3), 4
+    Qg, cg, info = _gpu(A, algo, ranks, K, q, seed=6, flags=flags)
+    assert int(_np(info["status"])[0]) == 0
+    fo = oracle.rand_thosvd if algo == "thosvd" else oracle.rand_sthosvd
+    Qo, co, infos = fo(A, ranks, K, q, "none", None, 6)
+    for n in range(A.ndim):
+        assert _rel(Qg[n], Qo[n]) <= 1e-10, (n, _rel(Qg[n], Qo[n]))
+        assert _rel(_np(info["sketch"][n]), infos[n]["C"]) <= 1e-9, n
+    assert _rel(cg, co) <= 1e-10
+
+
+@pytest.mark.parametrize("algo", ["thosvd", "sthosvd"])
+def test_single_range_power_step_nan_sets_status(algo):
+    A = synth.low_rank_plus_noise(SINGLE_RANGE_SHAPE, (5, 4, 4), 1e-2, 21)
+    A[200, 3, 5] = np.nan
+    _, _, info = _gpu(A, algo, (4, 3, 3), 4, 1, seed=6)
+    assert int(_np(info["status"])[0]) & _abi.TR_DEV_NONFINITE
