@@ -914,10 +914,10 @@ int launch_factor_jobs(const trk::FactorJob* job, int n, int cast_f32, uint32_t*
                        hipStream_t st);
 
 // Orthonormalisation steps of the R-accumulated power scheme for k modes at
-// once: Z_n = the orthonormal factor of C_n (its s left singular vectors; one
-// factor launch for all), Zt_n its zero-padded row-major copy (row stride
-// ldzt; skipped when null), then Rbar_n <- (Z_n^T C_n) Rbar_n (first: the
-// product alone).  C_n is left intact (the factor's scratch is its own).
+// once: Z_n = an orthonormal basis of C_n's range (one factor launch for
+// all), Zt_n its zero-padded row-major copy (row stride ldzt; skipped when
+// null), then Rbar_n <- (Z_n^T C_n) Rbar_n (first: the product alone).  C_n is
+// left intact (the factor's scratch is its own).
 int stab_orth(const Plan& P, const int* modes, int k, double* const* C, double* const* Zt,
               bool first, void* ws, uint32_t* status, hipStream_t st) {
   trk::FactorJob jobs[TR_MAX_ORDER];
