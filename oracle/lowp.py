@@ -34,12 +34,14 @@ sample matrix C' with D = diag(scale_t^2)):
   bfloat16 matrices (about 16 significant bits), and Mhat in bfloat16, which
   holds every bfloat16 and every e4m3 value exactly.
 
-For q > 1 the power scheme runs in its R-accumulated form: Z_0 R_0 = G and
-Z_i R_i = M D M^T Z_{i-1} (i = 1..q), where Z_i is the orthonormal QR factor
-of the iterate with the canonical signs and R_i = Z_i^T (M D M^T Z_{i-1}),
-and C_n = Z_q Rbar with Rbar = R_q ... R_0, equal to (M D M^T)^q G in exact
-arithmetic.  Only orthonormal iterates are rounded to the operand format, so
-directions far below the leading one survive the rounding.
+For q > 1 the power scheme runs in its R-accumulated form: Z_0 R_0 = G (with
+Z_0 = G and R_0 = I when s <= I / 2, where the Gaussian G is well
+conditioned) and Z_i R_i = M D M^T Z_{i-1} (i = 1..q), where Z_i is the
+orthonormal QR factor of the iterate with the canonical signs and
+R_i = Z_i^T (M D M^T Z_{i-1}), and C_n = Z_q Rbar with Rbar = R_q ... R_0, equal to (M D M^T)^q G in exact
+arithmetic.  Only orthonormal iterates (or that well-conditioned G) are
+rounded to the operand format, so directions far below the leading one
+survive the rounding.
 
 Scale arithmetic follows the device in float32: tau and sigma are
 max / 448 and the rounded value is x / scale; the tensor is multiplied by
@@ -169,7 +171,11 @@ def power_sketch_lp(X: np.ndarray, n: int, s: int, q: int, prec: str, seed: int,
     G = gaussian_matrix(I, s, n, seed)
     if q == 1:
         return power_step(Mhat, d, G, prec)
-    Z, Rbar = _orth(G)
+    if 2 * s <= I:
+        # a well-conditioned Gaussian start is rounded as it is: Z_0 = G, R_0 = I
+        Z, Rbar = G, np.eye(s)
+    else:
+        Z, Rbar = _orth(G)
     for _ in range(q):
         Z, R = _orth(power_step(Mhat, d, Z, prec))
         Rbar = R @ Rbar

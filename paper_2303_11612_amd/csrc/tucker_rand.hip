@@ -946,11 +946,19 @@ int stab_orth(const Plan& P, const int* modes, int k, double* const* C, double* 
   return TR_OK;
 }
 
+// Whether the R-accumulated low-precision scheme starts from G itself
+// (Z_0 = G, R_0 = I) rather than from an orthonormal basis of it: with
+// s <= I / 2 the Gaussian G is well conditioned (kappa about
+// (1 + sqrt(s/I)) / (1 - sqrt(s/I)) <= 6), so rounding it to the operand
+// format keeps every direction, and the first orthonormalisation is skipped.
+inline bool lp_raw_start(int64_t I, int64_t s) { return 2 * s <= I; }
+
 // Low-precision power products of mode n from G (float64 I x s): without
-// R-accumulation (q = 1) C = M D M^T G; with it, Z_0 Rbar = G, then per step
-// C = M D M^T Z_{i-1} in the operand format and Z_i, Rbar updated (the
-// iterate that is rounded is always orthonormal, which keeps directions far
-// below the leading one; C_n = Z_q Rbar is left to the final factor).
+// R-accumulation (q = 1) C = M D M^T G; with it, Z_0 Rbar = G (Z_0 = G and
+// Rbar = I when lp_raw_start), then per step C = M D M^T Z_{i-1} in the
+// operand format and Z_i, Rbar updated (the iterate that is rounded is
+// orthonormal or a well-conditioned G, which keeps directions far below the
+// leading one; C_n = Z_q Rbar is left to the final factor).
 int run_power_lp(const Plan& P, int n, int kind, const void* M, int64_t L, int64_t I, int64_t R,
                  int64_t ldi, const float* omega, const unsigned* xmax, int64_t s,
                  double* G, double* C, void* ws, uint32_t* status, hipStream_t st) {
@@ -958,12 +966,14 @@ int run_power_lp(const Plan& P, int n, int kind, const void* M, int64_t L, int64
     return power_lp_step(P, kind, M, L, I, R, ldi, omega, xmax, s, G, C, ws, status, st);
   double* const none[1] = {nullptr};
   double* Zn = at<double>(ws, P.oZn[n]);
+  const bool raw = lp_raw_start(I, s);
   double* cs[1] = {G};
-  TR_TRY(stab_orth(P, &n, 1, cs, none, true, ws, status, st));
+  if (!raw) TR_TRY(stab_orth(P, &n, 1, cs, none, true, ws, status, st));
   cs[0] = C;
   for (int step = 0; step < P.q; ++step) {
-    TR_TRY(power_lp_step(P, kind, M, L, I, R, ldi, omega, xmax, s, Zn, C, ws, status, st));
-    TR_TRY(stab_orth(P, &n, 1, cs, none, false, ws, status, st));
+    double* Z = raw && step == 0 ? G : Zn;
+    TR_TRY(power_lp_step(P, kind, M, L, I, R, ldi, omega, xmax, s, Z, C, ws, status, st));
+    TR_TRY(stab_orth(P, &n, 1, cs, none, raw && step == 0, ws, status, st));
   }
   return TR_OK;
 }
@@ -1548,26 +1558,57 @@ int run_thosvd(const tr_params* p, int dtype, const void* A, void* const* Q, voi
     double* Cs[TR_MAX_ORDER];
     double* const nozt[TR_MAX_ORDER] = {};
     int k = 0;
+    // modes whose G is first orthonormalised (the rest start from G itself,
+    // as run_power_lp does) and their first R-accumulation step
+    int k0 = 0;
+    int modes0[TR_MAX_ORDER];
+    double* Cs0[TR_MAX_ORDER];
+    bool raw[TR_MAX_ORDER] = {};
     for (int n = 0; n < P.N; ++n)
       if (together[n]) {
         modes[k] = n;
-        Cs[k++] = at<double>(ws, P.oGs[n]);
+        Cs[k++] = at<double>(ws, P.oYn[n]);
+        raw[n] = lp_raw_start(P.m[n].I, P.m[n].s);
+        if (!raw[n]) {
+          modes0[k0] = n;
+          Cs0[k0++] = at<double>(ws, P.oGs[n]);
+        }
       }
-    {
+    if (k0 > 0) {
       TimeScope ts(tm0, TR_KC_POWER, 0, st);
-      TR_TRY(stab_orth(P, modes, k, Cs, nozt, true, ws, status, st));
+      TR_TRY(stab_orth(P, modes0, k0, Cs0, nozt, true, ws, status, st));
     }
-    for (int b = 0; b < k; ++b) Cs[b] = at<double>(ws, P.oYn[modes[b]]);
     for (int step = 0; step < P.q; ++step) {
       for (int b = 0; b < k; ++b) {
         const int n = modes[b];
         const ModePlan& M = P.m[n];
         TimeScope ts(tm0, TR_KC_POWER, n, st);
+        double* Z = raw[n] && step == 0 ? at<double>(ws, P.oGs[n]) : at<double>(ws, P.oZn[n]);
         TR_TRY(power_lp_step(P, M.src_f64 ? kLpF64 : kLpF32, A, M.L, M.I, M.R, M.I, nullptr,
-                             xmax, M.s, at<double>(ws, P.oZn[n]), Cs[b], ws, status, st));
+                             xmax, M.s, Z, Cs[b], ws, status, st));
       }
       TimeScope ts(tm0, TR_KC_POWER, 0, st);
-      TR_TRY(stab_orth(P, modes, k, Cs, nozt, false, ws, status, st));
+      if (step > 0 || k0 == k) {
+        TR_TRY(stab_orth(P, modes, k, Cs, nozt, false, ws, status, st));
+      } else {
+        // the first step: the raw-start modes begin their Rbar here, the
+        // others extend theirs (two groups, one factor launch each)
+        int m1[TR_MAX_ORDER], m2[TR_MAX_ORDER];
+        double* c1[TR_MAX_ORDER];
+        double* c2[TR_MAX_ORDER];
+        int n1 = 0, n2 = 0;
+        for (int b = 0; b < k; ++b) {
+          if (raw[modes[b]]) {
+            m1[n1] = modes[b];
+            c1[n1++] = Cs[b];
+          } else {
+            m2[n2] = modes[b];
+            c2[n2++] = Cs[b];
+          }
+        }
+        TR_TRY(stab_orth(P, m1, n1, c1, nozt, true, ws, status, st));
+        if (n2 > 0) TR_TRY(stab_orth(P, m2, n2, c2, nozt, false, ws, status, st));
+      }
     }
   }
   if (P.related) {

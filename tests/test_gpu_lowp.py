@@ -81,6 +81,9 @@ CASES = [
     ((130, 40, 37), (6, 6, 6), 10, 1, "nearly_optimal", (300, 200, 200)),
     ((300, 70, 20), (12, 8, 5), 10, 1, "uniform", (500, 400, 400)),
     ((300, 70, 20), (12, 8, 5), 10, 2, "nearly_optimal", (500, 400, 400)),
+    # q = 2 exact, modes 1-2 starting from G itself (s <= I / 2) beside mode 3
+    # starting from an orthonormal basis of G (s = 16 > 10)
+    ((61, 45, 20), (5, 4, 6), 10, 2, "none", None),
 ]
 
 

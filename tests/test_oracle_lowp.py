@@ -86,12 +86,15 @@ def test_power_step_exact_on_representable_data(prec):
 
 @pytest.mark.parametrize("prec,tol", [("bf16", 8e-3), ("fp8e4m3", 0.1)])
 @pytest.mark.parametrize("q", [1, 2])
-def test_sketch_error_is_format_sized(prec, tol, q):
+@pytest.mark.parametrize("K", [6, 10])
+def test_sketch_error_is_format_sized(prec, tol, q, K):
+    # K = 10 gives mode 3 (I = 20) s = 14 > I / 2: its q = 2 scheme starts from
+    # an orthonormal basis of G; every other mode starts from G itself
     A = synth.low_rank_plus_noise((40, 30, 20), (4, 4, 4), 1e-3, 5, np.float32)
     A64 = A.astype(np.float64)
     for n in range(3):
         I = A.shape[n]
-        s = min(4 + 6, I)
+        s = min(4 + K, I)
         C = lowp.power_sketch_lp(A, n, s, q, prec, 7)
         Q, _ = oracle.leading_left_singular_vectors(C, 4)
         Ce = oracle.power_sketch(oracle.unfold(A64, n), oracle.gaussian_matrix(I, s, n, 7), q)
