@@ -3,10 +3,12 @@
 // equal to them in exact arithmetic):
 //   Z_0 R_0 = G,  Z_i R_i = M D M^T Z_{i-1}  (i = 1..q),  Rbar = R_q ... R_0,
 // so (M D M^T)^q G = Z_q Rbar and its leading left singular vectors are
-// Z_q U'(:, 1:mu) with Rbar = U' S V'^T.  Each Z_i is the orthonormal factor
-// the factor kernel computes (the left singular vectors of the iterate), and
-// R_i = Z_i^T Y_i.  The kernels here form R_i, accumulate Rbar and apply the
-// small factor U' (with the canonical signs) to produce Q_n.
+// Z_q U'(:, 1:mu) with Rbar = U' S V'^T.  Each Z_i is an orthonormal basis of
+// the iterate's range from the factor kernel, and R_i = Z_i^T Y_i.  The
+// kernels here form R_i, accumulate Rbar and apply the small factor U' (with
+// the canonical signs) to produce Q_n, for several modes per launch: job y of
+// a launch is mode y's (blockIdx.y), and a mode's arithmetic does not depend
+// on the others.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -16,15 +18,36 @@
 namespace trk {
 
 constexpr int kStabNT = 256;
+constexpr int kStabMaxJobs = 8;  // modes per launch
 
-// R(a, b) = sum_i Z(i, a) Y(i, b) for a, b < s; Z, Y column-major I x s, R
-// column-major s x s.  One workgroup per entry; thread t sums rows t, t + 256,
-// ... in order, the partial sums are added by a fixed tree.
+// One mode's step: R = Z^T Y (Z, Y column-major I x s, R column-major s x s),
+// then Rbar <- R Rbar (first: Rbar <- R), s <= 64.
+struct StabStep {
+  const double* Z;
+  const double* Y;
+  double* R;
+  double* Rbar;
+  int64_t I;
+  int s, first;
+};
+struct StabSteps {
+  StabStep j[kStabMaxJobs];
+};
+
+// R(a, b) = sum_i Z(i, a) Y(i, b) for a, b < s.  Grid (smax^2, jobs), smax the
+// largest s: workgroup x of job y takes entry (x % smax, x / smax) if both are
+// below the job's s; thread t sums rows t, t + 256, ... in order, the partial
+// sums are added by a fixed tree.
 static __global__ void __launch_bounds__(kStabNT)
-k_small_tn(const double* __restrict__ Z, const double* __restrict__ Y, int64_t I, int s,
-           double* __restrict__ R) {
+k_small_tn(StabSteps jobs, int smax) {
   __shared__ double red[kStabNT];
-  const int a = (int)(blockIdx.x % s), b = (int)(blockIdx.x / s);
+  const StabStep& jb = jobs.j[blockIdx.y];
+  const int s = jb.s;
+  const int64_t I = jb.I;
+  const int a = (int)(blockIdx.x % smax), b = (int)(blockIdx.x / smax);
+  if (a >= s || b >= s) return;  // the whole workgroup
+  const double* __restrict__ Z = jb.Z;
+  const double* __restrict__ Y = jb.Y;
   const double* za = Z + (int64_t)a * I;
   const double* yb = Y + (int64_t)b * I;
   double acc = 0.0;
@@ -35,14 +58,19 @@ k_small_tn(const double* __restrict__ Z, const double* __restrict__ Y, int64_t I
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) R[a + (int64_t)s * b] = red[0];
+  if (threadIdx.x == 0) jb.R[a + (int64_t)s * b] = red[0];
 }
 
 // Rbar <- R Rbar (first: Rbar <- R); s x s column-major, s <= 64.  One
-// workgroup; the old Rbar is staged in LDS, each entry summed in increasing c.
+// workgroup per job; the old Rbar is staged in LDS, each entry summed in
+// increasing c.
 static __global__ void __launch_bounds__(kStabNT)
-k_rbar_update(const double* __restrict__ R, double* __restrict__ Rbar, int s, int first) {
+k_rbar_update(StabSteps jobs) {
   __shared__ double old[64 * 64];
+  const StabStep& jb = jobs.j[blockIdx.x];
+  const double* __restrict__ R = jb.R;
+  double* __restrict__ Rbar = jb.Rbar;
+  const int s = jb.s, first = jb.first;
   const int n = s * s;
   if (first) {
     for (int e = threadIdx.x; e < n; e += kStabNT) Rbar[e] = R[e];
@@ -58,20 +86,45 @@ k_rbar_update(const double* __restrict__ R, double* __restrict__ Rbar, int s, in
   }
 }
 
-// Q = Z U(:, 1:mu) (Z: I x s, U: s x mu, both column-major, ld I and s) with
-// each column's largest-magnitude entry made positive (lowest row on ties),
-// written as Q64 (I x mu), Qt (row stride ldqt, columns mu..ldqt-1 zero; may
-// be null) and Qcast (caller dtype; may be null).  Blocks k < mu produce
-// column k, blocks mu <= k < ldqt clear Qt's padding column k, and with Cd
-// (may be null) blocks ldqt + c write column c of the sketch Z Rbar (I x s).
+// One mode's Q = Z U(:, 1:mu) (Z: I x s, U: s x mu, both column-major, ld I
+// and s) with each column's largest-magnitude entry made positive (lowest row
+// on ties), written as Q64 (I x mu), Qt (row stride ldqt, columns mu..ldqt-1
+// zero; may be null) and Qcast (caller dtype; may be null); with Cd (may be
+// null) also the sketch Z Rbar (I x s).  nb = (Qt ? ldqt : mu) + (Cd ? s : 0).
+struct StabFinal {
+  const double* Z;
+  const double* U;
+  const double* Rbar;
+  double* Q64;
+  double* Qt;
+  void* Qcast;
+  double* Cd;
+  int64_t I;
+  int s, mu, ldqt, nb;
+};
+struct StabFinals {
+  StabFinal j[kStabMaxJobs];
+};
+
+// Grid (max nb, jobs).  Workgroups k < mu of job y produce its column k,
+// mu <= k < ldqt clear Qt's padding column k, and (with Cd) ldqt + c write
+// column c of the sketch; k >= nb have nothing to do.
 static __global__ void __launch_bounds__(kStabNT)
-k_stab_final(const double* __restrict__ Z, int64_t I, int s, const double* __restrict__ U,
-             int mu, const double* __restrict__ Rbar, double* __restrict__ Q64,
-             double* __restrict__ Qt, int ldqt, void* __restrict__ Qcast, int cast_f32,
-             double* __restrict__ Cd) {
+k_stab_final(StabFinals jobs, int cast_f32) {
   __shared__ double babs[kStabNT], bval[kStabNT];
   __shared__ int64_t bidx[kStabNT];
+  const StabFinal& jb = jobs.j[blockIdx.y];
   const int k = blockIdx.x;
+  if (k >= jb.nb) return;  // the whole workgroup
+  const double* __restrict__ Z = jb.Z;
+  const double* __restrict__ U = jb.U;
+  const double* __restrict__ Rbar = jb.Rbar;
+  double* __restrict__ Q64 = jb.Q64;
+  double* __restrict__ Qt = jb.Qt;
+  void* __restrict__ Qcast = jb.Qcast;
+  double* __restrict__ Cd = jb.Cd;
+  const int64_t I = jb.I;
+  const int s = jb.s, mu = jb.mu, ldqt = jb.ldqt;
   const int t = threadIdx.x;
   const int lq = Qt ? ldqt : mu;
   if (k >= lq) {  // a column of the sketch Z Rbar

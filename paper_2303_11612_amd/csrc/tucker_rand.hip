@@ -932,18 +932,22 @@ int stab_orth(const Plan& P, const int* modes, int k, double* const* C, double* 
                              Zt[b] ? M.sw : 0, nullptr, 1};
   }
   TR_TRY(launch_factor_jobs(jobs, k, 0, status, st));
+  // R_n = Z_n^T C_n and the Rbar_n update: one launch each for all k modes
+  static_assert(trk::kStabMaxJobs >= TR_MAX_ORDER, "one stabilised job per mode");
+  trk::StabSteps steps{};
+  int64_t smax = 1;
   for (int b = 0; b < k; ++b) {
     const int n = modes[b];
     const ModePlan& M = P.m[n];
-    double* Rs = at<double>(ws, P.oRst[n]);
-    hipLaunchKernelGGL(trk::k_small_tn, dim3((unsigned)(M.s * M.s)), dim3(trk::kStabNT), 0, st,
-                       at<double>(ws, P.oZn[n]), C[b], M.I, (int)M.s, Rs);
-    TR_TRY(check_launch());
-    hipLaunchKernelGGL(trk::k_rbar_update, dim3(1), dim3(trk::kStabNT), 0, st, Rs,
-                       at<double>(ws, P.oRbar[n]), (int)M.s, first ? 1 : 0);
-    TR_TRY(check_launch());
+    steps.j[b] = trk::StabStep{at<double>(ws, P.oZn[n]), C[b], at<double>(ws, P.oRst[n]),
+                               at<double>(ws, P.oRbar[n]), M.I, (int)M.s, first ? 1 : 0};
+    smax = std::max<int64_t>(smax, M.s);
   }
-  return TR_OK;
+  hipLaunchKernelGGL(trk::k_small_tn, dim3((unsigned)(smax * smax), (unsigned)k),
+                     dim3(trk::kStabNT), 0, st, steps, (int)smax);
+  TR_TRY(check_launch());
+  hipLaunchKernelGGL(trk::k_rbar_update, dim3((unsigned)k), dim3(trk::kStabNT), 0, st, steps);
+  return check_launch();
 }
 
 // Whether the R-accumulated low-precision scheme starts from G itself
@@ -1358,21 +1362,36 @@ trk::FactorJob rbar_job(const Plan& P, int n, double* sig, void* ws) {
                         nullptr, at<double>(ws, P.oGA[n]), (int)M.s, (int)M.s, (int)M.mu, 0};
 }
 
-// R-accumulated form, after rbar_job: Q_n = Z_n U'_n(:, 1:mu) with canonical
-// signs into the mode's Q64 / Qt and the caller's Q; the sketch Z_n Rbar_n
-// into the diagnostics when asked for.
+// R-accumulated form, after rbar_job, for k modes in one launch: Q_n = Z_n
+// U'_n(:, 1:mu) with canonical signs into the mode's Q64 / Qt and the caller's
+// Q (Qout[b] for modes[b]); the sketch Z_n Rbar_n into the diagnostics when
+// asked for.
+int stab_final(const Plan& P, const int* modes, int k, void* ws, void* const* Qout,
+               const tr_diag* diag, hipStream_t st) {
+  trk::StabFinals fin{};
+  int nbmax = 1;
+  for (int b = 0; b < k; ++b) {
+    const int n = modes[b];
+    const ModePlan& M = P.m[n];
+    // (without R-accumulation the sketch was copied out when it was formed)
+    double* Cd =
+        (P.racc && diag && diag->sketch && diag->sketch[n]) ? diag->sketch[n] : nullptr;
+    const int nb = (int)(M.muw + (Cd ? M.s : 0));
+    fin.j[b] = trk::StabFinal{at<double>(ws, P.oZn[n]), at<double>(ws, P.oUp[n]),
+                              at<double>(ws, P.oRbar[n]), at<double>(ws, P.oQ[n]),
+                              at<double>(ws, P.oQt[n]), Qout[b], Cd, M.I, (int)M.s,
+                              (int)M.mu, M.muw, nb};
+    nbmax = std::max(nbmax, nb);
+  }
+  hipLaunchKernelGGL(trk::k_stab_final, dim3((unsigned)nbmax, (unsigned)k), dim3(trk::kStabNT),
+                     0, st, fin, P.dtype == TR_F32 ? 1 : 0);
+  return check_launch();
+}
+
 int stab_final(const Plan& P, int n, void* ws, void* Qout, const tr_diag* diag,
                hipStream_t st) {
-  const ModePlan& M = P.m[n];
-  // (without R-accumulation the sketch was copied out when it was formed)
-  double* Cd =
-      (P.racc && diag && diag->sketch && diag->sketch[n]) ? diag->sketch[n] : nullptr;
-  const unsigned nb = (unsigned)(M.muw + (Cd ? M.s : 0));
-  hipLaunchKernelGGL(trk::k_stab_final, dim3(nb), dim3(trk::kStabNT), 0, st,
-                     at<double>(ws, P.oZn[n]), M.I, (int)M.s, at<double>(ws, P.oUp[n]),
-                     (int)M.mu, at<double>(ws, P.oRbar[n]), at<double>(ws, P.oQ[n]),
-                     at<double>(ws, P.oQt[n]), M.muw, Qout, P.dtype == TR_F32 ? 1 : 0, Cd);
-  return check_launch();
+  void* const qo[1] = {Qout};
+  return stab_final(P, &n, 1, ws, qo, diag, st);
 }
 
 // Related forms (Alg. 6 / Alg. 7), for k modes at once.  Step 1: P_n, an
@@ -1414,8 +1433,11 @@ int related_gram(const Plan& P, int n, const void* X, double* Y, void* ws, uint3
   TR_TRY(run_power(M.src_f64, X, M.L, M.I, M.R, nullptr, 1, M.s, M.sw, Y,
                    at<double>(ws, P.oYts[n]), at<double>(ws, P.oZ), at<double>(ws, P.oPart),
                    status, st, P.fused));
-  hipLaunchKernelGGL(trk::k_small_tn, dim3((unsigned)(M.s * M.s)), dim3(trk::kStabNT), 0, st,
-                     at<double>(ws, P.oZn[n]), Y, M.I, (int)M.s, at<double>(ws, P.oRst[n]));
+  trk::StabSteps one{};
+  one.j[0] = trk::StabStep{at<double>(ws, P.oZn[n]), Y, at<double>(ws, P.oRst[n]), nullptr, M.I,
+                           (int)M.s, 0};
+  hipLaunchKernelGGL(trk::k_small_tn, dim3((unsigned)(M.s * M.s), 1u), dim3(trk::kStabNT), 0, st,
+                     one, (int)M.s);
   return check_launch();
 }
 
@@ -1440,8 +1462,7 @@ int related_eig(const Plan& P, const int* modes, int k, void* ws, uint32_t* stat
 int related_finish(const Plan& P, const int* modes, int k, void* ws, void* const* Qout,
                    const tr_diag* diag, uint32_t* status, hipStream_t st) {
   TR_TRY(related_eig(P, modes, k, ws, status, st));
-  for (int b = 0; b < k; ++b) TR_TRY(stab_final(P, modes[b], ws, Qout[b], diag, st));
-  return TR_OK;
+  return stab_final(P, modes, k, ws, Qout, diag, st);
 }
 
 // Range finder of mode n (ST-HOSVD: sketch, then factor).
@@ -1635,8 +1656,11 @@ int run_thosvd(const tr_params* p, int dtype, const void* A, void* const* Q, voi
   if (!P.related) {
     TimeScope ts(diag ? diag->timer : nullptr, TR_KC_FACTOR, 0, st);
     TR_TRY(launch_factor_jobs(jobs, P.N, P.dtype == TR_F32, diag ? diag->status : nullptr, st));
-    if (P.racc)
-      for (int n = 0; n < P.N; ++n) TR_TRY(stab_final(P, n, ws, Q[n], diag, st));
+    if (P.racc) {
+      int all[TR_MAX_ORDER];
+      for (int n = 0; n < P.N; ++n) all[n] = n;
+      TR_TRY(stab_final(P, all, P.N, ws, Q, diag, st));
+    }
   }
   int64_t shp[TR_MAX_ORDER];
   for (int k = 0; k < P.N; ++k) shp[k] = P.dims[k];
