@@ -124,12 +124,11 @@ __device__ __forceinline__ float block_max_f32(float v, float* red) {
 // Operand form of the sketch C (I x s, float64, column-major): Cq[k][i]
 // (k < SP, i < Ip, zero outside I x s) in the operand type, and tau[k], the
 // scale of column k (1 for BF16).  One block of 256 threads per k < SP; Ip <= 512.
+// (Column k's workgroup; the whole workgroup calls it.)
 template <typename OP>
-__global__ void __launch_bounds__(kNT)
-k_quant_y(const double* __restrict__ C, int64_t I, int s, int Ip,
-          typename OP::stor* __restrict__ Cq, float* __restrict__ tau) {
-  __shared__ float red[kNT / kWave];
-  const int k = blockIdx.x;
+__device__ __forceinline__ void quant_y_col(const double* __restrict__ C, int64_t I, int s,
+                                            int Ip, typename OP::stor* __restrict__ Cq,
+                                            float* __restrict__ tau, int k, float* red) {
   float v[2];
   float mx = 0.0f;
 #pragma unroll
@@ -149,6 +148,14 @@ k_quant_y(const double* __restrict__ C, int64_t I, int s, int Ip,
     if (i < Ip) Cq[(int64_t)k * Ip + i] = OP::cvt1(v[u] / sc);
   }
   if (threadIdx.x == 0) tau[k] = sc;
+}
+
+template <typename OP>
+__global__ void __launch_bounds__(kNT)
+k_quant_y(const double* __restrict__ C, int64_t I, int s, int Ip,
+          typename OP::stor* __restrict__ Cq, float* __restrict__ tau) {
+  __shared__ float red[kNT / kWave];
+  quant_y_col<OP>(C, I, s, Ip, Cq, tau, blockIdx.x, red);
 }
 
 // Gathered sample matrix in operand form: column t of Cq (rows 0 .. Ip - 1,
@@ -485,13 +492,15 @@ k_pw_lp(const Tin* __restrict__ X, int64_t L, int64_t I, int64_t R, int64_t ldi,
 // i < I, k < s; C column-major I x s.  Block: 32 entries x 8 groups of
 // blocks b (group q takes b = q, q + 8, ...); the 8 group sums are added in
 // order.
-static __global__ void __launch_bounds__(kNT)
-k_reduce_parts_lp(const float* __restrict__ part, int64_t nparts, int64_t I, int s, int SP,
-                  int Ip, double* __restrict__ C, uint32_t* __restrict__ status) {
-  __shared__ double red[8][33];
+// (Workgroup blk of cdiv(I s, 32); the whole workgroup calls it.)
+__device__ __forceinline__ void reduce_parts_lp_blk(const float* __restrict__ part,
+                                                    int64_t nparts, int64_t I, int s, int SP,
+                                                    int Ip, double* __restrict__ C,
+                                                    uint32_t* __restrict__ status, int64_t blk,
+                                                    double (*red)[33]) {
   const int el = threadIdx.x & 31, q = threadIdx.x >> 5;
   const int64_t n = I * s;
-  const int64_t e = (int64_t)blockIdx.x * 32 + el;
+  const int64_t e = blk * 32 + el;
   const int64_t ec = e < n ? e : n - 1;
   const int64_t i = ec % I, k = ec / I;
   const float* src = part + k * Ip + i;
@@ -518,6 +527,31 @@ k_reduce_parts_lp(const float* __restrict__ part, int64_t nparts, int64_t I, int
     C[e] = s8;
     if (!isfinite(s8) && status) atomicOr(status, kDevNonFinite);
   }
+}
+
+static __global__ void __launch_bounds__(kNT)
+k_reduce_parts_lp(const float* __restrict__ part, int64_t nparts, int64_t I, int s, int SP,
+                  int Ip, double* __restrict__ C, uint32_t* __restrict__ status) {
+  __shared__ double red[8][33];
+  reduce_parts_lp_blk(part, nparts, I, s, SP, Ip, C, status, blockIdx.x, red);
+}
+
+// One mode's k_reduce_parts_lp (workgroups 0 .. nred - 1) and the next mode's
+// k_quant_y (workgroups nred .., one per operand column) in one launch: the
+// two share no buffer (the product that read the operand buffers and wrote
+// the partial sums has finished).
+template <typename OP>
+__global__ void __launch_bounds__(kNT)
+k_reduce_quant(const float* __restrict__ part, int64_t nparts, int64_t I, int s, int SP, int Ip,
+               double* __restrict__ C, uint32_t* __restrict__ status, int64_t nred,
+               const double* __restrict__ Y2, int64_t I2, int s2, int Ip2,
+               typename OP::stor* __restrict__ Cq, float* __restrict__ tau) {
+  __shared__ double rred[8][33];
+  __shared__ float qred[kNT / kWave];
+  if ((int64_t)blockIdx.x < nred)
+    reduce_parts_lp_blk(part, nparts, I, s, SP, Ip, C, status, blockIdx.x, rred);
+  else
+    quant_y_col<OP>(Y2, I2, s2, Ip2, Cq, tau, (int)(blockIdx.x - nred), qred);
 }
 
 }  // namespace trk

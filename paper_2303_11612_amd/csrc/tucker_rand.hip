@@ -910,6 +910,51 @@ int power_lp_step(const Plan& P, int kind, const void* M, int64_t L, int64_t I, 
   return check_launch();
 }
 
+// One low-precision power step for k modes of the same tensor M (tensor
+// form, ldi = I_n): C_b = M D M^T Y_b for mode modes[b], as power_lp_step for
+// each in turn, with each mode's reduction and the next mode's operand
+// quantisation in one launch (they share no buffer), 2k launches in all.
+int power_lp_step_modes(const Plan& P, const int* modes, int k, const void* M,
+                        const unsigned* xmax, const double* const* Y, double* const* C,
+                        void* ws, uint32_t* status, hipStream_t st) {
+  void* Cq = static_cast<char*>(ws) + P.oYq;
+  float* tau = reinterpret_cast<float*>(static_cast<char*>(ws) + P.oTau);
+  float* part = reinterpret_cast<float*>(static_cast<char*>(ws) + P.oPartLp);
+  {
+    const ModePlan& M0 = P.m[modes[0]];
+    TR_TRY(launch_quant_y(P.prec, Y[0], M0.I, M0.s, Cq, tau, st));
+  }
+  for (int b = 0; b < k; ++b) {
+    const ModePlan& Mb = P.m[modes[b]];
+    const int kind = Mb.src_f64 ? kLpF64 : kLpF32;
+    const int64_t I = Mb.I, s = Mb.s;
+    const int64_t nblk = lp_blocks(I, s, Mb.L * Mb.R);
+    const int Ip = (int)lp_ip(I), SP = (int)(16 * lp_nkt(s));
+    TR_TRY(launch_pw_lp(P.prec, kind, s, M, Mb.L, I, Mb.R, I, Cq, tau, nullptr, xmax, part,
+                        nblk, st));
+    const int64_t nred = cdiv(I * s, 32);
+    if (b + 1 == k) {
+      hipLaunchKernelGGL(trk::k_reduce_parts_lp, dim3((unsigned)nred), dim3(kNT), 0, st, part,
+                         nblk, I, (int)s, SP, Ip, C[b], status);
+      TR_TRY(check_launch());
+      break;
+    }
+    const ModePlan& Mn = P.m[modes[b + 1]];
+    const int Ip2 = (int)lp_ip(Mn.I), SP2 = (int)(16 * lp_nkt(Mn.s));
+    const dim3 grid((unsigned)(nred + SP2));
+    if (P.prec == TR_PREC_FP8E4M3)
+      hipLaunchKernelGGL(trk::k_reduce_quant<trk::OpFp8>, grid, dim3(kNT), 0, st, part, nblk, I,
+                         (int)s, SP, Ip, C[b], status, nred, Y[b + 1], Mn.I, (int)Mn.s, Ip2,
+                         (uint8_t*)Cq, tau);
+    else
+      hipLaunchKernelGGL(trk::k_reduce_quant<trk::OpBf16>, grid, dim3(kNT), 0, st, part, nblk,
+                         I, (int)s, SP, Ip, C[b], status, nred, Y[b + 1], Mn.I, (int)Mn.s, Ip2,
+                         (uint16_t*)Cq, tau);
+    TR_TRY(check_launch());
+  }
+  return TR_OK;
+}
+
 int launch_factor_jobs(const trk::FactorJob* job, int n, int cast_f32, uint32_t* status,
                        hipStream_t st);
 
@@ -1600,13 +1645,14 @@ int run_thosvd(const tr_params* p, int dtype, const void* A, void* const* Q, voi
       TR_TRY(stab_orth(P, modes0, k0, Cs0, nozt, true, ws, status, st));
     }
     for (int step = 0; step < P.q; ++step) {
-      for (int b = 0; b < k; ++b) {
-        const int n = modes[b];
-        const ModePlan& M = P.m[n];
-        TimeScope ts(tm0, TR_KC_POWER, n, st);
-        double* Z = raw[n] && step == 0 ? at<double>(ws, P.oGs[n]) : at<double>(ws, P.oZn[n]);
-        TR_TRY(power_lp_step(P, M.src_f64 ? kLpF64 : kLpF32, A, M.L, M.I, M.R, M.I, nullptr,
-                             xmax, M.s, Z, Cs[b], ws, status, st));
+      {
+        const double* Zs[TR_MAX_ORDER];
+        for (int b = 0; b < k; ++b) {
+          const int n = modes[b];
+          Zs[b] = raw[n] && step == 0 ? at<double>(ws, P.oGs[n]) : at<double>(ws, P.oZn[n]);
+        }
+        TimeScope ts(tm0, TR_KC_POWER, 0, st);
+        TR_TRY(power_lp_step_modes(P, modes, k, A, xmax, Zs, Cs, ws, status, st));
       }
       TimeScope ts(tm0, TR_KC_POWER, 0, st);
       if (step > 0 || k0 == k) {
