@@ -75,6 +75,9 @@ struct FactorJob {
   // columns of the Householder QR's Q1 with canonical signs, no SVD (the
   // power scheme's orthonormalisation between steps); sig is not written
   int qr_only;
+  // (the register-resident kernel) C is s x s (I == s) and upper triangular:
+  // the Householder QR is skipped and entries below the diagonal are ignored
+  int tri_in;
 };
 constexpr int kMaxFactorJobs = 8;
 // Independent factorizations launched together, one workgroup each (by value

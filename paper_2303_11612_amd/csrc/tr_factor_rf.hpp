@@ -186,6 +186,7 @@ __device__ __forceinline__ void factor_rf_body(const FactorJob& jb, int cast_f32
   const double* __restrict__ C = jb.C;
   const int I = jb.I, s = jb.s, mu = jb.mu, ldqt = jb.ldqt;
   const bool qr_only = jb.qr_only != 0;  // Q1's leading columns, no SVD
+  const bool tri_in = jb.tri_in != 0 && I == s;  // R1 = C: no QR
   double* __restrict__ Q = jb.Q;
   double* __restrict__ Qt = jb.Qt;
   double* __restrict__ sig_out = jb.sig;
@@ -223,7 +224,8 @@ __device__ __forceinline__ void factor_rf_body(const FactorJob& jb, int cast_f32
   for (int r = 0; r < R; ++r) {
     const int i = tid + NT * r;
 #pragma unroll
-    for (int j = 0; j < SM; ++j) a[r][j] *= (i < I && j < s) ? 1.0 : 0.0;
+    for (int j = 0; j < SM; ++j)
+      a[r][j] *= (i < I && j < s && (!tri_in || i <= j)) ? 1.0 : 0.0;
   }
   for (int e = tid; e < SM * LDX; e += NT) X[e] = 0.0;
   if (tid < SM) vec[tid] = 0.0;
@@ -279,7 +281,13 @@ __device__ __forceinline__ void factor_rf_body(const FactorJob& jb, int cast_f32
     }
     if (tid == 0) tau[k] = tk;
   };
-  StaticFor<0, SM>::run(qr_step);
+  // an upper-triangular square input is its own R1 (Q1 = I: every tau zero,
+  // so the Q formation below returns U itself)
+  if (tri_in) {
+    if (tid < SM) tau[tid] = 0.0;
+  } else {
+    StaticFor<0, SM>::run(qr_step);
+  }
 
   // ---- 2. QR of M = R1^T by wave 0: lane j holds column j of M (row j of
   //         R1, in thread j's registers); column k is broadcast by readlane ----

@@ -1400,11 +1400,19 @@ double* mode_sigma(const Plan& P, int n, const tr_diag* diag, void* ws, size_t o
 }
 
 // R-accumulated form: the factor of Rbar_n (s x s) into U'_n (s x mu); its
-// singular values are those of C_n = Z_n Rbar_n.
+// singular values are those of C_n = Z_n Rbar_n.  When the mode's
+// orthonormalisations run in the register-resident kernel (Z_i = Q_1 of the
+// Householder QR with canonical signs, so each R_i = Z_i^T C_i and R_0 are
+// upper triangular up to rounding) Rbar_n is upper triangular and its factor
+// skips the QR.
 trk::FactorJob rbar_job(const Plan& P, int n, double* sig, void* ws) {
   const ModePlan& M = P.m[n];
+  int var = -1;
+  const bool tri = factor_variant(M.I, M.s, M.s, true, false, &var) == TR_OK &&
+                   is_rf_variant(var);
   return trk::FactorJob{at<double>(ws, P.oRbar[n]), at<double>(ws, P.oUp[n]), nullptr, sig,
-                        nullptr, at<double>(ws, P.oGA[n]), (int)M.s, (int)M.s, (int)M.mu, 0};
+                        nullptr, at<double>(ws, P.oGA[n]), (int)M.s, (int)M.s, (int)M.mu, 0,
+                        nullptr, 0, tri ? 1 : 0};
 }
 
 // R-accumulated form, after rbar_job, for k modes in one launch: Q_n = Z_n
