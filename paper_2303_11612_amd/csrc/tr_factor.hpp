@@ -509,8 +509,10 @@ k_factor(FactorJobs jobs, int cast_f32, uint32_t* __restrict__ status) {
     if (lane == 0) sgn[c] = bval < 0.0 ? -1.0 : 1.0;
   }
   __syncthreads();
-  for (int e = tid; e < I * ldqt; e += NT) {
-    const int i = e / ldqt, c = e % ldqt;
+  // Q's mu columns, and with Qt its padding columns up to ldqt too
+  const int lq = Qt ? ldqt : mu;
+  for (int e = tid; e < I * lq; e += NT) {
+    const int i = e / lq, c = e % lq;
     const double zz = Z[(size_t)min(c, mu1) * I + i] * sgn[min(c, mu1)];
     const double z = c < mu ? zz : 0.0;
     if (c < mu) {

@@ -51,6 +51,9 @@ STAB_CASES = [
     ((150, 40, 37), (6, 6, 6), (6, 5, 5), 6, 2, "none", None),
     ((60, 50, 40), (6, 6, 6), (5, 5, 5), 5, 2, "nearly_optimal", (900, 500, 300)),
     ((18, 14, 12, 10), (4, 4, 3, 3), (3, 3, 2, 2), 3, 2, "uniform", (60, 50, 40, 30)),
+    # s = 56 > 48: the LDS-resident factor kernel for every orthonormalisation
+    # and for Rbar (no transposed copy asked of it there)
+    ((80, 70, 60), (40, 40, 40), (40, 40, 40), 16, 2, "none", None),
 ]
 
 
@@ -76,6 +79,29 @@ def test_stabilized_power_matches_oracle(algo, case):
         assert _rel(C, infl[n]["C"]) <= 1e-9, (n, _rel(C, infl[n]["C"]))
     assert _rel(cg, cs) <= 1e-10
     assert _rel(cg, cl) <= 1e-10
+
+
+@pytest.mark.parametrize("variant", ["reg", "lds"])
+@pytest.mark.parametrize("algo", ["thosvd", "sthosvd"])
+def test_stabilized_power_both_factor_kernels(algo, variant, monkeypatch):
+    """The register-resident factor kernel orthonormalises each iterate by its
+    Householder QR (and the accumulated triangular factor then skips its own
+    QR); the LDS-resident one, forced here for every shape, returns the SVD
+    basis and factors a full Rbar.  Either way C_n, the factors and the core
+    match the oracle's stabilised form."""
+    monkeypatch.setenv("TUCKER_RAND_FACTOR", variant)
+    shape, true_r, ranks, K, q, prob, samples = STAB_CASES[2]
+    A = synth.low_rank_plus_noise(shape, true_r, 1e-2, 32)
+    Qg, cg, info = _gpu(A, algo, ranks, K, q, prob, samples, 4, flags=["stabilized_power"])
+    assert int(_np(info["status"])[0]) == 0
+    fo = oracle.rand_thosvd if algo == "thosvd" else oracle.rand_sthosvd
+    Qs, cs, infs = fo(A, ranks, K, q, prob, samples, 4, stabilised=True)
+    for n in range(A.ndim):
+        assert _rel(Qg[n], Qs[n]) <= 1e-10, (n, _rel(Qg[n], Qs[n]))
+        sig = infs[n]["sigma"]
+        assert np.allclose(_np(info["sigma"][n]), sig, rtol=1e-9, atol=1e-12 * sig[0]), n
+        assert _rel(_np(info["sketch"][n]), infs[n]["C"]) <= 1e-9, n
+    assert _rel(cg, cs) <= 1e-10
 
 
 def test_stabilized_power_full_size_400cube_q2():

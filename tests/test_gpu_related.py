@@ -104,6 +104,14 @@ def test_related_power_and_stabilized(algo, q):
     _compare_related(A, algo, (6, 5, 5), 6, q, seed=4, flags=("stabilized_power",))
 
 
+@pytest.mark.parametrize("flags", [(), ("stabilized_power",)])
+def test_related_wide_sketch(flags):
+    # s = 56 > 48: the Gram's eigenvectors (and with R-accumulation Rbar's
+    # factor) come from the LDS-resident factor kernel, with no transposed copy
+    A = synth.low_rank_plus_noise((80, 70, 60), (40, 40, 40), 1e-2, 36)
+    _compare_related(A, "thosvd", (40, 40, 40), 16, 2, seed=5, flags=flags)
+
+
 def test_related_fourth_order_and_k_zero():
     A = synth.low_rank_plus_noise((18, 14, 12, 10), (4, 4, 3, 3), 1e-2, 63)
     _compare_related(A, "sthosvd", (3, 3, 2, 2), 3, 2, "nearly_optimal", (60, 50, 40, 9), seed=8)
