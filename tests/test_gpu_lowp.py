@@ -219,6 +219,17 @@ def test_lowp_relative_error_within_rounding_bound(prec, algo, q):
     _against_oracle(A, algo, (8, 8, 8), 10, q, "nearly_optimal", (400, 400, 400), 3, prec)
 
 
+@pytest.mark.parametrize("variant", ["reg", "lds"])
+@pytest.mark.parametrize("algo", ["thosvd", "sthosvd"])
+def test_lowp_power_scheme_both_factor_kernels(algo, variant, monkeypatch):
+    # q = 2 orthonormalises every iterate: Q_1 of the Householder QR in the
+    # register-resident factor kernel, the SVD basis in the LDS-resident one
+    # (forced here); either way the bf16 result meets the FP64 oracle's bars
+    monkeypatch.setenv("TUCKER_RAND_FACTOR", variant)
+    A = synth.low_rank_plus_noise((61, 45, 33), (5, 4, 6), 1e-3, 41, np.float32)
+    _against_oracle(A, algo, (5, 4, 6), 10, 2, "none", None, 12, "bf16", rel5=True)
+
+
 def test_unsupported_shapes_rejected():
     A = tr.to_device(np.zeros((600, 4, 4), np.float32))
     with pytest.raises(RuntimeError, match="not supported"):
